@@ -1,0 +1,188 @@
+/*
+ * sa.h -- C ABI of the MI355X matrix-free global stability library.
+ *
+ * The library applies the linearised compressible Navier-Stokes operator
+ * J(q0) (Section "Matrix free framework", eq. frechet: the operator N_lin
+ * obtained by linearising N(q) about a base state q0) to perturbation
+ * vectors, solves the Cayley systems (J - sigma I) x = b with restarted
+ * GMRES (Section "Iterative solvers"), optionally right-preconditioned by a
+ * block-Jacobi preconditioner (Section "Preconditioning"), and finds the
+ * leading eigenpairs of J (eq. stability) with the implicitly restarted
+ * Arnoldi method (Algorithm 1, eq. ritz_estimate) applied to the Cayley
+ * transform C = (J - sigma I)^{-1} (J - mu I) (eq. cayley_transform,
+ * eq. cayley_arnoldi).
+ *
+ * Conventions
+ *  - Every pointer named *_dev is a device pointer (HIP memory on the
+ *    context's device); *_host pointers are host memory.  The caller owns
+ *    every buffer it passes; the library never frees caller memory.
+ *  - Vectors are struct-of-arrays, x fastest:
+ *        idx = ((var*Nz + k)*Ny + j)*Nx + i,
+ *    var = (p, u, v, s) in 2D (Nz = 1) and (p, u, v, w, s) in 3D.
+ *    n = nv*Nx*Ny*Nz entries.  Ny counts both wall rows (j = 0, Ny-1).
+ *  - Perturbation vectors live in the interior subspace: the operator is
+ *    P J P with P zeroing the wall rows; wall entries of inputs are ignored
+ *    and wall entries of outputs are written as 0.
+ *  - SA_F64 buffers are double*, SA_F32 buffers are float*.  SA_MIXED takes
+ *    and returns double* and computes the inner work in float.
+ *  - All work is ordered on the stream given to sa_create.  Calls that
+ *    return host results (info / eigen structs) synchronise that stream
+ *    first.  A context is not thread-safe; use one per host thread.
+ *  - Return codes: 0 success; > 0 a result was produced but the requested
+ *    tolerance was not met (the info struct tells which); < 0 an error, the
+ *    outputs are unspecified and sa_last_error() describes it.
+ */
+#ifndef SA_H
+#define SA_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  SA_OK = 0,
+  SA_NOT_CONVERGED = 1, /* budget exhausted before the tolerance was met   */
+  SA_EINVAL = -1,       /* bad argument (shape, size, null pointer, option) */
+  SA_ENOMEM = -2,       /* device allocation failed                          */
+  SA_EDEVICE = -3,      /* a HIP call failed                                 */
+  SA_ESINGULAR = -4,    /* zero pivot in a block factorisation               */
+  SA_ENONFINITE = -5,   /* NaN or Inf in an input or residual                */
+  SA_ESTATE = -6        /* call out of order (e.g. apply before setup)       */
+};
+
+typedef enum { SA_F64 = 0, SA_F32 = 1, SA_MIXED = 2 } sa_prec;
+typedef enum { SA_BC_PERIODIC = 0, SA_BC_WALL = 1 } sa_bc;
+
+typedef struct sa_ctx sa_ctx;
+
+/* One base-flow problem (Section "Governing equations" and "Model problem").
+ * The x (and z) axes are periodic with x_i = i Lx/Nx; the y axis is either
+ * bounded by walls with y_j = -Ly/2 + j Ly/(Ny-1) (both walls on the grid)
+ * or periodic.  Non-dimensional: rho_ref = T_ref = u_inf = delta = 1, so the
+ * reference pressure is 1/(gamma M^2); mu_ref = 1/re (re <= 0: inviscid). */
+typedef struct {
+  int ndim;            /* 2 or 3                                        */
+  int n[3];            /* Nx, Ny, Nz (Nz = 1 in 2D); each >= 7          */
+  double len[3];       /* Lx, Ly, Lz                                    */
+  int bc_y;            /* sa_bc of the y axis                           */
+  double mach, re, pr, gamma, sutherland; /* sutherland = S/T_ref      */
+} sa_problem;
+
+typedef struct {
+  int restart;         /* Krylov dimension m of GMRES(m); 1..128            */
+  double tol;          /* stop when ||b - A x|| <= tol ||b||                */
+  long max_matvec;     /* budget of operator applications (per system)      */
+  int use_precond;     /* 1: right block-Jacobi preconditioning (after setup) */
+  sa_prec prec;        /* F64: all FP64; F32: all FP32 (float buffers);
+                          MIXED: FP64 iterative refinement around FP32 GMRES */
+  double inner_tol;    /* MIXED: relative tolerance of each inner solve     */
+  int max_outer;       /* MIXED: maximum refinement sweeps                  */
+} sa_gmres_opts;
+
+typedef struct {
+  long iters;          /* Arnoldi steps (inner steps for MIXED)            */
+  long matvecs;        /* operator applications (all precisions)           */
+  long precond_applies;
+  int cycles;          /* restart cycles (inner cycles for MIXED)          */
+  int outer;           /* refinement sweeps (MIXED), else 0                */
+  double relres;       /* final true relative residual (FP64 for MIXED)    */
+  int status;          /* SA_OK or SA_NOT_CONVERGED for this system        */
+} sa_gmres_info;
+
+typedef struct {
+  int bx, by, bz;          /* block size in cells (bz = 1 in 2D)          */
+  double diag_add;         /* added to every block diagonal               */
+  double noise_std;        /* std of the seeded N(0,1) noise added         */
+  unsigned long long seed; /* Philox4x32-10 key for the noise             */
+} sa_precond_opts;
+
+typedef struct {
+  int nev;             /* wanted eigenpairs (1..32)                        */
+  int ncv;             /* Arnoldi dimension m (nev+2 .. 64)               */
+  double sigma, mu;    /* Cayley parameters                                */
+  double tol;          /* tol_iram of the Ritz estimate test              */
+  int max_restarts;
+  sa_gmres_opts lin;   /* inner linear solves of the Cayley systems        */
+} sa_eig_opts;
+
+typedef struct {
+  int nconv;           /* wanted Ritz pairs passing the Ritz estimate test */
+  int restarts;
+  long n_cayley;       /* Cayley applications (linear solves)             */
+  long n_matvec;       /* operator applications, all inner solves          */
+  long n_precond;
+  double lam_re[32], lam_im[32];     /* eigenvalues of J (back-transformed) */
+  double theta_re[32], theta_im[32]; /* Ritz values of C, by |theta|        */
+  double ritz_est[32];               /* ||f_m|| |e_m^T y|                    */
+  double resid[32];    /* ||J x - lam x|| / (|lam| ||x||) if vectors given   */
+  double *evec_re_dev, *evec_im_dev; /* caller buffers of nev*n doubles or NULL */
+} sa_eig_result;
+
+/* Context life cycle.  hip_stream is a hipStream_t (may be NULL: the null
+ * stream).  *out is set to a new context or NULL on error. */
+int sa_create(sa_ctx **out, void *hip_stream);
+void sa_destroy(sa_ctx *ctx);
+const char *sa_last_error(const sa_ctx *ctx);
+/* Library version string. */
+const char *sa_version(void);
+
+/* Set the base state q0 (eq. model_stabiity: J is linearised about q0).
+ * q0_dev: nv*Npts doubles (wall rows included), copied into the context,
+ * which also derives its FP32 shadow and pointwise thermodynamic fields.
+ * Errors: SA_EINVAL (bad problem), SA_ENONFINITE (NaN/Inf or non-positive
+ * pressure in q0), SA_ENOMEM. */
+int sa_base_set(sa_ctx *ctx, const sa_problem *prob, const double *q0_dev);
+
+/* y = (J(q0) - shift I) x for nrhs vectors stored one after another
+ * (x_dev, y_dev: nrhs*n entries, double for SA_F64, float for SA_F32).
+ * Section "Matrix free framework": the product N_lin x, computed exactly
+ * (the tangent-linear of the discrete N) rather than by the finite quotient.
+ * x and y must not overlap.  Errors: SA_ESTATE before sa_base_set,
+ * SA_EINVAL (nrhs < 1, null pointer, SA_MIXED). */
+int sa_op_apply(sa_ctx *ctx, sa_prec prec, int nrhs, const void *x_dev, void *y_dev,
+                double shift);
+
+/* Assemble and factor the block-Jacobi preconditioner for nshift shifts
+ * (Section "Preconditioning": blocks of the operator assembled from
+ * operator calls).  Block b of shift s is
+ *     B_b(s) = P_b J P_b^T + diag_add I + noise_std E_b - s I,
+ * E_b seeded standard-normal (Philox4x32-10), P_b the restriction to the
+ * block's DOFs.  Blocks are extracted by coloured probing with the FP64
+ * operator and factored (LU with partial pivoting) in FP32, all blocks of
+ * all shifts in one launch.  Grid sizes must be divisible by the block
+ * size; nb = nv*bx*by*bz <= 128.  Errors: SA_ESTATE, SA_EINVAL,
+ * SA_ENOMEM, SA_ESINGULAR (an exactly zero pivot). */
+int sa_precond_setup(sa_ctx *ctx, const sa_precond_opts *opts, int nshift,
+                     const double *shifts_host);
+
+/* z = P blockdiag(B_b(shift ishift))^{-1} r for nrhs vectors (double for
+ * SA_F64, float for SA_F32; the factors are FP32).  Errors: SA_ESTATE
+ * before setup, SA_EINVAL. */
+int sa_precond_apply(sa_ctx *ctx, sa_prec prec, int ishift, int nrhs, const void *r_dev,
+                     void *z_dev);
+
+/* Solve (J - sigma_s I) x_s = b_s for nshift systems (eq. cayley_arnoldi's
+ * linear system; Section "Iterative solvers": restarted GMRES, here with
+ * classical Gram-Schmidt applied twice).  b_dev / x_dev hold nshift vectors
+ * one after another; x is the initial guess on entry (zero it for x0 = 0)
+ * and the solution on exit.  With use_precond, system s uses the factors of
+ * shift s (nshift must equal the setup's).  info_host[nshift] is filled.
+ * Returns SA_OK if every system converged, SA_NOT_CONVERGED otherwise. */
+int sa_gmres_solve(sa_ctx *ctx, const sa_gmres_opts *opts, int nshift,
+                   const double *sigma_host, const void *b_dev, void *x_dev,
+                   sa_gmres_info *info_host);
+
+/* Leading eigenpairs of J for nprob problems (Algorithm 1 on the Cayley
+ * transform; eigenvalues ordered by decreasing |theta|, theta = (lam - mu)/
+ * (lam - sigma)).  ctxs[p] holds problem p's base state; v0_dev[p] its start
+ * vector (n doubles).  All contexts must share one stream.  res_host[nprob].
+ * Returns SA_OK if all problems converged, SA_NOT_CONVERGED otherwise. */
+int sa_arnoldi_eigs(sa_ctx *const *ctxs, int nprob, const sa_eig_opts *opts,
+                    const double *const *v0_dev, sa_eig_result *res_host);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SA_H */

@@ -1,0 +1,280 @@
+// Vector kernels of the Krylov solvers: multi-dot products against a block of
+// basis vectors, the fused Gram-Schmidt update w -= V h with the next pass's
+// dot products, norms, scaling and precision casts.
+//
+// Every reduction is deterministic: a fixed grid of RED_BLOCKS blocks writes
+// one partial per block (and per column) in double precision, and a second
+// kernel sums the partials in a fixed order.  All kernels take an `active`
+// device flag and return at once when it is zero, so that a whole GMRES
+// cycle can be enqueued ahead and stop on the device when it converges.
+#include "blas.h"
+
+namespace sa {
+namespace {
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+// Sum acc[c] over the block for c < ncol; thread 0.. writes partial[c].
+template <int MAXC>
+__device__ __forceinline__ void block_sum_cols(double (&acc)[MAXC], int ncol, double* __restrict__ out) {
+  __shared__ double red[RED_THREADS / 64][MAXC];
+  const int lane = threadIdx.x & 63;
+  const int wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < MAXC; ++c) {
+    if (c < ncol) {
+      const double s = wave_sum(acc[c]);
+      if (lane == 0) red[wid][c] = s;
+    }
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < ncol; c += blockDim.x) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < RED_THREADS / 64; ++w) s += red[w][c];
+    out[c] = s;
+  }
+}
+
+// partial[b*ldp + c0 + c] = sum over this block's elements of V[c0+c][i] w[i]
+template <typename R, int MAXC>
+__global__ void __launch_bounds__(RED_THREADS) multidot_kernel(long long n, const R* __restrict__ V,
+                                                               long long ldv, int ncol,
+                                                               const R* __restrict__ w,
+                                                               double* __restrict__ partial, int ldp,
+                                                               const int* __restrict__ active) {
+  if (active && !*active) return;
+  const int c0 = blockIdx.y * MAXC;
+  const int nc = min(MAXC, ncol - c0);
+  double acc[MAXC];
+#pragma unroll
+  for (int c = 0; c < MAXC; ++c) acc[c] = 0.0;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const double wi = (double)w[i];
+#pragma unroll
+    for (int c = 0; c < MAXC; ++c)
+      if (c < nc) acc[c] += (double)V[(long long)(c0 + c) * ldv + i] * wi;
+  }
+  block_sum_cols<MAXC>(acc, nc, partial + (long long)blockIdx.x * ldp + c0);
+}
+
+// w_new = w - sum_c V[c] h[c]; writes w_new to wout (may alias w).  If dot:
+// partial dots V^T w_new, else partial ||w_new||^2 in column 0.
+template <typename R, int MAXC>
+__global__ void __launch_bounds__(RED_THREADS) update_dot_kernel(
+    long long n, const R* __restrict__ V, long long ldv, int ncol, const double* __restrict__ h,
+    double hsign, const R* w, R* wout, int dot, double* __restrict__ partial, int ldp,
+    const int* __restrict__ active) {
+  if (active && !*active) return;
+  double hc[MAXC];
+#pragma unroll
+  for (int c = 0; c < MAXC; ++c) hc[c] = c < ncol ? hsign * h[c] : 0.0;
+  double acc[MAXC];
+#pragma unroll
+  for (int c = 0; c < MAXC; ++c) acc[c] = 0.0;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    double vc[MAXC];
+    double s = (double)w[i];
+#pragma unroll
+    for (int c = 0; c < MAXC; ++c) {
+      if (c < ncol) {
+        vc[c] = (double)V[(long long)c * ldv + i];
+        s -= vc[c] * hc[c];
+      }
+    }
+    const R wn = (R)s;
+    wout[i] = wn;
+    const double wd = (double)wn;
+    if (dot) {
+#pragma unroll
+      for (int c = 0; c < MAXC; ++c)
+        if (c < ncol) acc[c] += vc[c] * wd;
+    } else {
+      acc[0] += wd * wd;
+    }
+  }
+  block_sum_cols<MAXC>(acc, dot ? ncol : 1, partial + (long long)blockIdx.x * ldp);
+}
+
+// out[c] = (accumulate ? out[c] : 0) + sum_b partial[b*ldp + c]  (fixed order)
+__global__ void reduce_cols_kernel(const double* __restrict__ partial, int nblocks, int ldp, int ncol,
+                                   double* __restrict__ out, int accumulate,
+                                   const int* __restrict__ active) {
+  if (active && !*active) return;
+  const int c = blockIdx.x;
+  if (c >= ncol) return;
+  __shared__ double red[RED_THREADS];
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nblocks; b += blockDim.x) s += partial[(long long)b * ldp + c];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[c] = accumulate ? out[c] + red[0] : red[0];
+}
+
+// partial ||x||^2 (column 0)
+template <typename R>
+__global__ void __launch_bounds__(RED_THREADS) nrm2_kernel(long long n, const R* __restrict__ x,
+                                                           double* __restrict__ partial, int ldp,
+                                                           const int* __restrict__ active) {
+  if (active && !*active) return;
+  double acc[1] = {0.0};
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const double v = (double)x[i];
+    acc[0] += v * v;
+  }
+  block_sum_cols<1>(acc, 1, partial + (long long)blockIdx.x * ldp);
+}
+
+// r = b - y, partial ||r||^2
+template <typename R>
+__global__ void __launch_bounds__(RED_THREADS) residual_kernel(long long n, const R* __restrict__ b,
+                                                               const R* __restrict__ y, R* __restrict__ r,
+                                                               double* __restrict__ partial, int ldp,
+                                                               const int* __restrict__ active) {
+  if (active && !*active) return;
+  double acc[1] = {0.0};
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const R v = b[i] - y[i];
+    r[i] = v;
+    acc[0] += (double)v * (double)v;
+  }
+  block_sum_cols<1>(acc, 1, partial + (long long)blockIdx.x * ldp);
+}
+
+// out = x * (*scale)   (scale read from device memory)
+template <typename R>
+__global__ void scale_kernel(long long n, const R* __restrict__ x, R* __restrict__ out,
+                             const double* __restrict__ scale, const int* __restrict__ active) {
+  if (active && !*active) return;
+  const double a = *scale;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    out[i] = (R)((double)x[i] * a);
+}
+
+// out = (To)(x * (*scale)) with a precision change
+template <typename Ti, typename To>
+__global__ void cast_scale_kernel(long long n, const Ti* __restrict__ x, To* __restrict__ out,
+                                  const double* __restrict__ scale, int accumulate) {
+  const double a = scale ? *scale : 1.0;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const double v = (double)x[i] * a;
+    out[i] = accumulate ? (To)((double)out[i] + v) : (To)v;
+  }
+}
+
+template <typename R>
+__global__ void fill_kernel(long long n, R* __restrict__ x, R v) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) x[i] = v;
+}
+
+inline unsigned grid_for(long long n) {
+  long long b = (n + RED_THREADS - 1) / RED_THREADS;
+  if (b > RED_BLOCKS) b = RED_BLOCKS;
+  if (b < 1) b = 1;
+  return (unsigned)b;
+}
+
+}  // namespace
+
+template <typename R>
+void Blas<R>::multidot(long long n, const R* V, long long ldv, int ncol, const R* w, double* out,
+                       bool accumulate, const int* active, hipStream_t s) const {
+  const int chunks = (ncol + 15) / 16;
+  const unsigned nb = grid_for(n);
+  multidot_kernel<R, 16><<<dim3(nb, chunks), RED_THREADS, 0, s>>>(n, V, ldv, ncol, w, partial, ldp,
+                                                                 active);
+  reduce_cols_kernel<<<ncol, RED_THREADS, 0, s>>>(partial, (int)nb, ldp, ncol, out, accumulate ? 1 : 0,
+                                                  active);
+}
+
+template <typename R>
+void Blas<R>::update(long long n, const R* V, long long ldv, int ncol, const double* h, double hsign,
+                     const R* w, R* wout, int mode, double* out, bool accumulate, const int* active,
+                     hipStream_t s) const {
+  // mode: 0 = no reduction, 1 = dots V^T w_new, 2 = ||w_new||^2
+  const bool dot = mode == 1;
+  const unsigned nb = grid_for(n);
+  int done = 0;
+  const R* src = w;
+  while (done < ncol || (ncol == 0 && done == 0)) {
+    const int nc = ncol - done;
+    const bool last = nc <= 64;
+    const int c = last ? nc : 64;
+    const int dflag = (last && dot && ncol <= 64) ? 1 : 0;
+    if (c <= 16)
+      update_dot_kernel<R, 16><<<nb, RED_THREADS, 0, s>>>(n, V + (long long)done * ldv, ldv, c,
+                                                                  h + done, hsign, src, wout, dflag,
+                                                                  partial, ldp, active);
+    else if (c <= 32)
+      update_dot_kernel<R, 32><<<nb, RED_THREADS, 0, s>>>(n, V + (long long)done * ldv, ldv, c,
+                                                                  h + done, hsign, src, wout, dflag,
+                                                                  partial, ldp, active);
+    else
+      update_dot_kernel<R, 64><<<nb, RED_THREADS, 0, s>>>(n, V + (long long)done * ldv, ldv, c,
+                                                                  h + done, hsign, src, wout, dflag,
+                                                                  partial, ldp, active);
+    src = wout;
+    done += c;
+    if (last) break;
+  }
+  if (dot && ncol > 64) {
+    multidot(n, V, ldv, ncol, wout, out, accumulate, active, s);
+  } else if (mode == 1) {
+    reduce_cols_kernel<<<ncol, RED_THREADS, 0, s>>>(partial, (int)nb, ldp, ncol, out,
+                                                    accumulate ? 1 : 0, active);
+  } else if (mode == 2) {
+    reduce_cols_kernel<<<1, RED_THREADS, 0, s>>>(partial, (int)nb, ldp, 1, out, accumulate ? 1 : 0,
+                                                 active);
+  }
+}
+
+template <typename R>
+void Blas<R>::nrm2sq(long long n, const R* x, double* out, const int* active, hipStream_t s) const {
+  nrm2_kernel<R><<<grid_for(n), RED_THREADS, 0, s>>>(n, x, partial, ldp, active);
+  reduce_cols_kernel<<<1, RED_THREADS, 0, s>>>(partial, (int)grid_for(n), ldp, 1, out, 0, active);
+}
+
+template <typename R>
+void Blas<R>::residual(long long n, const R* b, const R* y, R* r, double* out, const int* active,
+                       hipStream_t s) const {
+  residual_kernel<R><<<grid_for(n), RED_THREADS, 0, s>>>(n, b, y, r, partial, ldp, active);
+  reduce_cols_kernel<<<1, RED_THREADS, 0, s>>>(partial, (int)grid_for(n), ldp, 1, out, 0, active);
+}
+
+template <typename R>
+void Blas<R>::scale(long long n, const R* x, R* out, const double* a, const int* active,
+                    hipStream_t s) const {
+  scale_kernel<R><<<grid_for(n), RED_THREADS, 0, s>>>(n, x, out, a, active);
+}
+
+template <typename R>
+void Blas<R>::fill(long long n, R* x, R v, hipStream_t s) const {
+  fill_kernel<R><<<grid_for(n), RED_THREADS, 0, s>>>(n, x, v);
+}
+
+template struct Blas<double>;
+template struct Blas<float>;
+
+void cast_d2f(long long n, const double* x, float* out, const double* scale, hipStream_t s) {
+  cast_scale_kernel<double, float><<<grid_for(n), RED_THREADS, 0, s>>>(n, x, out, scale, 0);
+}
+void axpy_f2d(long long n, const float* x, double* out, const double* scale, hipStream_t s) {
+  cast_scale_kernel<float, double><<<grid_for(n), RED_THREADS, 0, s>>>(n, x, out, scale, 1);
+}
+
+}  // namespace sa

@@ -1,0 +1,378 @@
+// Tangent-linear Navier-Stokes operator: y = (J(q0) - shift I) x.
+//
+// J is the exact derivative of the discrete right-hand side N(q) of the
+// compressible Navier-Stokes equations in (p, u_i, s) form (Section
+// "Governing equations", eq. navier_stokes), i.e. the operator N_lin that
+// the Frechet quotient of eq. frechet approximates.  The discretisation:
+//   * explicit central differences, 6th order in the interior, 4th and 2nd
+//     order on the second and first rows next to a wall; mixed derivatives
+//     are products of first differences;
+//   * viscous terms in expanded form, d_j tau_ij = mu L u_i + mu/3 G_i +
+//     mu'(T)[D_j T (D_j u_i + D_i u_j) - 2/3 D_i T D_k u_k] with
+//     G_i = D2_i u_i + sum_{j!=i} D_i D_j u_j, heat flux lambda L T +
+//     lambda'(T) |D T|^2, dissipation mu (2 s_ij s_ij - 2/3 s_kk^2);
+//   * the pressure equation with the material derivative and the heat
+//     terms (gamma-1)(Q+Phi); the entropy equation with +(Q+Phi)/(rho T);
+//   * Sutherland viscosity, lambda = c_p mu/Pr, ideal gas.
+// Linearisation: every product is differentiated by the product rule; the
+// temperature perturbation T' = T_p p' + T_s s' is formed pointwise before
+// it is differentiated; base-state derivatives are the discrete ones.
+#include "sa_internal.h"
+
+namespace sa {
+namespace {
+
+template <typename R, int ND>
+struct Pt {
+  R q[ND + 3];        // p, u_1..u_ND, s, T
+  R D[ND + 3][ND];    // D_a of each of them
+  R Lu[ND];           // sum_a D2_a u_i
+  R G[ND];            // D2_i u_i + sum_{j != i} D_i D_j u_j
+  R LT;               // sum_a D2_a T
+};
+
+// Stencil coefficients of one axis at one point.
+template <typename R>
+struct Axis {
+  R c1[3];   // multiplies f(+m) - f(-m)
+  R c0;      // second-derivative centre
+  R c2[3];   // multiplies f(+m) + f(-m)
+};
+
+template <typename R>
+__device__ __forceinline__ Axis<R> axis_coefs(int order) {
+  Axis<R> a;
+  if (order == 6) {
+    a.c1[0] = R(3.0 / 4.0); a.c1[1] = R(-3.0 / 20.0); a.c1[2] = R(1.0 / 60.0);
+    a.c0 = R(-49.0 / 18.0);
+    a.c2[0] = R(3.0 / 2.0); a.c2[1] = R(-3.0 / 20.0); a.c2[2] = R(1.0 / 90.0);
+  } else if (order == 4) {
+    a.c1[0] = R(2.0 / 3.0); a.c1[1] = R(-1.0 / 12.0); a.c1[2] = R(0);
+    a.c0 = R(-5.0 / 2.0);
+    a.c2[0] = R(4.0 / 3.0); a.c2[1] = R(-1.0 / 12.0); a.c2[2] = R(0);
+  } else if (order == 2) {
+    a.c1[0] = R(1.0 / 2.0); a.c1[1] = R(0); a.c1[2] = R(0);
+    a.c0 = R(-2.0);
+    a.c2[0] = R(1.0); a.c2[1] = R(0); a.c2[2] = R(0);
+  } else {
+    a.c1[0] = a.c1[1] = a.c1[2] = R(0);
+    a.c0 = R(0);
+    a.c2[0] = a.c2[1] = a.c2[2] = R(0);
+  }
+  return a;
+}
+
+__device__ __forceinline__ int wall_row_order(int j, int ny, int bcy) {
+  if (bcy == 0) return 6;
+  if (j <= 0 || j >= ny - 1) return 0;
+  if (j == 1 || j == ny - 2) return 2;
+  if (j == 2 || j == ny - 3) return 4;
+  return 6;
+}
+
+// Field access around one point.  Variables 0..ND+1 are p, u_i, s; ND+2 is T.
+// PERT: values come from the perturbation x (zero on wall rows), T' is formed
+// from the base fields T_p, T_s.  !PERT: base fields, T from the T0 field.
+template <typename R, int ND, bool PERT>
+struct Acc {
+  const R* base;
+  const R* x;
+  long long npts;
+  int nx, ny, nz, bcy;
+  int i, j, k;
+
+  __device__ __forceinline__ long long at(int di, int dj, int dk, bool& wall) const {
+    int ii = i + di;
+    ii = ii < 0 ? ii + nx : (ii >= nx ? ii - nx : ii);
+    int jj = j + dj;
+    if (bcy == 0) {
+      jj = jj < 0 ? jj + ny : (jj >= ny ? jj - ny : jj);
+      wall = false;
+    } else {
+      jj = jj < 0 ? 0 : (jj >= ny ? ny - 1 : jj);   // clamped: coefficient is 0 there
+      wall = (jj == 0 || jj == ny - 1);
+    }
+    int kk = 0;
+    if (ND == 3) {
+      kk = k + dk;
+      kk = kk < 0 ? kk + nz : (kk >= nz ? kk - nz : kk);
+    }
+    return ((long long)kk * ny + jj) * nx + ii;
+  }
+
+  __device__ __forceinline__ R operator()(int f, int di, int dj, int dk) const {
+    bool wall;
+    long long id = at(di, dj, dk, wall);
+    if (!PERT) return base[(long long)f * npts + id];
+    if (wall) return R(0);
+    if (f < ND + 2) return x[(long long)f * npts + id];
+    // T' = T_p p' + T_s s'
+    const R tp = base[(long long)(ND + 3) * npts + id];
+    const R ts = base[(long long)(ND + 4) * npts + id];
+    return tp * x[id] + ts * x[(long long)(ND + 1) * npts + id];
+  }
+};
+
+template <typename R, int ND, bool PERT>
+__device__ __forceinline__ R d1(const Acc<R, ND, PERT>& A, int f, int a, const Axis<R>& ax, R ih) {
+  R acc = R(0);
+#pragma unroll
+  for (int m = 1; m <= 3; ++m) {
+    const int dx = a == 0 ? m : 0, dy = a == 1 ? m : 0, dz = a == 2 ? m : 0;
+    acc += ax.c1[m - 1] * (A(f, dx, dy, dz) - A(f, -dx, -dy, -dz));
+  }
+  return acc * ih;
+}
+
+template <typename R, int ND, bool PERT>
+__device__ __forceinline__ R d2(const Acc<R, ND, PERT>& A, int f, int a, const Axis<R>& ax, R ih) {
+  R acc = ax.c0 * A(f, 0, 0, 0);
+#pragma unroll
+  for (int m = 1; m <= 3; ++m) {
+    const int dx = a == 0 ? m : 0, dy = a == 1 ? m : 0, dz = a == 2 ? m : 0;
+    acc += ax.c2[m - 1] * (A(f, dx, dy, dz) + A(f, -dx, -dy, -dz));
+  }
+  return acc * (ih * ih);
+}
+
+// D_a D_b f (a != b) as the tensor product of the two first differences.
+template <typename R, int ND, bool PERT>
+__device__ __forceinline__ R dmix(const Acc<R, ND, PERT>& A, int f, int a, int b,
+                                  const Axis<R>& axa, const Axis<R>& axb, R iha, R ihb) {
+  R acc = R(0);
+#pragma unroll
+  for (int m = 1; m <= 3; ++m) {
+    R inner = R(0);
+#pragma unroll
+    for (int n = 1; n <= 3; ++n) {
+      int o1[3] = {0, 0, 0}, o2[3] = {0, 0, 0};
+      o1[a] = m;
+      o2[b] = n;
+      const R pp = A(f, o1[0] + o2[0], o1[1] + o2[1], o1[2] + o2[2]);
+      const R pm = A(f, o1[0] - o2[0], o1[1] - o2[1], o1[2] - o2[2]);
+      const R mp = A(f, -o1[0] + o2[0], -o1[1] + o2[1], -o1[2] + o2[2]);
+      const R mm = A(f, -o1[0] - o2[0], -o1[1] - o2[1], -o1[2] - o2[2]);
+      inner += axb.c1[n - 1] * ((pp - pm) - (mp - mm));
+    }
+    acc += axa.c1[m - 1] * inner;
+  }
+  return acc * (iha * ihb);
+}
+
+template <typename R, int ND, bool PERT>
+__device__ __forceinline__ void gather(Pt<R, ND>& P, const Acc<R, ND, PERT>& A, const Axis<R>* ax,
+                                       const R* ih) {
+#pragma unroll
+  for (int f = 0; f < ND + 3; ++f) {
+    P.q[f] = A(f, 0, 0, 0);
+#pragma unroll
+    for (int a = 0; a < ND; ++a) P.D[f][a] = d1(A, f, a, ax[a], ih[a]);
+  }
+#pragma unroll
+  for (int i = 0; i < ND; ++i) {
+    R L = R(0);
+    R d2ii = R(0);
+#pragma unroll
+    for (int a = 0; a < ND; ++a) {
+      const R v = d2(A, 1 + i, a, ax[a], ih[a]);
+      L += v;
+      if (a == i) d2ii = v;
+    }
+    P.Lu[i] = L;
+    R g = d2ii;
+#pragma unroll
+    for (int jv = 0; jv < ND; ++jv)
+      if (jv != i) g += dmix(A, 1 + jv, i, jv, ax[i], ax[jv], ih[i], ih[jv]);
+    P.G[i] = g;
+  }
+  R LT = R(0);
+#pragma unroll
+  for (int a = 0; a < ND; ++a) LT += d2(A, ND + 2, a, ax[a], ih[a]);
+  P.LT = LT;
+}
+
+// Pointwise tangent-linear algebra: out = N'(q0; v) given base and
+// perturbation data at one point.
+template <typename R, int ND>
+__device__ __forceinline__ void tangent(const Pt<R, ND>& b, const Pt<R, ND>& v, const OpParams& op,
+                                        R rho, R mu0, R muT, R muTT, R out[ND + 2]) {
+  const R gam = R(op.gamma);
+  const R cp = R(op.cp);
+  const R cpr = R(op.cp / op.pr);
+  const R p0 = b.q[0];
+  const R T0 = b.q[ND + 2];
+  const R pp = v.q[0];
+  const R sp = v.q[ND + 1];
+  const R Tpr = v.q[ND + 2];
+  const R rhop = rho * (pp / (gam * p0) - sp / cp);   // rho_p p' + rho_s s'
+
+  R th0 = R(0), thp = R(0);
+#pragma unroll
+  for (int k = 0; k < ND; ++k) {
+    th0 += b.D[1 + k][k];
+    thp += v.D[1 + k][k];
+  }
+  R S00 = R(0), S0p = R(0);
+#pragma unroll
+  for (int i = 0; i < ND; ++i)
+#pragma unroll
+    for (int j = 0; j < ND; ++j) {
+      const R s0 = R(0.5) * (b.D[1 + i][j] + b.D[1 + j][i]);
+      const R s1 = R(0.5) * (v.D[1 + i][j] + v.D[1 + j][i]);
+      S00 += s0 * s0;
+      S0p += s0 * s1;
+    }
+  R g2 = R(0), g1 = R(0);
+#pragma unroll
+  for (int j = 0; j < ND; ++j) {
+    g2 += b.D[ND + 2][j] * b.D[ND + 2][j];
+    g1 += b.D[ND + 2][j] * v.D[ND + 2][j];
+  }
+  const R lam0 = cpr * mu0, lamT = cpr * muT, lamTT = cpr * muTT;
+  const R phiS = R(2) * S00 - R(2.0 / 3.0) * th0 * th0;
+  const R Phi0 = mu0 * phiS;
+  const R Phip = muT * Tpr * phiS + mu0 * (R(4) * S0p - R(4.0 / 3.0) * th0 * thp);
+  const R Q0 = lam0 * b.LT + lamT * g2;
+  const R Qp = lamT * Tpr * b.LT + lam0 * v.LT + lamTT * Tpr * g2 + R(2) * lamT * g1;
+  const R H0 = Q0 + Phi0;
+  const R Hp = Qp + Phip;
+
+  // pressure
+  R adv = R(0);
+#pragma unroll
+  for (int j = 0; j < ND; ++j) adv += v.q[1 + j] * b.D[0][j] + b.q[1 + j] * v.D[0][j];
+  out[0] = -adv - gam * (pp * th0 + p0 * thp) + (gam - R(1)) * Hp;
+
+  // velocity
+  const R irho = R(1) / rho;
+#pragma unroll
+  for (int i = 0; i < ND; ++i) {
+    R c0 = R(0), cpert = R(0), advu = R(0);
+#pragma unroll
+    for (int j = 0; j < ND; ++j) {
+      const R s0 = b.D[1 + i][j] + b.D[1 + j][i];   // 2 s0_ij
+      const R s1 = v.D[1 + i][j] + v.D[1 + j][i];   // 2 s'_ij
+      c0 += b.D[ND + 2][j] * s0;
+      cpert += v.D[ND + 2][j] * s0 + b.D[ND + 2][j] * s1;
+      advu += v.q[1 + j] * b.D[1 + i][j] + b.q[1 + j] * v.D[1 + i][j];
+    }
+    const R visc0 = b.Lu[i] + b.G[i] * R(1.0 / 3.0);
+    const R viscp = v.Lu[i] + v.G[i] * R(1.0 / 3.0);
+    const R bT0 = c0 - R(2.0 / 3.0) * b.D[ND + 2][i] * th0;
+    const R V0 = mu0 * visc0 + muT * bT0;
+    const R Vp = muT * Tpr * visc0 + mu0 * viscp + muTT * Tpr * bT0 +
+                 muT * (cpert - R(2.0 / 3.0) * (v.D[ND + 2][i] * th0 + b.D[ND + 2][i] * thp));
+    out[1 + i] = -advu + (Vp - v.D[0][i]) * irho - rhop * (V0 - b.D[0][i]) * irho * irho;
+  }
+
+  // entropy
+  R advs = R(0);
+#pragma unroll
+  for (int j = 0; j < ND; ++j) advs += v.q[1 + j] * b.D[ND + 1][j] + b.q[1 + j] * v.D[ND + 1][j];
+  const R rT = rho * T0;
+  out[ND + 1] = -advs + Hp / rT - H0 * (rhop * T0 + rho * Tpr) / (rT * rT);
+}
+
+template <typename R, int ND>
+__global__ void __launch_bounds__(256) jv_direct_kernel(OpParams op, const R* __restrict__ base,
+                                                        const R* __restrict__ x, R* __restrict__ y,
+                                                        int nrhs, R shift,
+                                                        const int* __restrict__ active) {
+  if (active && !*active) return;
+  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= op.npts) return;
+  const int i = (int)(id % op.nx);
+  const int j = (int)((id / op.nx) % op.ny);
+  const int k = ND == 3 ? (int)(id / ((long long)op.nx * op.ny)) : 0;
+  const long long ndof = (long long)(ND + 2) * op.npts;
+  const bool wall = op.bcy == 1 && (j == 0 || j == op.ny - 1);
+  if (wall) {
+    for (int r = 0; r < nrhs; ++r)
+#pragma unroll
+      for (int f = 0; f < ND + 2; ++f) y[r * ndof + (long long)f * op.npts + id] = R(0);
+    return;
+  }
+  Axis<R> ax[3];
+  ax[0] = axis_coefs<R>(6);
+  ax[1] = axis_coefs<R>(wall_row_order(j, op.ny, op.bcy));
+  ax[2] = axis_coefs<R>(6);
+  const R ih[3] = {R(op.ihx), R(op.ihy), R(op.ihz)};
+
+  Acc<R, ND, false> Ab{base, nullptr, op.npts, op.nx, op.ny, op.nz, op.bcy, i, j, k};
+  Pt<R, ND> b;
+  gather(b, Ab, ax, ih);
+
+  // pointwise base thermodynamics
+  const R T0 = b.q[ND + 2];
+  const R rho = b.q[0] / (R(op.R) * T0);
+  const R S = R(op.suth);
+  const R mu0 = R(op.mu_ref) * T0 * sqrt(T0) * (R(1) + S) / (T0 + S);
+  const R f1 = R(1.5) / T0 - R(1) / (T0 + S);
+  const R muT = mu0 * f1;
+  const R muTT = muT * f1 + mu0 * (R(-1.5) / (T0 * T0) + R(1) / ((T0 + S) * (T0 + S)));
+
+  for (int r = 0; r < nrhs; ++r) {
+    const R* xr = x + r * ndof;
+    Acc<R, ND, true> Av{base, xr, op.npts, op.nx, op.ny, op.nz, op.bcy, i, j, k};
+    Pt<R, ND> v;
+    gather(v, Av, ax, ih);
+    R out[ND + 2];
+    tangent<R, ND>(b, v, op, rho, mu0, muT, muTT, out);
+#pragma unroll
+    for (int f = 0; f < ND + 2; ++f) {
+      const long long o = (long long)f * op.npts + id;
+      y[r * ndof + o] = out[f] - shift * xr[o];
+    }
+  }
+}
+
+__global__ void base_derive_kernel(OpParams op, double* __restrict__ base, float* __restrict__ base32,
+                                   int* __restrict__ flag) {
+  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= op.npts) return;
+  const int nv = op.ndim + 2;
+  const double p = base[id];
+  const double s = base[(long long)(nv - 1) * op.npts + id];
+  bool bad = !(p > 0.0) || !isfinite(p);
+  for (int f = 0; f < nv; ++f) bad = bad || !isfinite(base[(long long)f * op.npts + id]);
+  // rho = (p/p_ref)^(1/gamma) exp(-s/c_p), T = p/(rho R)
+  const double rho = exp(log(p / op.p_ref) / op.gamma - s / op.cp);
+  const double T = p / (rho * op.R);
+  const double Tp = T / p * (1.0 - 1.0 / op.gamma);
+  const double Ts = T / op.cp;
+  base[(long long)nv * op.npts + id] = T;
+  base[(long long)(nv + 1) * op.npts + id] = Tp;
+  base[(long long)(nv + 2) * op.npts + id] = Ts;
+  for (int f = 0; f < nv + 3; ++f)
+    base32[(long long)f * op.npts + id] = (float)base[(long long)f * op.npts + id];
+  if (bad) atomicOr(flag, 1);
+}
+
+}  // namespace
+
+template <typename R>
+hipError_t launch_jv(const OpParams& p, const R* base, const R* x, R* y, int nrhs, R shift,
+                     const int* active, hipStream_t s) {
+  const int threads = 256;
+  const long long blocks = (p.npts + threads - 1) / threads;
+  if (p.ndim == 2)
+    jv_direct_kernel<R, 2><<<dim3((unsigned)blocks), dim3(threads), 0, s>>>(p, base, x, y, nrhs, shift, active);
+  else
+    jv_direct_kernel<R, 3><<<dim3((unsigned)blocks), dim3(threads), 0, s>>>(p, base, x, y, nrhs, shift, active);
+  return hipGetLastError();
+}
+
+template hipError_t launch_jv<double>(const OpParams&, const double*, const double*, double*, int,
+                                      double, const int*, hipStream_t);
+template hipError_t launch_jv<float>(const OpParams&, const float*, const float*, float*, int, float,
+                                     const int*, hipStream_t);
+
+hipError_t launch_base_derive(const OpParams& p, double* base, float* base32, int* flag,
+                              hipStream_t s) {
+  const int threads = 256;
+  const long long blocks = (p.npts + threads - 1) / threads;
+  base_derive_kernel<<<dim3((unsigned)blocks), dim3(threads), 0, s>>>(p, base, base32, flag);
+  return hipGetLastError();
+}
+
+}  // namespace sa

@@ -1,0 +1,182 @@
+// C ABI of libsa: context, base state, operator application and the GMRES
+// solvers of the Cayley systems.  Host code only orchestrates: every
+// arithmetic step runs in the kernels of jv.hip, blas.hip, gmres_small.hip,
+// arnoldi_small.hip and bjac.hip.
+#include "sa_runtime.h"
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+
+using namespace sa;
+
+namespace sa {
+
+int Ctx::fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  err = buf;
+  return code;
+}
+
+int Ctx::hip_fail(hipError_t e, const char* where) {
+  return fail(e == hipErrorOutOfMemory ? SA_ENOMEM : SA_EDEVICE, "%s: %s", where,
+              hipGetErrorString(e));
+}
+
+void* Ctx::buffer(const std::string& name, size_t bytes, bool zero) {
+  auto it = bufs.find(name);
+  if (it != bufs.end() && it->second.bytes >= bytes) return it->second.ptr;
+  if (it != bufs.end()) {
+    hipStreamSynchronize(stream);
+    hipFree(it->second.ptr);
+    bufs.erase(it);
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes == 0 ? 256 : bytes) != hipSuccess) return nullptr;
+  if (zero) hipMemsetAsync(p, 0, bytes, stream);
+  bufs[name] = Buf{p, bytes};
+  return p;
+}
+
+Ctx::~Ctx() {
+  if (stream) hipStreamSynchronize(stream);
+  for (auto& kv : bufs) hipFree(kv.second.ptr);
+}
+
+}  // namespace sa
+
+extern "C" {
+
+const char* sa_version(void) { return "sa-mi355x 0.1 (gfx950)"; }
+
+int sa_create(sa_ctx** out, void* hip_stream) {
+  if (!out) return SA_EINVAL;
+  *out = nullptr;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return SA_EDEVICE;
+  auto* c = new (std::nothrow) sa_ctx();
+  if (!c) return SA_ENOMEM;
+  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  c->device = dev;
+  *out = c;
+  return SA_OK;
+}
+
+void sa_destroy(sa_ctx* ctx) { delete ctx; }
+
+const char* sa_last_error(const sa_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int sa_base_set(sa_ctx* c, const sa_problem* pb, const double* q0_dev) {
+  if (!c) return SA_EINVAL;
+  if (!pb || !q0_dev) return c->fail(SA_EINVAL, "sa_base_set: null argument");
+  if (pb->ndim != 2 && pb->ndim != 3) return c->fail(SA_EINVAL, "sa_base_set: ndim must be 2 or 3");
+  const int nz = pb->ndim == 2 ? 1 : pb->n[2];
+  if (pb->n[0] < 7 || pb->n[1] < 7 || (pb->ndim == 3 && nz < 7))
+    return c->fail(SA_EINVAL, "sa_base_set: every axis needs at least 7 points");
+  if (pb->ndim == 2 && pb->n[2] != 1) return c->fail(SA_EINVAL, "sa_base_set: 2D needs n[2] == 1");
+  if (pb->bc_y != SA_BC_PERIODIC && pb->bc_y != SA_BC_WALL)
+    return c->fail(SA_EINVAL, "sa_base_set: bad bc_y");
+  if (!(pb->mach > 0) || !(pb->gamma > 1) || !(pb->pr > 0) || !(pb->sutherland > 0))
+    return c->fail(SA_EINVAL, "sa_base_set: mach, gamma, pr, sutherland must be positive (gamma > 1)");
+  for (int a = 0; a < pb->ndim; ++a)
+    if (!(pb->len[a] > 0)) return c->fail(SA_EINVAL, "sa_base_set: lengths must be positive");
+  OpParams& op = c->op;
+  op.ndim = pb->ndim;
+  op.nx = pb->n[0];
+  op.ny = pb->n[1];
+  op.nz = nz;
+  op.bcy = pb->bc_y;
+  op.npts = (long long)op.nx * op.ny * op.nz;
+  op.ihx = op.nx / pb->len[0];
+  op.ihy = (pb->bc_y == SA_BC_WALL ? (op.ny - 1) : op.ny) / pb->len[1];
+  op.ihz = pb->ndim == 3 ? op.nz / pb->len[2] : 1.0;
+  op.gamma = pb->gamma;
+  op.R = 1.0 / (pb->gamma * pb->mach * pb->mach);
+  op.p_ref = op.R;
+  op.cp = pb->gamma * op.R / (pb->gamma - 1.0);
+  op.mu_ref = pb->re > 0 ? 1.0 / pb->re : 0.0;
+  op.suth = pb->sutherland;
+  op.pr = pb->pr;
+  c->prob = *pb;
+  c->nv = pb->ndim + 2;
+  c->n = (long long)c->nv * op.npts;
+  const size_t nf = (size_t)(c->nv + 3) * op.npts;
+  c->has_base = false;
+  c->has_precond = false;
+  c->base64 = (double*)c->buffer("base64", nf * sizeof(double));
+  c->base32 = (float*)c->buffer("base32", nf * sizeof(float));
+  int* flag = (int*)c->buffer("flag", sizeof(int));
+  if (!c->base64 || !c->base32 || !flag) return c->fail(SA_ENOMEM, "sa_base_set: out of device memory");
+  hipError_t e = hipMemcpyAsync(c->base64, q0_dev, (size_t)c->n * sizeof(double), hipMemcpyDeviceToDevice,
+                                c->stream);
+  if (e != hipSuccess) return c->hip_fail(e, "sa_base_set copy");
+  hipMemsetAsync(flag, 0, sizeof(int), c->stream);
+  e = launch_base_derive(op, c->base64, c->base32, flag, c->stream);
+  if (e != hipSuccess) return c->hip_fail(e, "sa_base_set derive");
+  int hflag = 0;
+  hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+  e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return c->hip_fail(e, "sa_base_set sync");
+  if (hflag) return c->fail(SA_ENONFINITE, "sa_base_set: q0 has NaN/Inf or non-positive pressure");
+  c->has_base = true;
+  return SA_OK;
+}
+
+int sa_op_apply(sa_ctx* c, sa_prec prec, int nrhs, const void* x_dev, void* y_dev, double shift) {
+  if (!c) return SA_EINVAL;
+  if (!c->has_base) return c->fail(SA_ESTATE, "sa_op_apply: call sa_base_set first");
+  if (nrhs < 1 || !x_dev || !y_dev) return c->fail(SA_EINVAL, "sa_op_apply: bad nrhs or null pointer");
+  hipError_t e;
+  if (prec == SA_F64)
+    e = launch_jv<double>(c->op, c->base64, (const double*)x_dev, (double*)y_dev, nrhs, shift, nullptr,
+                          c->stream);
+  else if (prec == SA_F32)
+    e = launch_jv<float>(c->op, c->base32, (const float*)x_dev, (float*)y_dev, nrhs, (float)shift,
+                         nullptr, c->stream);
+  else
+    return c->fail(SA_EINVAL, "sa_op_apply: precision must be SA_F64 or SA_F32");
+  if (e != hipSuccess) return c->hip_fail(e, "sa_op_apply");
+  return SA_OK;
+}
+
+int sa_gmres_solve(sa_ctx* c, const sa_gmres_opts* o, int nshift, const double* sigma_host,
+                   const void* b_dev, void* x_dev, sa_gmres_info* info) {
+  if (!c) return SA_EINVAL;
+  if (!c->has_base) return c->fail(SA_ESTATE, "sa_gmres_solve: call sa_base_set first");
+  if (!o || !sigma_host || !b_dev || !x_dev || !info || nshift < 1)
+    return c->fail(SA_EINVAL, "sa_gmres_solve: null argument or nshift < 1");
+  if (o->restart < 1 || o->restart > GMAX) return c->fail(SA_EINVAL, "sa_gmres_solve: restart must be 1..%d", GMAX);
+  if (!(o->tol > 0) || o->max_matvec < 1) return c->fail(SA_EINVAL, "sa_gmres_solve: bad tol or max_matvec");
+  if (o->use_precond) {
+    if (!c->has_precond) return c->fail(SA_ESTATE, "sa_gmres_solve: preconditioner not set up");
+    if (nshift != c->pc_nshift)
+      return c->fail(SA_EINVAL, "sa_gmres_solve: nshift must equal the preconditioner's shift count");
+  }
+  if (o->prec == SA_MIXED && (!(o->inner_tol > 0) || o->max_outer < 1))
+    return c->fail(SA_EINVAL, "sa_gmres_solve: MIXED needs inner_tol > 0 and max_outer >= 1");
+  int rc_all = SA_OK;
+  for (int s = 0; s < nshift; ++s) {
+    int rc;
+    const long long off = (long long)s * c->n;
+    const int pci = o->use_precond ? s : -1;
+    if (o->prec == SA_F64)
+      rc = solve_gmres<double>(c, *o, sigma_host[s], (const double*)b_dev + off, (double*)x_dev + off, pci,
+                               &info[s]);
+    else if (o->prec == SA_F32)
+      rc = solve_gmres<float>(c, *o, sigma_host[s], (const float*)b_dev + off, (float*)x_dev + off, pci,
+                              &info[s]);
+    else if (o->prec == SA_MIXED)
+      rc = solve_ir(c, *o, sigma_host[s], (const double*)b_dev + off, (double*)x_dev + off, pci, &info[s]);
+    else
+      return c->fail(SA_EINVAL, "sa_gmres_solve: bad precision");
+    if (rc < 0) return rc;
+    if (rc > 0) rc_all = rc;
+  }
+  return rc_all;
+}
+
+}  // extern "C"

@@ -1,0 +1,63 @@
+// Host-side runtime of libsa: the context and the solver drivers.
+#pragma once
+
+#include <cstdarg>
+#include <map>
+#include <string>
+
+#include "../../include/sa.h"
+#include "blas.h"
+#include "gmres_small.h"
+#include "sa_internal.h"
+
+namespace sa {
+
+struct Buf {
+  void* ptr;
+  size_t bytes;
+};
+
+struct Ctx {
+  hipStream_t stream = nullptr;
+  int device = 0;
+  std::string err;
+  std::map<std::string, Buf> bufs;
+
+  bool has_base = false;
+  sa_problem prob{};
+  OpParams op{};
+  int nv = 0;
+  long long n = 0;
+  double* base64 = nullptr;
+  float* base32 = nullptr;
+
+  // block-Jacobi preconditioner
+  bool has_precond = false;
+  int pc_nshift = 0;
+  int pc_nb = 0;           // block order
+  long long pc_nblocks = 0;
+  int pc_bx = 0, pc_by = 0, pc_bz = 0;
+  float* pc_lu = nullptr;  // [nshift][nblocks][nb][nb] LU factors (row-major)
+  int* pc_piv = nullptr;   // [nshift][nblocks][nb]
+  int* pc_dof = nullptr;   // [nblocks][nb] flat DOF index (wall DOFs -> -1)
+
+  int fail(int code, const char* fmt, ...);
+  int hip_fail(hipError_t e, const char* where);
+  // Named, context-owned device buffer of at least `bytes` (kept across calls).
+  void* buffer(const std::string& name, size_t bytes, bool zero = true);
+  ~Ctx();
+};
+
+template <typename R>
+int solve_gmres(Ctx* c, const sa_gmres_opts& o, double sigma, const R* b, R* x, int pc_shift,
+                sa_gmres_info* info, const std::string& tag = "g");
+int solve_ir(Ctx* c, const sa_gmres_opts& o, double sigma, const double* b, double* x, int pc_shift,
+             sa_gmres_info* info);
+
+// block-Jacobi apply z = P M^{-1} r (bjac.hip)
+template <typename R>
+hipError_t precond_apply(Ctx* c, int ishift, int nrhs, const R* r, R* z, const int* active);
+
+}  // namespace sa
+
+struct sa_ctx : sa::Ctx {};

@@ -1,0 +1,102 @@
+"""Parity of the HIP GMRES / iterative-refinement solves of the Cayley system
+(J - sigma I) x = b with the oracle (dense solve of the oracle's Jacobian and
+the oracle's GMRES)."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import krylov as kr
+from oracle import operator as op
+from gpu_util import dev, host, need_gpu, rel, torch
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def small():
+    need_gpu()
+    from paper_1502_03701_amd import Context
+    prob = synth.mixing_layer_2d(16, 14, 0.3, 500.0)
+    q0 = synth.random_base(prob, 21)
+    J = op.dense_jacobian(prob, q0)
+    idx = op.interior_index(prob)
+    ctx = Context()
+    ctx.base_set(prob, dev(q0))
+    return prob, q0, J, idx, ctx
+
+
+def _solve_ref(J, idx, prob, b, sigma):
+    A = J - sigma * np.eye(J.shape[0])
+    x = np.zeros(prob.ndof)
+    x[idx] = np.linalg.solve(A, b.ravel()[idx])
+    return x, np.linalg.cond(A)
+
+
+@pytest.mark.parametrize("restart", [40, 7])
+def test_gmres_fp64_solution(small, restart):
+    prob, q0, J, idx, ctx = small
+    b = synth.random_vector(prob, 31)
+    x = torch.zeros(prob.ndof, dtype=torch.float64, device="cuda:0")
+    rc, info = ctx.gmres_solve([0.2], dev(b), x, restart=restart, tol=1e-10, max_matvec=200000)
+    assert rc == 0 and info[0]["status"] == 0
+    assert info[0]["relres"] <= 1e-10
+    xr, cond = _solve_ref(J, idx, prob, b, 0.2)
+    assert rel(host(x), xr) < 1e-10 * cond
+    # same Krylov method as the oracle's GMRES: iteration counts agree closely
+    A = J - 0.2 * np.eye(J.shape[0])
+    _, oi = kr.gmres(lambda v: A @ v, b.ravel()[idx], restart=restart, tol=1e-10, max_matvec=200000)
+    assert abs(info[0]["iters"] - oi["iters"]) <= max(2, oi["iters"] // 50)
+
+
+def test_gmres_fp32_and_mixed(small):
+    prob, q0, J, idx, ctx = small
+    from paper_1502_03701_amd import SA_F32, SA_MIXED
+    b = synth.random_vector(prob, 32)
+    xr, cond = _solve_ref(J, idx, prob, b, 0.2)
+    x32 = torch.zeros(prob.ndof, dtype=torch.float32, device="cuda:0")
+    rc, info = ctx.gmres_solve([0.2], dev(b, torch.float32), x32, restart=30, tol=1e-4, prec=SA_F32)
+    assert rc == 0 and info[0]["relres"] <= 1e-4
+    xm = torch.zeros(prob.ndof, dtype=torch.float64, device="cuda:0")
+    rc, info = ctx.gmres_solve([0.2], dev(b), xm, restart=30, tol=1e-10, prec=SA_MIXED,
+                               inner_tol=1e-4, max_outer=20)
+    assert rc == 0 and info[0]["relres"] <= 1e-10 and info[0]["outer"] >= 2
+    assert rel(host(xm), xr) < 1e-10 * cond
+
+
+def test_gmres_multi_shift_equals_single(small):
+    prob, q0, J, idx, ctx = small
+    sig = [0.05, 0.15, 0.3]
+    B = synth.random_vector(prob, 33, nrhs=3)
+    X = torch.zeros(3 * prob.ndof, dtype=torch.float64, device="cuda:0")
+    rc, info = ctx.gmres_solve(sig, dev(B), X, restart=30, tol=1e-10)
+    assert rc == 0
+    Xh = host(X).reshape(3, -1)
+    for s in range(3):
+        x1 = torch.zeros(prob.ndof, dtype=torch.float64, device="cuda:0")
+        ctx.gmres_solve([sig[s]], dev(B[s]), x1, restart=30, tol=1e-10)
+        assert np.array_equal(host(x1), Xh[s])
+        xr, cond = _solve_ref(J, idx, prob, B[s], sig[s])
+        assert rel(Xh[s], xr) < 1e-10 * cond
+
+
+def test_gmres_edge_cases(small):
+    prob, q0, J, idx, ctx = small
+    from paper_1502_03701_amd import SAError
+    from paper_1502_03701_amd import _native as n
+    b = synth.random_vector(prob, 34)
+    x = torch.zeros(prob.ndof, dtype=torch.float64, device="cuda:0")
+    rc, info = ctx.gmres_solve([0.2], dev(b), x, restart=5, tol=1e-14, max_matvec=3)
+    assert rc == n.SA_NOT_CONVERGED and info[0]["status"] == n.SA_NOT_CONVERGED
+    assert info[0]["matvecs"] <= 4
+    z = torch.zeros(prob.ndof, dtype=torch.float64, device="cuda:0")
+    x = torch.full((prob.ndof,), 0.0, dtype=torch.float64, device="cuda:0")
+    rc, info = ctx.gmres_solve([0.2], z, x, restart=5, tol=1e-10)
+    assert rc == 0 and torch.count_nonzero(x) == 0
+    bn = b.copy()
+    bn[1, 5, 5] = np.nan
+    with pytest.raises(SAError) as e:
+        ctx.gmres_solve([0.2], dev(bn), torch.zeros_like(x), restart=5, tol=1e-10)
+    assert e.value.code == n.SA_ENONFINITE
+    with pytest.raises(SAError) as e:
+        ctx.gmres_solve([0.2], dev(b), torch.zeros_like(x), restart=5, tol=1e-10, use_precond=True)
+    assert e.value.code == n.SA_ESTATE
