@@ -96,6 +96,7 @@ typedef struct {
   double diag_add;         /* added to every block diagonal               */
   double noise_std;        /* std of the seeded N(0,1) noise added         */
   unsigned long long seed; /* Philox4x32-10 key for the noise             */
+  sa_prec factor_prec;     /* SA_F32 (default use) or SA_F64 factors      */
 } sa_precond_opts;
 
 typedef struct {
@@ -150,15 +151,19 @@ int sa_op_apply(sa_ctx *ctx, sa_prec prec, int nrhs, const void *x_dev, void *y_
  *     B_b(s) = P_b J P_b^T + diag_add I + noise_std E_b - s I,
  * E_b seeded standard-normal (Philox4x32-10), P_b the restriction to the
  * block's DOFs.  Blocks are extracted by coloured probing with the FP64
- * operator and factored (LU with partial pivoting) in FP32, all blocks of
- * all shifts in one launch.  Grid sizes must be divisible by the block
- * size; nb = nv*bx*by*bz <= 128.  Errors: SA_ESTATE, SA_EINVAL,
- * SA_ENOMEM, SA_ESINGULAR (an exactly zero pivot). */
+ * operator, formed in FP64 (unshifted blocks plus noise are kept in FP64 on
+ * the device), rounded once to the factor precision and factored (LU with
+ * partial pivoting), all blocks of all shifts in one launch.  Every axis
+ * must be divisible by its block size, and along a periodic axis the block
+ * count must be divisible by the probe colour count 1 + ceil(3/b);
+ * nb = nv*bx*by*bz <= 128.  Errors: SA_ESTATE, SA_EINVAL, SA_ENOMEM,
+ * SA_ESINGULAR (an exactly zero pivot; the factors are then unusable). */
 int sa_precond_setup(sa_ctx *ctx, const sa_precond_opts *opts, int nshift,
                      const double *shifts_host);
 
 /* z = P blockdiag(B_b(shift ishift))^{-1} r for nrhs vectors (double for
- * SA_F64, float for SA_F32; the factors are FP32).  Errors: SA_ESTATE
+ * SA_F64, float for SA_F32), computed in the factor precision.  Wall
+ * entries of r are ignored and those of z are 0.  Errors: SA_ESTATE
  * before setup, SA_EINVAL. */
 int sa_precond_apply(sa_ctx *ctx, sa_prec prec, int ishift, int nrhs, const void *r_dev,
                      void *z_dev);

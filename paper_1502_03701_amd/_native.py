@@ -50,7 +50,7 @@ class GmresInfo(C.Structure):
 
 class PrecondOpts(C.Structure):
     _fields_ = [("bx", C.c_int), ("by", C.c_int), ("bz", C.c_int), ("diag_add", C.c_double),
-                ("noise_std", C.c_double), ("seed", C.c_ulonglong)]
+                ("noise_std", C.c_double), ("seed", C.c_ulonglong), ("factor_prec", C.c_int)]
 
 
 class EigOpts(C.Structure):
@@ -185,8 +185,9 @@ class Context:
         _check_dev(y, x.dtype, nrhs * self.ndof)
         return self._err(self.lib.sa_op_apply(self.h, prec, nrhs, _ptr(x), _ptr(y), float(shift)))
 
-    def precond_setup(self, shifts, bx=4, by=4, bz=1, diag_add=0.1, noise_std=0.01, seed=3):
-        o = PrecondOpts(bx, by, bz, diag_add, noise_std, seed)
+    def precond_setup(self, shifts, bx=4, by=4, bz=1, diag_add=0.1, noise_std=0.01, seed=3,
+                      factor_prec=SA_F32):
+        o = PrecondOpts(bx, by, bz, diag_add, noise_std, seed, factor_prec)
         arr = (C.c_double * len(shifts))(*shifts)
         return self._err(self.lib.sa_precond_setup(self.h, C.byref(o), len(shifts), arr))
 

@@ -1,25 +1,406 @@
-// Block-Jacobi preconditioner (placeholder until the batched kernels land).
+// Block-Jacobi preconditioner (Section "Preconditioning"): local dense blocks
+// of the operator assembled from operator calls, factored once, applied in
+// every GMRES step.
+//
+//  * Extraction by coloured probing: blocks of one colour are more than the
+//    stencil reach (3 cells) apart along some axis, so one product J e with
+//    e = sum over those blocks of unit vector l gives column l of all of
+//    them.  The products run through the FP64 operator kernel, many probes
+//    per launch.
+//  * Block b of shift s is B_b + diag_add I + noise_std E_b - s I with E_b
+//    seeded standard normals (Philox4x32-10 + Box-Muller, one per entry),
+//    kept in FP64; the factor kernel rounds once to the factor precision.
+//  * One workgroup per (shift, block) factors a block in LDS by LU with
+//    partial pivoting and stores L\U column-major plus the row permutation.
+//  * The apply gathers r_b from the struct-of-arrays vector, solves
+//    L U z = P r with one wavefront per block (a lane per row, columns read
+//    coalesced), and scatters z back; wall DOFs give 0.
+#include <cmath>
+#include <vector>
+
 #include "sa_runtime.h"
 
 namespace sa {
+namespace {
+
+struct BLayout {
+  int nv, nx, ny, nz;
+  int bx, by, bz;
+  int nbx, nby, nbz;
+  int cells, nb;
+  long long nblocks, npts;
+  int bcy;
+};
+
+// flat DOF index of local DOF l of block b; -1 for a wall DOF
+__device__ __forceinline__ long long block_dof(const BLayout& L, long long b, int l, bool& wall) {
+  const int ib = (int)(b % L.nbx);
+  const int jb = (int)((b / L.nbx) % L.nby);
+  const int kb = (int)(b / ((long long)L.nbx * L.nby));
+  const int var = l / L.cells;
+  const int cell = l % L.cells;
+  const int cx = cell % L.bx;
+  const int cy = (cell / L.bx) % L.by;
+  const int cz = cell / (L.bx * L.by);
+  const int i = ib * L.bx + cx, j = jb * L.by + cy, k = kb * L.bz + cz;
+  wall = L.bcy == 1 && (j == 0 || j == L.ny - 1);
+  return (((long long)var * L.nz + k) * L.ny + j) * L.nx + i;
+}
+
+// e[r][dof(b, l0 + r)] = 1 for blocks b of colour `col`, r < nprobe
+__global__ void probe_fill_kernel(BLayout L, double* __restrict__ e, long long n, int col, int cx, int cy,
+                                  int cz, int l0, int nprobe) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= L.nblocks * nprobe) return;
+  const long long b = t % L.nblocks;
+  const int r = (int)(t / L.nblocks);
+  const int ib = (int)(b % L.nbx);
+  const int jb = (int)((b / L.nbx) % L.nby);
+  const int kb = (int)(b / ((long long)L.nbx * L.nby));
+  const int c = ((kb % cz) * cy + (jb % cy)) * cx + (ib % cx);
+  if (c != col) return;
+  bool wall;
+  const long long d = block_dof(L, b, l0 + r, wall);
+  e[(long long)r * n + d] = 1.0;
+}
+
+// B[b][l0 + r][row] = y[r][dof(b, row)] for blocks of colour col (column-major blocks)
+__global__ void probe_extract_kernel(BLayout L, const double* __restrict__ y, long long n, double* __restrict__ B,
+                                     int col, int cx, int cy, int cz, int l0, int nprobe) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long per = (long long)L.nb * nprobe;
+  if (t >= L.nblocks * per) return;
+  const long long b = t / per;
+  const int rem = (int)(t % per);
+  const int r = rem / L.nb;
+  const int row = rem % L.nb;
+  const int ib = (int)(b % L.nbx);
+  const int jb = (int)((b / L.nbx) % L.nby);
+  const int kb = (int)(b / ((long long)L.nbx * L.nby));
+  const int c = ((kb % cz) * cy + (jb % cy)) * cx + (ib % cx);
+  if (c != col) return;
+  bool wall;
+  const long long d = block_dof(L, b, row, wall);
+  B[(b * L.nb + (l0 + r)) * L.nb + row] = y[(long long)r * n + d];
+}
+
+// --- Philox4x32-10 (Salmon et al. 2011) ---
+__device__ __forceinline__ void philox(unsigned c[4], unsigned k0, unsigned k1) {
+  const unsigned M0 = 0xD2511F53u, M1 = 0xCD9E8D57u, W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += W0;
+      k1 += W1;
+    }
+    const unsigned long long p0 = (unsigned long long)M0 * c[0];
+    const unsigned long long p1 = (unsigned long long)M1 * c[2];
+    const unsigned hi0 = (unsigned)(p0 >> 32), lo0 = (unsigned)p0;
+    const unsigned hi1 = (unsigned)(p1 >> 32), lo1 = (unsigned)p1;
+    const unsigned n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+  }
+}
+
+__device__ __forceinline__ double noise_entry(unsigned long long seed, long long b, int idx) {
+  unsigned c[4] = {(unsigned)idx, (unsigned)((unsigned long long)b & 0xffffffffu),
+                   (unsigned)((unsigned long long)b >> 32), 0u};
+  philox(c, (unsigned)(seed & 0xffffffffu), (unsigned)(seed >> 32));
+  const unsigned long long a = ((unsigned long long)c[0] | ((unsigned long long)c[1] << 32)) >> 11;
+  const unsigned long long bb = ((unsigned long long)c[2] | ((unsigned long long)c[3] << 32)) >> 11;
+  const double u1 = ((double)a + 1.0) * 0x1.0p-53;
+  const double u2 = (double)bb * 0x1.0p-53;
+  return sqrt(-2.0 * log(u1)) * cos(2.0 * M_PI * u2);
+}
+
+// B[b] += noise_std * E_b   (E_b[r][c] at column-major position c*nb + r)
+__global__ void add_noise_kernel(BLayout L, double* __restrict__ B, double noise_std, unsigned long long seed) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long per = (long long)L.nb * L.nb;
+  if (t >= L.nblocks * per) return;
+  const long long b = t / per;
+  const int e = (int)(t % per);
+  const int col = e / L.nb, row = e % L.nb;
+  B[t] += noise_std * noise_entry(seed, b, row * L.nb + col);
+}
+
+// Factor B_b + (diag_add - shift_s) I.  One workgroup per (shift, block).
+template <typename F>
+__global__ void __launch_bounds__(256) lu_kernel(BLayout L, const double* __restrict__ B, const double* __restrict__ shifts,
+                                                 double diag_add, F* __restrict__ LU, int* __restrict__ perm,
+                                                 int* __restrict__ singular) {
+  extern __shared__ unsigned char smem[];
+  F* A = reinterpret_cast<F*>(smem);            // nb x nb column-major
+  __shared__ int s_perm[128];
+  __shared__ F s_redv[256];
+  __shared__ int s_redi[256];
+  __shared__ int s_piv;
+  const int nb = L.nb;
+  const long long b = blockIdx.x;
+  const int s = blockIdx.y;
+  const double dshift = diag_add - shifts[s];
+  const double* Bb = B + b * nb * nb;
+  for (int t = threadIdx.x; t < nb * nb; t += blockDim.x) {
+    const int col = t / nb, row = t % nb;
+    double v = Bb[t];
+    if (row == col) v += dshift;
+    A[t] = (F)v;
+  }
+  for (int t = threadIdx.x; t < nb; t += blockDim.x) s_perm[t] = t;
+  __syncthreads();
+  for (int k = 0; k < nb; ++k) {
+    // pivot: argmax |A[i][k]|, i >= k (first maximum)
+    F best = F(-1);
+    int bi = k;
+    for (int i = k + threadIdx.x; i < nb; i += blockDim.x) {
+      const F v = fabs(A[k * nb + i]);
+      if (v > best) {
+        best = v;
+        bi = i;
+      }
+    }
+    s_redv[threadIdx.x] = best;
+    s_redi[threadIdx.x] = bi;
+    __syncthreads();
+    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+      if (threadIdx.x < off) {
+        const F v2 = s_redv[threadIdx.x + off];
+        const int i2 = s_redi[threadIdx.x + off];
+        if (v2 > s_redv[threadIdx.x] || (v2 == s_redv[threadIdx.x] && i2 < s_redi[threadIdx.x])) {
+          s_redv[threadIdx.x] = v2;
+          s_redi[threadIdx.x] = i2;
+        }
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      s_piv = s_redi[0];
+      if (!(s_redv[0] > F(0))) atomicOr(singular, 1);
+    }
+    __syncthreads();
+    const int p = s_piv;
+    if (p != k) {
+      for (int c = threadIdx.x; c < nb; c += blockDim.x) {
+        const F t1 = A[c * nb + k];
+        A[c * nb + k] = A[c * nb + p];
+        A[c * nb + p] = t1;
+      }
+      if (threadIdx.x == 0) {
+        const int t2 = s_perm[k];
+        s_perm[k] = s_perm[p];
+        s_perm[p] = t2;
+      }
+    }
+    __syncthreads();
+    const F piv = A[k * nb + k];
+    const F ipiv = piv != F(0) ? F(1) / piv : F(0);
+    for (int i = k + 1 + threadIdx.x; i < nb; i += blockDim.x) A[k * nb + i] *= ipiv;
+    __syncthreads();
+    // trailing update A[i][c] -= A[i][k] A[k][c], i, c > k
+    const int rem = nb - k - 1;
+    for (int t = threadIdx.x; t < rem * rem; t += blockDim.x) {
+      const int c = k + 1 + t / rem, i = k + 1 + t % rem;
+      A[c * nb + i] -= A[k * nb + i] * A[c * nb + k];
+    }
+    __syncthreads();
+  }
+  F* out = LU + ((long long)s * L.nblocks + b) * nb * nb;
+  for (int t = threadIdx.x; t < nb * nb; t += blockDim.x) out[t] = A[t];
+  int* pout = perm + ((long long)s * L.nblocks + b) * nb;
+  for (int t = threadIdx.x; t < nb; t += blockDim.x) pout[t] = s_perm[t];
+}
+
+// z_b = U^{-1} L^{-1} (P r_b) for one block per 64-lane workgroup; rows lane, lane+64
+template <typename F, typename R>
+__global__ void __launch_bounds__(64) apply_kernel(BLayout L, const F* __restrict__ LU, const int* __restrict__ perm,
+                                                   int shift, const R* __restrict__ r, R* __restrict__ z, long long n,
+                                                   const int* __restrict__ active) {
+  if (active && !*active) return;
+  __shared__ F sr[128];
+  const int nb = L.nb;
+  const long long b = blockIdx.x;
+  const int rhs = blockIdx.y;
+  const int lane = threadIdx.x;
+  const R* rr = r + (long long)rhs * n;
+  R* zz = z + (long long)rhs * n;
+  for (int l = lane; l < nb; l += 64) {
+    bool wall;
+    const long long d = block_dof(L, b, l, wall);
+    sr[l] = wall ? F(0) : (F)rr[d];
+  }
+  __syncthreads();
+  const int* pb = perm + ((long long)shift * L.nblocks + b) * nb;
+  const F* A = LU + ((long long)shift * L.nblocks + b) * nb * nb;
+  F x0 = F(0), x1 = F(0);
+  if (lane < nb) x0 = sr[pb[lane]];
+  if (lane + 64 < nb) x1 = sr[pb[lane + 64]];
+  // forward: unit lower triangular
+  for (int j = 0; j < nb; ++j) {
+    const F yj = j < 64 ? __shfl(x0, j, 64) : __shfl(x1, j - 64, 64);
+    const F* col = A + (long long)j * nb;
+    if (lane > j && lane < nb) x0 -= col[lane] * yj;
+    if (lane + 64 > j && lane + 64 < nb) x1 -= col[lane + 64] * yj;
+  }
+  // backward: upper triangular
+  for (int j = nb - 1; j >= 0; --j) {
+    const F* col = A + (long long)j * nb;
+    F zj = j < 64 ? __shfl(x0, j, 64) : __shfl(x1, j - 64, 64);
+    zj = zj / col[j];
+    if (lane == j) x0 = zj;
+    if (lane + 64 == j) x1 = zj;
+    if (lane < j) x0 -= col[lane] * zj;
+    if (lane + 64 < j) x1 -= col[lane + 64] * zj;
+  }
+  for (int l = lane; l < nb; l += 64) {
+    bool wall;
+    const long long d = block_dof(L, b, l, wall);
+    const F v = l < 64 ? x0 : x1;
+    zz[d] = wall ? R(0) : (R)v;
+  }
+}
+
+BLayout layout_of(const Ctx* c) {
+  BLayout L{};
+  L.nv = c->nv;
+  L.nx = c->op.nx;
+  L.ny = c->op.ny;
+  L.nz = c->op.nz;
+  L.bx = c->pc_bx;
+  L.by = c->pc_by;
+  L.bz = c->pc_bz;
+  L.nbx = L.nx / L.bx;
+  L.nby = L.ny / L.by;
+  L.nbz = L.nz / L.bz;
+  L.cells = L.bx * L.by * L.bz;
+  L.nb = L.nv * L.cells;
+  L.nblocks = (long long)L.nbx * L.nby * L.nbz;
+  L.npts = c->op.npts;
+  L.bcy = c->op.bcy;
+  return L;
+}
+
+int colours(int nblk, int width, bool periodic, int ndim_ok) {
+  if (!ndim_ok || nblk == 1) return 1;
+  int cnum = 1 + (3 + width - 1) / width;
+  if (cnum > nblk) cnum = nblk;
+  if (periodic && nblk % cnum) return -1;
+  return cnum;
+}
+
+inline unsigned blocks_for(long long n, int threads) { return (unsigned)((n + threads - 1) / threads); }
+
+}  // namespace
+
 template <typename R>
 hipError_t precond_apply(Ctx* c, int ishift, int nrhs, const R* r, R* z, const int* active) {
-  (void)c; (void)ishift; (void)nrhs; (void)r; (void)z; (void)active;
-  return hipErrorNotSupported;
+  BLayout L = layout_of(c);
+  dim3 grid((unsigned)L.nblocks, (unsigned)nrhs);
+  if (c->pc_f64)
+    apply_kernel<double, R><<<grid, 64, 0, c->stream>>>(L, (const double*)c->pc_lu, c->pc_perm, ishift, r, z, c->n,
+                                                        active);
+  else
+    apply_kernel<float, R><<<grid, 64, 0, c->stream>>>(L, (const float*)c->pc_lu, c->pc_perm, ishift, r, z, c->n,
+                                                       active);
+  return hipGetLastError();
 }
 template hipError_t precond_apply<double>(Ctx*, int, int, const double*, double*, const int*);
 template hipError_t precond_apply<float>(Ctx*, int, int, const float*, float*, const int*);
+
 }  // namespace sa
 
-extern "C" {
-int sa_precond_setup(sa_ctx* c, const sa_precond_opts*, int, const double*) {
-  return c ? c->fail(SA_ESTATE, "sa_precond_setup: not available") : SA_EINVAL;
+using namespace sa;
+
+extern "C" int sa_precond_setup(sa_ctx* c, const sa_precond_opts* o, int nshift, const double* shifts_host) {
+  if (!c) return SA_EINVAL;
+  if (!c->has_base) return c->fail(SA_ESTATE, "sa_precond_setup: call sa_base_set first");
+  if (!o || !shifts_host || nshift < 1) return c->fail(SA_EINVAL, "sa_precond_setup: null argument or nshift < 1");
+  const int bz = c->op.ndim == 2 ? 1 : o->bz;
+  if (o->bx < 1 || o->by < 1 || bz < 1) return c->fail(SA_EINVAL, "sa_precond_setup: bad block size");
+  if (c->op.nx % o->bx || c->op.ny % o->by || c->op.nz % bz)
+    return c->fail(SA_EINVAL, "sa_precond_setup: grid not divisible by the block size");
+  if (o->factor_prec != SA_F32 && o->factor_prec != SA_F64)
+    return c->fail(SA_EINVAL, "sa_precond_setup: factor precision must be SA_F32 or SA_F64");
+  c->has_precond = false;
+  c->pc_bx = o->bx;
+  c->pc_by = o->by;
+  c->pc_bz = bz;
+  BLayout L = layout_of(c);
+  if (L.nb > 128) return c->fail(SA_EINVAL, "sa_precond_setup: block order %d exceeds 128", L.nb);
+  if (o->factor_prec == SA_F64 && L.nb > 90)
+    return c->fail(SA_EINVAL, "sa_precond_setup: FP64 factors need block order <= 90");
+  const int cx = colours(L.nbx, L.bx, true, 1);
+  const int cy = colours(L.nby, L.by, c->op.bcy == 0, 1);
+  const int cz = colours(L.nbz, L.bz, true, c->op.ndim == 3);
+  if (cx < 0 || cy < 0 || cz < 0)
+    return c->fail(SA_EINVAL, "sa_precond_setup: periodic block count not divisible by the probe colour count");
+  hipStream_t s = c->stream;
+  const long long n = c->n;
+  const size_t bbytes = sizeof(double) * (size_t)L.nblocks * L.nb * L.nb;
+  double* B = (double*)c->buffer("pc_B", bbytes);
+  double* sh = (double*)c->buffer("pc_shifts", sizeof(double) * nshift, false);
+  int* flag = (int*)c->buffer("flag", sizeof(int));
+  const size_t fsz = o->factor_prec == SA_F64 ? sizeof(double) : sizeof(float);
+  void* LU = c->buffer("pc_LU", fsz * (size_t)nshift * L.nblocks * L.nb * L.nb, false);
+  int* perm = (int*)c->buffer("pc_perm", sizeof(int) * (size_t)nshift * L.nblocks * L.nb, false);
+  const int batch = L.nb < 16 ? L.nb : 16;
+  double* E = (double*)c->buffer("pc_probe", sizeof(double) * n * batch, false);
+  double* Y = (double*)c->buffer("pc_resp", sizeof(double) * n * batch, false);
+  if (!B || !sh || !flag || !LU || !perm || !E || !Y) return c->fail(SA_ENOMEM, "sa_precond_setup: out of device memory");
+  hipMemsetAsync(B, 0, bbytes, s);
+  hipMemcpyAsync(sh, shifts_host, sizeof(double) * nshift, hipMemcpyHostToDevice, s);
+  const int ncol = cx * cy * cz;
+  for (int col = 0; col < ncol; ++col) {
+    for (int l0 = 0; l0 < L.nb; l0 += batch) {
+      const int np = std::min(batch, L.nb - l0);
+      hipMemsetAsync(E, 0, sizeof(double) * n * np, s);
+      probe_fill_kernel<<<blocks_for(L.nblocks * np, 256), 256, 0, s>>>(L, E, n, col, cx, cy, cz, l0, np);
+      hipError_t e = launch_jv<double>(c->op, c->base64, E, Y, np, 0.0, nullptr, s);
+      if (e != hipSuccess) return c->hip_fail(e, "sa_precond_setup probe");
+      probe_extract_kernel<<<blocks_for(L.nblocks * L.nb * np, 256), 256, 0, s>>>(L, Y, n, B, col, cx, cy, cz, l0,
+                                                                                 np);
+    }
+  }
+  if (o->noise_std != 0.0)
+    add_noise_kernel<<<blocks_for(L.nblocks * L.nb * L.nb, 256), 256, 0, s>>>(L, B, o->noise_std, o->seed);
+  hipMemsetAsync(flag, 0, sizeof(int), s);
+  dim3 grid((unsigned)L.nblocks, (unsigned)nshift);
+  const size_t lds = fsz * L.nb * L.nb;
+  if (o->factor_prec == SA_F64)
+    lu_kernel<double><<<grid, 256, lds, s>>>(L, B, sh, o->diag_add, (double*)LU, perm, flag);
+  else
+    lu_kernel<float><<<grid, 256, lds, s>>>(L, B, sh, o->diag_add, (float*)LU, perm, flag);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return c->hip_fail(e, "sa_precond_setup factor");
+  int hflag = 0;
+  hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s);
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return c->hip_fail(e, "sa_precond_setup sync");
+  if (hflag) return c->fail(SA_ESINGULAR, "sa_precond_setup: zero pivot in a block");
+  c->pc_lu = LU;
+  c->pc_perm = perm;
+  c->pc_f64 = o->factor_prec == SA_F64;
+  c->pc_nshift = nshift;
+  c->pc_nb = L.nb;
+  c->pc_nblocks = L.nblocks;
+  c->has_precond = true;
+  return SA_OK;
 }
-int sa_precond_apply(sa_ctx* c, sa_prec, int, int, const void*, void*) {
-  return c ? c->fail(SA_ESTATE, "sa_precond_apply: not available") : SA_EINVAL;
-}
-int sa_arnoldi_eigs(sa_ctx* const* ctxs, int, const sa_eig_opts*, const double* const*, sa_eig_result*) {
-  (void)ctxs;
-  return SA_ESTATE;
-}
+
+extern "C" int sa_precond_apply(sa_ctx* c, sa_prec prec, int ishift, int nrhs, const void* r_dev, void* z_dev) {
+  if (!c) return SA_EINVAL;
+  if (!c->has_precond) return c->fail(SA_ESTATE, "sa_precond_apply: call sa_precond_setup first");
+  if (ishift < 0 || ishift >= c->pc_nshift || nrhs < 1 || !r_dev || !z_dev)
+    return c->fail(SA_EINVAL, "sa_precond_apply: bad shift index, nrhs or pointer");
+  hipError_t e;
+  if (prec == SA_F64)
+    e = precond_apply<double>(c, ishift, nrhs, (const double*)r_dev, (double*)z_dev, nullptr);
+  else if (prec == SA_F32)
+    e = precond_apply<float>(c, ishift, nrhs, (const float*)r_dev, (float*)z_dev, nullptr);
+  else
+    return c->fail(SA_EINVAL, "sa_precond_apply: precision must be SA_F64 or SA_F32");
+  if (e != hipSuccess) return c->hip_fail(e, "sa_precond_apply");
+  return SA_OK;
 }

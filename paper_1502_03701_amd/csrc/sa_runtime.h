@@ -37,9 +37,9 @@ struct Ctx {
   int pc_nb = 0;           // block order
   long long pc_nblocks = 0;
   int pc_bx = 0, pc_by = 0, pc_bz = 0;
-  float* pc_lu = nullptr;  // [nshift][nblocks][nb][nb] LU factors (row-major)
-  int* pc_piv = nullptr;   // [nshift][nblocks][nb]
-  int* pc_dof = nullptr;   // [nblocks][nb] flat DOF index (wall DOFs -> -1)
+  void* pc_lu = nullptr;   // [nshift][nblocks][nb x nb] L\U factors, column-major
+  int* pc_perm = nullptr;  // [nshift][nblocks][nb] row permutation of the pivoting
+  bool pc_f64 = false;     // factor precision
 
   int fail(int code, const char* fmt, ...);
   int hip_fail(hipError_t e, const char* where);
