@@ -63,7 +63,7 @@ __global__ void __launch_bounds__(RED_THREADS) multidot_kernel(long long n, cons
   block_sum_cols<MAXC>(acc, nc, partial + (long long)blockIdx.x * ldp + c0);
 }
 
-// w_new = w - sum_c V[c] h[c]; writes w_new to wout (may alias w).  If dot:
+// w_new = w + hsign * sum_c V[c] h[c]; writes w_new to wout (may alias w).  If dot:
 // partial dots V^T w_new, else partial ||w_new||^2 in column 0.
 template <typename R, int MAXC>
 __global__ void __launch_bounds__(RED_THREADS) update_dot_kernel(
@@ -85,7 +85,7 @@ __global__ void __launch_bounds__(RED_THREADS) update_dot_kernel(
     for (int c = 0; c < MAXC; ++c) {
       if (c < ncol) {
         vc[c] = (double)V[(long long)c * ldv + i];
-        s -= vc[c] * hc[c];
+        s += vc[c] * hc[c];
       }
     }
     const R wn = (R)s;

@@ -29,6 +29,15 @@ struct OpParams {
 // Jv: y = (J - shift I) x for nrhs vectors.  base holds the nv base fields
 // followed by three pointwise fields T0, dT/dp, dT/ds (all with walls).
 template <typename R>
+hipError_t launch_jv_tiled(const OpParams& p, const R* base, const R* x, R* y, int nrhs, R shift,
+                           const int* active, hipStream_t s);
+// Reference kernel (one thread per point, stencil taps straight from memory).
+template <typename R>
+hipError_t launch_jv_direct(const OpParams& p, const R* base, const R* x, R* y, int nrhs, R shift,
+                            const int* active, hipStream_t s);
+// Operator dispatch: the tiled kernel, or the reference kernel when the
+// process was started with SA_JV_REFERENCE=1 (used to cross-check tilings).
+template <typename R>
 hipError_t launch_jv(const OpParams& p, const R* base, const R* x, R* y, int nrhs, R shift,
                      const int* active, hipStream_t s);
 
