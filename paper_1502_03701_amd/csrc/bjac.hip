@@ -357,7 +357,7 @@ extern "C" int sa_precond_setup(sa_ctx* c, const sa_precond_opts* o, int nshift,
       const int np = std::min(batch, L.nb - l0);
       hipMemsetAsync(E, 0, sizeof(double) * n * np, s);
       probe_fill_kernel<<<blocks_for(L.nblocks * np, 256), 256, 0, s>>>(L, E, n, col, cx, cy, cz, l0, np);
-      hipError_t e = launch_jv<double>(c->op, c->base64, E, Y, np, 0.0, nullptr, s);
+      hipError_t e = c->jv<double>(E, Y, np, 0.0, nullptr);
       if (e != hipSuccess) return c->hip_fail(e, "sa_precond_setup probe");
       probe_extract_kernel<<<blocks_for(L.nblocks * L.nb * np, 256), 256, 0, s>>>(L, Y, n, B, col, cx, cy, cz, l0,
                                                                                  np);

@@ -33,7 +33,7 @@ int cayley_apply(Iram& w, const double* v, double* out) {
   Ctx* c = w.c;
   hipStream_t s = c->stream;
   const sa_eig_opts& o = *w.o;
-  hipError_t e = launch_jv<double>(c->op, c->base64, v, w.tb, 1, o.mu, nullptr, s);
+  hipError_t e = c->jv<double>(v, w.tb, 1, o.mu, nullptr);
   if (e != hipSuccess) return c->hip_fail(e, "iram jv");
   w.bl.fill(w.n, out, 0.0, s);
   sa_gmres_info info{};
@@ -152,8 +152,8 @@ int run_one(Ctx* c, const sa_eig_opts& o, const double* v0, sa_eig_result* res) 
     double* Ji = w.T + n;
     double* out = (double*)c->buffer("iramR", sizeof(double) * 2);
     for (int i = 0; i < o.nev; ++i) {
-      launch_jv<double>(c->op, c->base64, evr + (long long)i * n, Jr, 1, 0.0, nullptr, s);
-      launch_jv<double>(c->op, c->base64, evi + (long long)i * n, Ji, 1, 0.0, nullptr, s);
+      c->jv<double>(evr + (long long)i * n, Jr, 1, 0.0, nullptr);
+      c->jv<double>(evi + (long long)i * n, Ji, 1, 0.0, nullptr);
       eig_residual(n, Jr, Ji, evr + (long long)i * n, evi + (long long)i * n, lr[i], li[i], w.bl.partial,
                    out, s);
       double hr[2];

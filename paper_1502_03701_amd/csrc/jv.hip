@@ -18,6 +18,7 @@
 // temperature perturbation T' = T_p p' + T_s s' is formed pointwise before
 // it is differentiated; base-state derivatives are the discrete ones.
 #include <cstdlib>
+#include <cstring>
 
 #include "jv_common.h"
 
@@ -242,24 +243,29 @@ hipError_t launch_base_derive(const OpParams& p, double* base, float* base32, in
 
 namespace sa {
 
-static bool use_reference_kernel() {
-  static const bool ref = [] {
-    const char* e = std::getenv("SA_JV_REFERENCE");
-    return e && e[0] == '1';
+// 0: tiled with precomputed base data, 1: tiled on the fly, 2: reference
+static int kernel_choice() {
+  static const int k = [] {
+    const char* e = std::getenv("SA_JV_KERNEL");
+    if (!e) return 0;
+    if (std::strcmp(e, "onthefly") == 0) return 1;
+    if (std::strcmp(e, "reference") == 0) return 2;
+    return 0;
   }();
-  return ref;
+  return k;
 }
 
 template <typename R>
-hipError_t launch_jv(const OpParams& p, const R* base, const R* x, R* y, int nrhs, R shift,
+hipError_t launch_jv(const OpParams& p, const R* base, const R* bdata, const R* x, R* y, int nrhs, R shift,
                      const int* active, hipStream_t s) {
-  if (use_reference_kernel()) return launch_jv_direct<R>(p, base, x, y, nrhs, shift, active, s);
-  return launch_jv_tiled<R>(p, base, x, y, nrhs, shift, active, s);
+  const int k = kernel_choice();
+  if (k == 2) return launch_jv_direct<R>(p, base, x, y, nrhs, shift, active, s);
+  return launch_jv_tiled<R>(p, base, x, y, nrhs, shift, active, k == 1 ? nullptr : bdata, s);
 }
 
-template hipError_t launch_jv<double>(const OpParams&, const double*, const double*, double*, int, double,
-                                      const int*, hipStream_t);
-template hipError_t launch_jv<float>(const OpParams&, const float*, const float*, float*, int, float,
-                                     const int*, hipStream_t);
+template hipError_t launch_jv<double>(const OpParams&, const double*, const double*, const double*, double*,
+                                      int, double, const int*, hipStream_t);
+template hipError_t launch_jv<float>(const OpParams&, const float*, const float*, const float*, float*, int,
+                                     float, const int*, hipStream_t);
 
 }  // namespace sa

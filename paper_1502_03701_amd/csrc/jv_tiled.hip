@@ -29,30 +29,33 @@ constexpr int PH = TY + 6;
 constexpr int NT = TX * TY;
 constexpr int NZC = 8;       // z planes per workgroup
 
-// LDS plane field slots: 0..ND+2 perturbation (p, u.., s, T'), then base.
-template <int ND>
-struct Slots {
-  static constexpr int NF = ND + 3;
-  static constexpr int PERT = 0;
-  static constexpr int BASE = NF;
-};
-
 template <typename R>
 __device__ __forceinline__ int wrap(int a, int n) {
   return a < 0 ? a + n : (a >= n ? a - n : a);
 }
 
-template <typename R, int ND>
+// MODE_FULL: perturbation and base stencils every call.
+// MODE_BASE: base stencils only; writes the per-point base data (bdata).
+// MODE_PERT: perturbation stencils only; base data read from bdata.
+constexpr int MODE_FULL = 0, MODE_BASE = 1, MODE_PERT = 2;
+
+template <int ND>
+constexpr int bdata_count() { return 1 + ND + 1 + ND + ND * ND + ND + ND + ND + 1; }
+
+template <typename R, int ND, int MODE>
 __global__ void __launch_bounds__(NT) jv_tiled_kernel(OpParams op, const R* __restrict__ base,
                                                       const R* __restrict__ x, R* __restrict__ y, R shift,
-                                                      const int* __restrict__ active) {
+                                                      const int* __restrict__ active, R* __restrict__ bdata) {
   if (active && !*active) return;
   constexpr int NF = ND + 3;
-  constexpr int NPL = 2 * NF;                       // staged plane fields
+  constexpr int NSET = MODE == MODE_FULL ? 2 : 1;
+  constexpr int NPL = NSET * NF;                    // staged plane fields
   __shared__ R sP[NPL][PH][PW];
   // x-staged: [set][0: D_y v + D_z w, 1: D_z u][TY][PW]; y-staged: [set][0: D_x u + D_z w, 1: D_z v][PH][TX]
-  __shared__ R sX[2][2][TY][PW];
-  __shared__ R sY[2][2][PH][TX];
+  __shared__ R sX[NSET][2][TY][PW];
+  __shared__ R sY[NSET][2][PH][TX];
+  // set s is the perturbation unless it is the base set
+  auto is_pert = [](int s) -> bool { return MODE == MODE_PERT || (MODE == MODE_FULL && s == 0); };
 
   const int tid = threadIdx.x;
   const int ti = tid % TX, tj = tid / TX;
@@ -112,18 +115,17 @@ __global__ void __launch_bounds__(NT) jv_tiled_kernel(OpParams op, const R* __re
       const bool wall = is_wall(gj);
       const long long p = ((long long)k * ny + gj) * nx + gi;
 #pragma unroll
-      for (int f = 0; f < NF; ++f) {
-        sP[Slots<ND>::PERT + f][jj][ii] = loadf(true, f, p, wall);
-        sP[Slots<ND>::BASE + f][jj][ii] = loadf(false, f, p, false);
-      }
+      for (int s = 0; s < NSET; ++s)
+#pragma unroll
+        for (int f = 0; f < NF; ++f) sP[s * NF + f][jj][ii] = loadf(is_pert(s), f, p, is_pert(s) && wall);
     }
     // 2. z-derivatives of the own column (registers)
-    R dz[2][NF], d2z[2][ND + 1];
+    R dz[NSET][NF], d2z[NSET][ND + 1];
     if (ND == 3) {
       const int gi = wrap<R>(i, nx), gj = grow(tj + 3);
       const bool wall = is_wall(gj);
 #pragma unroll
-      for (int s = 0; s < 2; ++s) {
+      for (int s = 0; s < NSET; ++s) {
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
           R a1 = R(0), a2 = R(0);
@@ -131,7 +133,7 @@ __global__ void __launch_bounds__(NT) jv_tiled_kernel(OpParams op, const R* __re
           for (int m = 1; m <= 3; ++m) {
             const long long pp = ((long long)wrap<R>(k + m, nz) * ny + gj) * nx + gi;
             const long long pm = ((long long)wrap<R>(k - m, nz) * ny + gj) * nx + gi;
-            const R vp = loadf(s == 0, f, pp, wall), vm = loadf(s == 0, f, pm, wall);
+            const R vp = loadf(is_pert(s), f, pp, wall), vm = loadf(is_pert(s), f, pm, wall);
             a1 += az.c1[m - 1] * (vp - vm);
             a2 += az.c2[m - 1] * (vp + vm);
           }
@@ -157,15 +159,15 @@ __global__ void __launch_bounds__(NT) jv_tiled_kernel(OpParams op, const R* __re
           const bool wall = is_wall(gj);
           const Axis<R> ay2 = axis_coefs<R>(wall_row_order(gj, ny, op.bcy));
 #pragma unroll
-          for (int s = 0; s < 2; ++s) {
-            const int F0 = s == 0 ? Slots<ND>::PERT : Slots<ND>::BASE;
+          for (int s = 0; s < NSET; ++s) {
+            const int F0 = s * NF;
             R dyv = R(0);
 #pragma unroll
             for (int m = 1; m <= 3; ++m)
               dyv += ay2.c1[m - 1] * (sP[F0 + 2][tj2 + 3 + m][ii] - sP[F0 + 2][tj2 + 3 - m][ii]);
             dyv *= ihy;
-            const R dzw = dz1(s == 0, 3, gi, gj, k, wall);
-            const R dzu = dz1(s == 0, 1, gi, gj, k, wall);
+            const R dzw = dz1(is_pert(s), 3, gi, gj, k, wall);
+            const R dzu = dz1(is_pert(s), 1, gi, gj, k, wall);
             sX[s][0][tj2][ii] = dyv + dzw;
             sX[s][1][tj2][ii] = dzu;
           }
@@ -177,15 +179,15 @@ __global__ void __launch_bounds__(NT) jv_tiled_kernel(OpParams op, const R* __re
           const int gj = grow(jj);
           const bool wall = is_wall(gj);
 #pragma unroll
-          for (int s = 0; s < 2; ++s) {
-            const int F0 = s == 0 ? Slots<ND>::PERT : Slots<ND>::BASE;
+          for (int s = 0; s < NSET; ++s) {
+            const int F0 = s * NF;
             R dxu = R(0);
 #pragma unroll
             for (int m = 1; m <= 3; ++m)
               dxu += ax.c1[m - 1] * (sP[F0 + 1][jj][ti2 + 3 + m] - sP[F0 + 1][jj][ti2 + 3 - m]);
             dxu *= ihx;
-            const R dzw = dz1(s == 0, 3, gi, gj, k, wall);
-            const R dzv = dz1(s == 0, 2, gi, gj, k, wall);
+            const R dzw = dz1(is_pert(s), 3, gi, gj, k, wall);
+            const R dzv = dz1(is_pert(s), 2, gi, gj, k, wall);
             sY[s][0][jj][ti2] = dxu + dzw;
             sY[s][1][jj][ti2] = dzv;
           }
@@ -201,8 +203,8 @@ __global__ void __launch_bounds__(NT) jv_tiled_kernel(OpParams op, const R* __re
           const int gj = grow(tj2 + 3);
           const Axis<R> ay2 = axis_coefs<R>(wall_row_order(gj, ny, op.bcy));
 #pragma unroll
-          for (int s = 0; s < 2; ++s) {
-            const int F0 = s == 0 ? Slots<ND>::PERT : Slots<ND>::BASE;
+          for (int s = 0; s < NSET; ++s) {
+            const int F0 = s * NF;
             R dyv = R(0);
 #pragma unroll
             for (int m = 1; m <= 3; ++m)
@@ -214,8 +216,8 @@ __global__ void __launch_bounds__(NT) jv_tiled_kernel(OpParams op, const R* __re
           const int ti2 = t2 % TX, r = t2 / TX;
           const int jj = r < 3 ? r : TY + r;
 #pragma unroll
-          for (int s = 0; s < 2; ++s) {
-            const int F0 = s == 0 ? Slots<ND>::PERT : Slots<ND>::BASE;
+          for (int s = 0; s < NSET; ++s) {
+            const int F0 = s * NF;
             R dxu = R(0);
 #pragma unroll
             for (int m = 1; m <= 3; ++m)
@@ -226,11 +228,11 @@ __global__ void __launch_bounds__(NT) jv_tiled_kernel(OpParams op, const R* __re
       }
     }
     // 3b. in-plane derivatives of the own point from LDS
-    Pt<R, ND> P[2];
+    Pt<R, ND> P[NSET];
     const int cx = ti + 3, cy = tj + 3;
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      const int F0 = s == 0 ? Slots<ND>::PERT : Slots<ND>::BASE;
+    for (int s = 0; s < NSET; ++s) {
+      const int F0 = s * NF;
 #pragma unroll
       for (int f = 0; f < NF; ++f) {
         const R c0 = sP[F0 + f][cy][cx];
@@ -267,7 +269,7 @@ __global__ void __launch_bounds__(NT) jv_tiled_kernel(OpParams op, const R* __re
     // own staged values
     if (ND == 3) {
 #pragma unroll
-      for (int s = 0; s < 2; ++s) {
+      for (int s = 0; s < NSET; ++s) {
         sX[s][0][tj][cx] = P[s].D[2][1] + P[s].D[3][ND - 1];   // D_y v + D_z w
         sX[s][1][tj][cx] = P[s].D[1][ND - 1];                  // D_z u
         sY[s][0][cy][ti] = P[s].D[1][0] + P[s].D[3][ND - 1];   // D_x u + D_z w
@@ -275,7 +277,7 @@ __global__ void __launch_bounds__(NT) jv_tiled_kernel(OpParams op, const R* __re
       }
     } else {
 #pragma unroll
-      for (int s = 0; s < 2; ++s) {
+      for (int s = 0; s < NSET; ++s) {
         sX[s][0][tj][cx] = P[s].D[2][1];   // D_y v
         sY[s][0][cy][ti] = P[s].D[1][0];   // D_x u
       }
@@ -283,7 +285,7 @@ __global__ void __launch_bounds__(NT) jv_tiled_kernel(OpParams op, const R* __re
     __syncthreads();
     // 4. mixed parts of G
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
+    for (int s = 0; s < NSET; ++s) {
       R gx = R(0), gy = R(0), gz1 = R(0), gz2 = R(0);
 #pragma unroll
       for (int m = 1; m <= 3; ++m) {
@@ -298,18 +300,68 @@ __global__ void __launch_bounds__(NT) jv_tiled_kernel(OpParams op, const R* __re
       P[s].G[1] += gy * ihy;
       if (ND == 3) P[s].G[2] += gz1 * ihx + gz2 * ihy;
     }
-    // 5. pointwise algebra and store
-    if (active_pt) {
-      const long long id = ((long long)k * ny + j) * nx + i;
+    // 5. pointwise algebra and store (or the base data)
+    const long long id = ((long long)k * ny + j) * nx + i;
+    if (MODE == MODE_BASE) {
+      if (inside) {
+        const Pt<R, ND>& b = P[0];
+        int q = 0;
+        auto put = [&](R v) { bdata[(long long)(q++) * npts + id] = v; };
+        put(b.q[0]);
+#pragma unroll
+        for (int a = 0; a < ND; ++a) put(b.q[1 + a]);
+        put(b.q[ND + 2]);
+#pragma unroll
+        for (int a = 0; a < ND; ++a) put(b.D[0][a]);
+#pragma unroll
+        for (int c2 = 0; c2 < ND; ++c2)
+#pragma unroll
+          for (int a = 0; a < ND; ++a) put(b.D[1 + c2][a]);
+#pragma unroll
+        for (int a = 0; a < ND; ++a) put(b.D[ND + 1][a]);
+#pragma unroll
+        for (int a = 0; a < ND; ++a) put(b.D[ND + 2][a]);
+#pragma unroll
+        for (int a = 0; a < ND; ++a) put(b.Lu[a] + b.G[a] * R(1.0 / 3.0));
+        put(b.LT);
+      }
+    } else if (active_pt) {
       R out[ND + 2];
-      tangent_point<R, ND>(P[1], P[0], op, out);
+      if (MODE == MODE_FULL) {
+        tangent_point<R, ND>(P[NSET - 1], P[0], op, out);
+      } else {
+        Pt<R, ND> b;
+        int q = 0;
+        auto get = [&]() -> R { return bdata[(long long)(q++) * npts + id]; };
+        b.q[0] = get();
+#pragma unroll
+        for (int a = 0; a < ND; ++a) b.q[1 + a] = get();
+        b.q[ND + 2] = get();
+        b.q[ND + 1] = R(0);
+#pragma unroll
+        for (int a = 0; a < ND; ++a) b.D[0][a] = get();
+#pragma unroll
+        for (int c2 = 0; c2 < ND; ++c2)
+#pragma unroll
+          for (int a = 0; a < ND; ++a) b.D[1 + c2][a] = get();
+#pragma unroll
+        for (int a = 0; a < ND; ++a) b.D[ND + 1][a] = get();
+#pragma unroll
+        for (int a = 0; a < ND; ++a) b.D[ND + 2][a] = get();
+#pragma unroll
+        for (int a = 0; a < ND; ++a) {
+          b.Lu[a] = get();
+          b.G[a] = R(0);
+        }
+        b.LT = get();
+        tangent_point<R, ND>(b, P[0], op, out);
+      }
 #pragma unroll
       for (int f = 0; f < ND + 2; ++f) {
         const long long o = (long long)f * npts + id;
         y[o] = out[f] - shift * P[0].q[f];
       }
     } else if (inside) {
-      const long long id = ((long long)k * ny + j) * nx + i;
 #pragma unroll
       for (int f = 0; f < ND + 2; ++f) y[(long long)f * npts + id] = R(0);
     }
@@ -318,23 +370,39 @@ __global__ void __launch_bounds__(NT) jv_tiled_kernel(OpParams op, const R* __re
 
 }  // namespace
 
-template <typename R>
-hipError_t launch_jv_tiled(const OpParams& p, const R* base, const R* x, R* y, int nrhs, R shift,
-                           const int* active, hipStream_t s) {
+template <typename R, int MODE>
+static hipError_t launch_mode(const OpParams& p, const R* base, const R* x, R* y, int nrhs, R shift,
+                              const int* active, R* bdata, hipStream_t s) {
   const long long ndof = (long long)(p.ndim + 2) * p.npts;
   dim3 grid((p.nx + TX - 1) / TX, (p.ny + TY - 1) / TY, p.ndim == 3 ? (p.nz + NZC - 1) / NZC : 1);
   for (int r = 0; r < nrhs; ++r) {
+    const R* xr = x ? x + r * ndof : nullptr;
+    R* yr = y ? y + r * ndof : nullptr;
     if (p.ndim == 2)
-      jv_tiled_kernel<R, 2><<<grid, NT, 0, s>>>(p, base, x + r * ndof, y + r * ndof, shift, active);
+      jv_tiled_kernel<R, 2, MODE><<<grid, NT, 0, s>>>(p, base, xr, yr, shift, active, bdata);
     else
-      jv_tiled_kernel<R, 3><<<grid, NT, 0, s>>>(p, base, x + r * ndof, y + r * ndof, shift, active);
+      jv_tiled_kernel<R, 3, MODE><<<grid, NT, 0, s>>>(p, base, xr, yr, shift, active, bdata);
   }
   return hipGetLastError();
 }
 
+int base_data_fields(int ndim) { return ndim == 2 ? bdata_count<2>() : bdata_count<3>(); }
+
+template <typename R>
+hipError_t launch_jv_tiled(const OpParams& p, const R* base, const R* x, R* y, int nrhs, R shift,
+                           const int* active, const R* bdata, hipStream_t s) {
+  if (bdata)
+    return launch_mode<R, MODE_PERT>(p, base, x, y, nrhs, shift, active, const_cast<R*>(bdata), s);
+  return launch_mode<R, MODE_FULL>(p, base, x, y, nrhs, shift, active, nullptr, s);
+}
+
+hipError_t launch_base_data(const OpParams& p, const double* base, double* bdata, hipStream_t s) {
+  return launch_mode<double, MODE_BASE>(p, base, nullptr, nullptr, 1, 0.0, nullptr, bdata, s);
+}
+
 template hipError_t launch_jv_tiled<double>(const OpParams&, const double*, const double*, double*, int,
-                                            double, const int*, hipStream_t);
+                                            double, const int*, const double*, hipStream_t);
 template hipError_t launch_jv_tiled<float>(const OpParams&, const float*, const float*, float*, int, float,
-                                           const int*, hipStream_t);
+                                           const int*, const float*, hipStream_t);
 
 }  // namespace sa

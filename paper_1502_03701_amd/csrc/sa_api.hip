@@ -109,6 +109,10 @@ int sa_base_set(sa_ctx* c, const sa_problem* pb, const double* q0_dev) {
   c->has_precond = false;
   c->base64 = (double*)c->buffer("base64", nf * sizeof(double));
   c->base32 = (float*)c->buffer("base32", nf * sizeof(float));
+  const size_t nbd = (size_t)base_data_fields(op.ndim) * op.npts;
+  c->bdata64 = (double*)c->buffer("bdata64", nbd * sizeof(double));
+  c->bdata32 = (float*)c->buffer("bdata32", nbd * sizeof(float));
+  if (!c->bdata64 || !c->bdata32) return c->fail(SA_ENOMEM, "sa_base_set: out of device memory");
   int* flag = (int*)c->buffer("flag", sizeof(int));
   if (!c->base64 || !c->base32 || !flag) return c->fail(SA_ENOMEM, "sa_base_set: out of device memory");
   hipError_t e = hipMemcpyAsync(c->base64, q0_dev, (size_t)c->n * sizeof(double), hipMemcpyDeviceToDevice,
@@ -122,6 +126,12 @@ int sa_base_set(sa_ctx* c, const sa_problem* pb, const double* q0_dev) {
   e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return c->hip_fail(e, "sa_base_set sync");
   if (hflag) return c->fail(SA_ENONFINITE, "sa_base_set: q0 has NaN/Inf or non-positive pressure");
+  // discrete derivatives of the base state, once per base state
+  e = launch_base_data(op, c->base64, c->bdata64, c->stream);
+  if (e != hipSuccess) return c->hip_fail(e, "sa_base_set base data");
+  cast_d2f((long long)nbd, c->bdata64, c->bdata32, nullptr, c->stream);
+  e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return c->hip_fail(e, "sa_base_set base data sync");
   c->has_base = true;
   return SA_OK;
 }
@@ -132,11 +142,9 @@ int sa_op_apply(sa_ctx* c, sa_prec prec, int nrhs, const void* x_dev, void* y_de
   if (nrhs < 1 || !x_dev || !y_dev) return c->fail(SA_EINVAL, "sa_op_apply: bad nrhs or null pointer");
   hipError_t e;
   if (prec == SA_F64)
-    e = launch_jv<double>(c->op, c->base64, (const double*)x_dev, (double*)y_dev, nrhs, shift, nullptr,
-                          c->stream);
+    e = c->jv<double>((const double*)x_dev, (double*)y_dev, nrhs, shift, nullptr);
   else if (prec == SA_F32)
-    e = launch_jv<float>(c->op, c->base32, (const float*)x_dev, (float*)y_dev, nrhs, (float)shift,
-                         nullptr, c->stream);
+    e = c->jv<float>((const float*)x_dev, (float*)y_dev, nrhs, shift, nullptr);
   else
     return c->fail(SA_EINVAL, "sa_op_apply: precision must be SA_F64 or SA_F32");
   if (e != hipSuccess) return c->hip_fail(e, "sa_op_apply");

@@ -28,17 +28,23 @@ struct OpParams {
 // Kernel launchers (all enqueue on the given stream; no synchronisation).
 // Jv: y = (J - shift I) x for nrhs vectors.  base holds the nv base fields
 // followed by three pointwise fields T0, dT/dp, dT/ds (all with walls).
+// Tiled kernel; with bdata (per-point base-state data from launch_base_data,
+// base_data_fields(ndim) fields) only the perturbation is differentiated.
 template <typename R>
 hipError_t launch_jv_tiled(const OpParams& p, const R* base, const R* x, R* y, int nrhs, R shift,
-                           const int* active, hipStream_t s);
+                           const int* active, const R* bdata, hipStream_t s);
+int base_data_fields(int ndim);
+hipError_t launch_base_data(const OpParams& p, const double* base, double* bdata, hipStream_t s);
 // Reference kernel (one thread per point, stencil taps straight from memory).
 template <typename R>
 hipError_t launch_jv_direct(const OpParams& p, const R* base, const R* x, R* y, int nrhs, R shift,
                             const int* active, hipStream_t s);
-// Operator dispatch: the tiled kernel, or the reference kernel when the
-// process was started with SA_JV_REFERENCE=1 (used to cross-check tilings).
+// Operator dispatch: the tiled kernel with precomputed base data (default),
+// the tiled kernel differentiating the base state every call
+// (SA_JV_KERNEL=onthefly) or the reference kernel (SA_JV_KERNEL=reference);
+// the variable is read once per process and serves to cross-check kernels.
 template <typename R>
-hipError_t launch_jv(const OpParams& p, const R* base, const R* x, R* y, int nrhs, R shift,
+hipError_t launch_jv(const OpParams& p, const R* base, const R* bdata, const R* x, R* y, int nrhs, R shift,
                      const int* active, hipStream_t s);
 
 // Base-state preprocessing: fields T0, T_p, T_s appended after q0 (FP64),

@@ -30,6 +30,12 @@ struct Ctx {
   long long n = 0;
   double* base64 = nullptr;
   float* base32 = nullptr;
+  double* bdata64 = nullptr;   // per-point base-state derivative data
+  float* bdata32 = nullptr;
+
+  // y = (J - shift I) x in precision R on the context's stream
+  template <typename R>
+  hipError_t jv(const R* x, R* y, int nrhs, double shift, const int* active) const;
 
   // block-Jacobi preconditioner
   bool has_precond = false;
@@ -58,6 +64,17 @@ int solve_ir(Ctx* c, const sa_gmres_opts& o, double sigma, const double* b, doub
 template <typename R>
 hipError_t precond_apply(Ctx* c, int ishift, int nrhs, const R* r, R* z, const int* active);
 
+}  // namespace sa
+
+namespace sa {
+template <>
+inline hipError_t Ctx::jv<double>(const double* x, double* y, int nrhs, double shift, const int* active) const {
+  return launch_jv<double>(op, base64, bdata64, x, y, nrhs, shift, active, stream);
+}
+template <>
+inline hipError_t Ctx::jv<float>(const float* x, float* y, int nrhs, double shift, const int* active) const {
+  return launch_jv<float>(op, base32, bdata32, x, y, nrhs, (float)shift, active, stream);
+}
 }  // namespace sa
 
 struct sa_ctx : sa::Ctx {};

@@ -16,13 +16,6 @@
 namespace sa {
 namespace {
 
-template <typename R>
-const R* base_of(Ctx* c);
-template <>
-const double* base_of<double>(Ctx* c) { return c->base64; }
-template <>
-const float* base_of<float>(Ctx* c) { return c->base32; }
-
 hipError_t read_tail(GState* st, GTail& h, hipStream_t s) {
   hipError_t e = hipMemcpyAsync(&h, &st->t, sizeof(GTail), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -46,7 +39,6 @@ int solve_gmres(Ctx* c, const sa_gmres_opts& o, double sigma, const R* b, R* x, 
   bl.partial = (double*)c->buffer("partial", sizeof(double) * RED_BLOCKS * PARTIAL_LD);
   bl.ldp = PARTIAL_LD;
   if (!V || !Z || !st || !bl.partial) return c->fail(SA_ENOMEM, "gmres: out of device memory");
-  const R* base = base_of<R>(c);
   const int* act = &st->t.active;
   *info = sa_gmres_info{};
 
@@ -58,7 +50,7 @@ int solve_gmres(Ctx* c, const sa_gmres_opts& o, double sigma, const R* b, R* x, 
   hipError_t e;
   for (;;) {
     // r = b - (J - sigma I) x  -> V[:,0]
-    e = launch_jv<R>(c->op, base, x, V + n, 1, (R)sigma, nullptr, s);
+    e = c->jv<R>(x, V + n, 1, sigma, nullptr);
     if (e != hipSuccess) return c->hip_fail(e, "gmres residual");
     bl.residual(n, b, V + n, V, &st->t.rnorm2, nullptr, s);
     gstate_cycle_start(st, s);
@@ -95,7 +87,7 @@ int solve_gmres(Ctx* c, const sa_gmres_opts& o, double sigma, const R* b, R* x, 
         if (e != hipSuccess) return c->hip_fail(e, "gmres precond");
         zj = zz;
       }
-      e = launch_jv<R>(c->op, base, zj, w, 1, (R)sigma, act, s);
+      e = c->jv<R>(zj, w, 1, sigma, act);
       if (e != hipSuccess) return c->hip_fail(e, "gmres jv");
       // CGS pass 1: d1 = V[0..j]^T w and ||w||^2
       bl.multidot(n, V, n, j + 2, w, st->d1, false, act, s);
@@ -149,7 +141,7 @@ int solve_ir(Ctx* c, const sa_gmres_opts& o, double sigma, const double* b, doub
   int inner_cycles = 0;
   hipError_t e;
   for (int outer = 0;; ++outer) {
-    e = launch_jv<double>(c->op, c->base64, x, y, 1, sigma, nullptr, s);
+    e = c->jv<double>(x, y, 1, sigma, nullptr);
     if (e != hipSuccess) return c->hip_fail(e, "ir residual");
     bl.residual(n, b, y, r, &st->t.rnorm2, nullptr, s);
     gstate_cycle_start(st, s);  // beta = ||r||, inv = 1/||r||, converged flag
