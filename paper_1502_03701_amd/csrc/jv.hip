@@ -243,13 +243,15 @@ hipError_t launch_base_derive(const OpParams& p, double* base, float* base32, in
 
 namespace sa {
 
-// 0: tiled with precomputed base data, 1: tiled on the fly, 2: reference
+// 0: perturbation-only queue kernel (jv_fast.hip), 1: tiled, base state
+// differentiated on the fly, 2: reference, 3: tiled with precomputed base data
 static int kernel_choice() {
   static const int k = [] {
     const char* e = std::getenv("SA_JV_KERNEL");
     if (!e) return 0;
     if (std::strcmp(e, "onthefly") == 0) return 1;
     if (std::strcmp(e, "reference") == 0) return 2;
+    if (std::strcmp(e, "tiled") == 0) return 3;
     return 0;
   }();
   return k;
@@ -260,6 +262,7 @@ hipError_t launch_jv(const OpParams& p, const R* base, const R* bdata, const R* 
                      const int* active, hipStream_t s) {
   const int k = kernel_choice();
   if (k == 2) return launch_jv_direct<R>(p, base, x, y, nrhs, shift, active, s);
+  if (k == 0 && bdata) return launch_jv_fast<R>(p, base, bdata, x, y, nrhs, shift, active, s);
   return launch_jv_tiled<R>(p, base, x, y, nrhs, shift, active, k == 1 ? nullptr : bdata, s);
 }
 

@@ -59,7 +59,7 @@ __device__ __forceinline__ int wall_row_order(int j, int ny, int bcy) {
 // perturbation data at one point.
 template <typename R, int ND>
 __device__ __forceinline__ void tangent(const Pt<R, ND>& b, const Pt<R, ND>& v, const OpParams& op,
-                                        R rho, R mu0, R muT, R muTT, R out[ND + 2]) {
+                                        R rho, R ip0, R mu0, R muT, R muTT, R out[ND + 2]) {
   const R gam = R(op.gamma);
   const R cp = R(op.cp);
   const R cpr = R(op.cp / op.pr);
@@ -68,7 +68,7 @@ __device__ __forceinline__ void tangent(const Pt<R, ND>& b, const Pt<R, ND>& v, 
   const R pp = v.q[0];
   const R sp = v.q[ND + 1];
   const R Tpr = v.q[ND + 2];
-  const R rhop = rho * (pp / (gam * p0) - sp / cp);   // rho_p p' + rho_s s'
+  const R rhop = rho * (pp * ip0 * R(1.0 / op.gamma) - sp * R(1.0 / op.cp));   // rho_p p' + rho_s s'
 
   R th0 = R(0), thp = R(0);
 #pragma unroll
@@ -108,7 +108,7 @@ __device__ __forceinline__ void tangent(const Pt<R, ND>& b, const Pt<R, ND>& v, 
   out[0] = -adv - gam * (pp * th0 + p0 * thp) + (gam - R(1)) * Hp;
 
   // velocity
-  const R irho = R(1) / rho;
+  const R irho = R(op.R) * T0 * ip0;   // 1/rho = R T0/p0
 #pragma unroll
   for (int i = 0; i < ND; ++i) {
     R c0 = R(0), cpert = R(0), advu = R(0);
@@ -133,8 +133,8 @@ __device__ __forceinline__ void tangent(const Pt<R, ND>& b, const Pt<R, ND>& v, 
   R advs = R(0);
 #pragma unroll
   for (int j = 0; j < ND; ++j) advs += v.q[1 + j] * b.D[ND + 1][j] + b.q[1 + j] * v.D[ND + 1][j];
-  const R rT = rho * T0;
-  out[ND + 1] = -advs + Hp / rT - H0 * (rhop * T0 + rho * Tpr) / (rT * rT);
+  const R irT = R(op.R) * ip0;   // 1/(rho T0), since rho T0 = p0/R
+  out[ND + 1] = -advs + Hp * irT - H0 * (rhop * T0 + rho * Tpr) * (irT * irT);
 }
 
 
@@ -143,13 +143,16 @@ template <typename R, int ND>
 __device__ __forceinline__ void tangent_point(const Pt<R, ND>& b, const Pt<R, ND>& v, const OpParams& op,
                                               R out[ND + 2]) {
   const R T0 = b.q[ND + 2];
-  const R rho = b.q[0] / (R(op.R) * T0);
   const R S = R(op.suth);
-  const R mu0 = R(op.mu_ref) * T0 * sqrt(T0) * (R(1) + S) / (T0 + S);
-  const R f1 = R(1.5) / T0 - R(1) / (T0 + S);
+  const R iT = R(1) / T0;
+  const R iTS = R(1) / (T0 + S);
+  const R ip0 = R(1) / b.q[0];
+  const R rho = b.q[0] * iT * R(1.0 / op.R);
+  const R mu0 = R(op.mu_ref) * T0 * sqrt(T0) * (R(1) + S) * iTS;
+  const R f1 = R(1.5) * iT - iTS;
   const R muT = mu0 * f1;
-  const R muTT = muT * f1 + mu0 * (R(-1.5) / (T0 * T0) + R(1) / ((T0 + S) * (T0 + S)));
-  tangent<R, ND>(b, v, op, rho, mu0, muT, muTT, out);
+  const R muTT = muT * f1 + mu0 * (R(-1.5) * iT * iT + iTS * iTS);
+  tangent<R, ND>(b, v, op, rho, ip0, mu0, muT, muTT, out);
 }
 
 }  // namespace sa

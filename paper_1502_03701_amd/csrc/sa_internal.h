@@ -34,6 +34,10 @@ template <typename R>
 hipError_t launch_jv_tiled(const OpParams& p, const R* base, const R* x, R* y, int nrhs, R shift,
                            const int* active, const R* bdata, hipStream_t s);
 int base_data_fields(int ndim);
+// Perturbation-only kernel with a register z-queue (needs bdata).
+template <typename R>
+hipError_t launch_jv_fast(const OpParams& p, const R* base, const R* bdata, const R* x, R* y, int nrhs, R shift,
+                          const int* active, hipStream_t s);
 hipError_t launch_base_data(const OpParams& p, const double* base, double* bdata, hipStream_t s);
 // Reference kernel (one thread per point, stencil taps straight from memory).
 template <typename R>
