@@ -216,16 +216,18 @@ __global__ void __launch_bounds__(256) lu_kernel(BLayout L, const double* __rest
 // z_b = U^{-1} L^{-1} (P r_b) for one block per 64-lane workgroup; rows lane, lane+64
 template <typename F, typename R>
 __global__ void __launch_bounds__(64) apply_kernel(BLayout L, const F* __restrict__ LU, const int* __restrict__ perm,
-                                                   int shift, const R* __restrict__ r, R* __restrict__ z, long long n,
-                                                   const int* __restrict__ active) {
-  if (active && !*active) return;
+                                                   int shift0, int shift_step, const R* __restrict__ r,
+                                                   R* __restrict__ z, long long sV, const int* __restrict__ active,
+                                                   long long sA) {
+  const int rhs = blockIdx.y;
+  if (active && !active[rhs * sA]) return;
   __shared__ F sr[128];
   const int nb = L.nb;
   const long long b = blockIdx.x;
-  const int rhs = blockIdx.y;
   const int lane = threadIdx.x;
-  const R* rr = r + (long long)rhs * n;
-  R* zz = z + (long long)rhs * n;
+  const int shift = shift0 + rhs * shift_step;
+  const R* rr = r + (long long)rhs * sV;
+  R* zz = z + (long long)rhs * sV;
   for (int l = lane; l < nb; l += 64) {
     bool wall;
     const long long d = block_dof(L, b, l, wall);
@@ -295,19 +297,23 @@ inline unsigned blocks_for(long long n, int threads) { return (unsigned)((n + th
 }  // namespace
 
 template <typename R>
-hipError_t precond_apply(Ctx* c, int ishift, int nrhs, const R* r, R* z, const int* active) {
+hipError_t precond_apply(Ctx* c, int ishift, int nrhs, const R* r, R* z, const int* active, int shift_step,
+                         long long sV, long long sA) {
   BLayout L = layout_of(c);
   dim3 grid((unsigned)L.nblocks, (unsigned)nrhs);
+  if (sV == 0) sV = c->n;
   if (c->pc_f64)
-    apply_kernel<double, R><<<grid, 64, 0, c->stream>>>(L, (const double*)c->pc_lu, c->pc_perm, ishift, r, z, c->n,
-                                                        active);
+    apply_kernel<double, R><<<grid, 64, 0, c->stream>>>(L, (const double*)c->pc_lu, c->pc_perm, ishift, shift_step,
+                                                        r, z, sV, active, sA);
   else
-    apply_kernel<float, R><<<grid, 64, 0, c->stream>>>(L, (const float*)c->pc_lu, c->pc_perm, ishift, r, z, c->n,
-                                                       active);
+    apply_kernel<float, R><<<grid, 64, 0, c->stream>>>(L, (const float*)c->pc_lu, c->pc_perm, ishift, shift_step,
+                                                       r, z, sV, active, sA);
   return hipGetLastError();
 }
-template hipError_t precond_apply<double>(Ctx*, int, int, const double*, double*, const int*);
-template hipError_t precond_apply<float>(Ctx*, int, int, const float*, float*, const int*);
+template hipError_t precond_apply<double>(Ctx*, int, int, const double*, double*, const int*, int, long long,
+                                          long long);
+template hipError_t precond_apply<float>(Ctx*, int, int, const float*, float*, const int*, int, long long,
+                                         long long);
 
 }  // namespace sa
 

@@ -5,27 +5,42 @@
 
 namespace sa {
 
-// A partial-sum workspace (RED_BLOCKS x ldp doubles) bound to the launchers.
+constexpr int PARTIAL_LD = 160;
+
+// A batch of independent systems handled by one launch: system s uses
+// vectors offset by s*vec, device results offset by s*res (doubles), active
+// flags offset by s*act (ints).  nsys = 1 with zero strides is a single system.
+struct Batch {
+  int nsys = 1;
+  long long vec = 0;    // stride of the basis / vector arrays (elements)
+  long long res = 0;    // stride of device result arrays (doubles)
+  long long act = 0;    // stride of the active flags (ints)
+  long long wvec = -1;  // stride of the w / wout vectors of update (-1: vec)
+  long long w() const { return wvec < 0 ? vec : wvec; }
+};
+
+// A partial-sum workspace (nsys x RED_BLOCKS x ldp doubles) bound to the launchers.
 template <typename R>
 struct Blas {
   double* partial = nullptr;
-  int ldp = 0;
+  int ldp = PARTIAL_LD;
 
   // out[0..ncol) (+)= V^T w, V column c at V + c*ldv.
-  void multidot(long long n, const R* V, long long ldv, int ncol, const R* w, double* out,
-                bool accumulate, const int* active, hipStream_t s) const;
+  void multidot(long long n, const R* V, long long ldv, int ncol, const R* w, double* out, bool accumulate,
+                const int* active, hipStream_t s, const Batch& b = Batch()) const;
   // wout = w + hsign * V h; mode 0: nothing else, 1: out (+)= V^T wout,
   // 2: out (+)= ||wout||^2.  wout may alias w.
-  void update(long long n, const R* V, long long ldv, int ncol, const double* h, double hsign,
-              const R* w, R* wout, int mode, double* out, bool accumulate, const int* active,
-              hipStream_t s) const;
-  void nrm2sq(long long n, const R* x, double* out, const int* active, hipStream_t s) const;
-  // r = b - y, out = ||r||^2
-  void residual(long long n, const R* b, const R* y, R* r, double* out, const int* active,
-                hipStream_t s) const;
+  void update(long long n, const R* V, long long ldv, int ncol, const double* h, double hsign, const R* w,
+              R* wout, int mode, double* out, bool accumulate, const int* active, hipStream_t s,
+              const Batch& b = Batch()) const;
+  void nrm2sq(long long n, const R* x, double* out, const int* active, hipStream_t s,
+              const Batch& b = Batch()) const;
+  // r = b - y, out = ||r||^2; r uses the batch's vec stride, b and y their own
+  void residual(long long n, const R* bvec, const R* y, R* r, double* out, const int* active, hipStream_t s,
+                const Batch& b = Batch(), long long sB = 0, long long sY = 0) const;
   // out = x * (*a)
-  void scale(long long n, const R* x, R* out, const double* a, const int* active,
-             hipStream_t s) const;
+  void scale(long long n, const R* x, R* out, const double* a, const int* active, hipStream_t s,
+             const Batch& b = Batch()) const;
   void fill(long long n, R* x, R v, hipStream_t s) const;
 };
 
@@ -33,7 +48,5 @@ struct Blas {
 void cast_d2f(long long n, const double* x, float* out, const double* scale, hipStream_t s);
 // out += double(x) * (*scale)
 void axpy_f2d(long long n, const float* x, double* out, const double* scale, hipStream_t s);
-
-constexpr int PARTIAL_LD = 160;
 
 }  // namespace sa

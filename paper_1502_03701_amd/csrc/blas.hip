@@ -1,12 +1,14 @@
 // Vector kernels of the Krylov solvers: multi-dot products against a block of
-// basis vectors, the fused Gram-Schmidt update w -= V h with the next pass's
+// basis vectors, the fused Gram-Schmidt update w += s V h with the next pass's
 // dot products, norms, scaling and precision casts.
 //
-// Every reduction is deterministic: a fixed grid of RED_BLOCKS blocks writes
-// one partial per block (and per column) in double precision, and a second
-// kernel sums the partials in a fixed order.  All kernels take an `active`
-// device flag and return at once when it is zero, so that a whole GMRES
-// cycle can be enqueued ahead and stop on the device when it converges.
+// Every reduction is deterministic: a fixed number of blocks (a function of
+// n only) writes one partial per block and per column in double precision,
+// and a second kernel sums the partials in a fixed order.  All kernels take
+// an `active` device flag and return at once when it is zero, so that a whole
+// GMRES cycle can be enqueued ahead and stop on the device when it converges.
+// A batch of independent systems runs in one launch: blockIdx.z (blockIdx.y
+// for the reductions) is the system, with the strides of a Batch.
 #include "blas.h"
 
 namespace sa {
@@ -18,7 +20,11 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Sum acc[c] over the block for c < ncol; thread 0.. writes partial[c].
+__device__ __forceinline__ bool inactive(const int* active, long long sA) {
+  return active && !active[blockIdx.z * sA];
+}
+
+// Sum acc[c] over the block for c < ncol; writes out[c].
 template <int MAXC>
 __device__ __forceinline__ void block_sum_cols(double (&acc)[MAXC], int ncol, double* __restrict__ out) {
   __shared__ double red[RED_THREADS / 64][MAXC];
@@ -41,13 +47,18 @@ __device__ __forceinline__ void block_sum_cols(double (&acc)[MAXC], int ncol, do
 }
 
 // partial[b*ldp + c0 + c] = sum over this block's elements of V[c0+c][i] w[i]
+// (blockIdx.y: column chunk, blockIdx.z: system)
 template <typename R, int MAXC>
-__global__ void __launch_bounds__(RED_THREADS) multidot_kernel(long long n, const R* __restrict__ V,
-                                                               long long ldv, int ncol,
-                                                               const R* __restrict__ w,
+__global__ void __launch_bounds__(RED_THREADS) multidot_kernel(long long n, const R* __restrict__ V, long long ldv,
+                                                               int ncol, const R* __restrict__ w,
                                                                double* __restrict__ partial, int ldp,
-                                                               const int* __restrict__ active) {
-  if (active && !*active) return;
+                                                               const int* __restrict__ active, long long sV,
+                                                               long long sP, long long sA) {
+  if (inactive(active, sA)) return;
+  const long long sys = blockIdx.z;
+  V += sys * sV;
+  w += sys * sV;
+  partial += sys * sP;
   const int c0 = blockIdx.y * MAXC;
   const int nc = min(MAXC, ncol - c0);
   double acc[MAXC];
@@ -67,10 +78,16 @@ __global__ void __launch_bounds__(RED_THREADS) multidot_kernel(long long n, cons
 // partial dots V^T w_new, else partial ||w_new||^2 in column 0.
 template <typename R, int MAXC>
 __global__ void __launch_bounds__(RED_THREADS) update_dot_kernel(
-    long long n, const R* __restrict__ V, long long ldv, int ncol, const double* __restrict__ h,
-    double hsign, const R* w, R* wout, int dot, double* __restrict__ partial, int ldp,
-    const int* __restrict__ active) {
-  if (active && !*active) return;
+    long long n, const R* __restrict__ V, long long ldv, int ncol, const double* __restrict__ h, double hsign,
+    const R* w, R* wout, int dot, double* __restrict__ partial, int ldp, const int* __restrict__ active,
+    long long sV, long long sR, long long sP, long long sA, long long sW) {
+  if (inactive(active, sA)) return;
+  const long long sys = blockIdx.z;
+  V += sys * sV;
+  w += sys * sW;
+  wout += sys * sW;
+  h += sys * sR;
+  partial += sys * sP;
   double hc[MAXC];
 #pragma unroll
   for (int c = 0; c < MAXC; ++c) hc[c] = c < ncol ? hsign * h[c] : 0.0;
@@ -103,10 +120,14 @@ __global__ void __launch_bounds__(RED_THREADS) update_dot_kernel(
 }
 
 // out[c] = (accumulate ? out[c] : 0) + sum_b partial[b*ldp + c]  (fixed order)
+// blockIdx.x: column, blockIdx.y: system
 __global__ void reduce_cols_kernel(const double* __restrict__ partial, int nblocks, int ldp, int ncol,
-                                   double* __restrict__ out, int accumulate,
-                                   const int* __restrict__ active) {
-  if (active && !*active) return;
+                                   double* __restrict__ out, int accumulate, const int* __restrict__ active,
+                                   long long sR, long long sP, long long sA) {
+  const long long sys = blockIdx.y;
+  if (active && !active[sys * sA]) return;
+  partial += sys * sP;
+  out += sys * sR;
   const int c = blockIdx.x;
   if (c >= ncol) return;
   __shared__ double red[RED_THREADS];
@@ -125,8 +146,11 @@ __global__ void reduce_cols_kernel(const double* __restrict__ partial, int nbloc
 template <typename R>
 __global__ void __launch_bounds__(RED_THREADS) nrm2_kernel(long long n, const R* __restrict__ x,
                                                            double* __restrict__ partial, int ldp,
-                                                           const int* __restrict__ active) {
-  if (active && !*active) return;
+                                                           const int* __restrict__ active, long long sV,
+                                                           long long sP, long long sA) {
+  if (inactive(active, sA)) return;
+  x += blockIdx.z * sV;
+  partial += blockIdx.z * sP;
   double acc[1] = {0.0};
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
@@ -136,13 +160,19 @@ __global__ void __launch_bounds__(RED_THREADS) nrm2_kernel(long long n, const R*
   block_sum_cols<1>(acc, 1, partial + (long long)blockIdx.x * ldp);
 }
 
-// r = b - y, partial ||r||^2
+// r = b - y, partial ||r||^2 (b uses its own stride sB)
 template <typename R>
 __global__ void __launch_bounds__(RED_THREADS) residual_kernel(long long n, const R* __restrict__ b,
                                                                const R* __restrict__ y, R* __restrict__ r,
                                                                double* __restrict__ partial, int ldp,
-                                                               const int* __restrict__ active) {
-  if (active && !*active) return;
+                                                               const int* __restrict__ active, long long sV,
+                                                               long long sB, long long sP, long long sA,
+                                                               long long sY) {
+  if (inactive(active, sA)) return;
+  b += blockIdx.z * sB;
+  y += blockIdx.z * sY;
+  r += blockIdx.z * sV;
+  partial += blockIdx.z * sP;
   double acc[1] = {0.0};
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
@@ -155,10 +185,12 @@ __global__ void __launch_bounds__(RED_THREADS) residual_kernel(long long n, cons
 
 // out = x * (*scale)   (scale read from device memory)
 template <typename R>
-__global__ void scale_kernel(long long n, const R* __restrict__ x, R* __restrict__ out,
-                             const double* __restrict__ scale, const int* __restrict__ active) {
-  if (active && !*active) return;
-  const double a = *scale;
+__global__ void scale_kernel(long long n, const R* x, R* out, const double* __restrict__ scale,
+                             const int* __restrict__ active, long long sV, long long sR, long long sA) {
+  if (inactive(active, sA)) return;
+  x += blockIdx.z * sV;
+  out += blockIdx.z * sV;
+  const double a = scale[blockIdx.z * sR];
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
     out[i] = (R)((double)x[i] * a);
@@ -189,26 +221,31 @@ inline unsigned grid_for(long long n) {
   return (unsigned)b;
 }
 
+inline long long part_stride(int ldp) { return (long long)RED_BLOCKS * ldp; }
+
 }  // namespace
 
 template <typename R>
-void Blas<R>::multidot(long long n, const R* V, long long ldv, int ncol, const R* w, double* out,
-                       bool accumulate, const int* active, hipStream_t s) const {
+void Blas<R>::multidot(long long n, const R* V, long long ldv, int ncol, const R* w, double* out, bool accumulate,
+                       const int* active, hipStream_t s, const Batch& b) const {
   const int chunks = (ncol + 15) / 16;
   const unsigned nb = grid_for(n);
-  multidot_kernel<R, 16><<<dim3(nb, chunks), RED_THREADS, 0, s>>>(n, V, ldv, ncol, w, partial, ldp,
-                                                                 active);
-  reduce_cols_kernel<<<ncol, RED_THREADS, 0, s>>>(partial, (int)nb, ldp, ncol, out, accumulate ? 1 : 0,
-                                                  active);
+  const long long sP = part_stride(ldp);
+  multidot_kernel<R, 16><<<dim3(nb, chunks, b.nsys), RED_THREADS, 0, s>>>(n, V, ldv, ncol, w, partial, ldp, active,
+                                                                          b.vec, sP, b.act);
+  reduce_cols_kernel<<<dim3(ncol, b.nsys), RED_THREADS, 0, s>>>(partial, (int)nb, ldp, ncol, out,
+                                                                accumulate ? 1 : 0, active, b.res, sP, b.act);
 }
 
 template <typename R>
-void Blas<R>::update(long long n, const R* V, long long ldv, int ncol, const double* h, double hsign,
-                     const R* w, R* wout, int mode, double* out, bool accumulate, const int* active,
-                     hipStream_t s) const {
+void Blas<R>::update(long long n, const R* V, long long ldv, int ncol, const double* h, double hsign, const R* w,
+                     R* wout, int mode, double* out, bool accumulate, const int* active, hipStream_t s,
+                     const Batch& b) const {
   // mode: 0 = no reduction, 1 = dots V^T w_new, 2 = ||w_new||^2
   const bool dot = mode == 1;
   const unsigned nb = grid_for(n);
+  const long long sP = part_stride(ldp);
+  const dim3 grid(nb, 1, b.nsys);
   int done = 0;
   const R* src = w;
   while (done < ncol || (ncol == 0 && done == 0)) {
@@ -216,50 +253,55 @@ void Blas<R>::update(long long n, const R* V, long long ldv, int ncol, const dou
     const bool last = nc <= 64;
     const int c = last ? nc : 64;
     const int dflag = (last && dot && ncol <= 64) ? 1 : 0;
+    const R* Vc = V + (long long)done * ldv;
     if (c <= 16)
-      update_dot_kernel<R, 16><<<nb, RED_THREADS, 0, s>>>(n, V + (long long)done * ldv, ldv, c,
-                                                                  h + done, hsign, src, wout, dflag,
-                                                                  partial, ldp, active);
+      update_dot_kernel<R, 16><<<grid, RED_THREADS, 0, s>>>(n, Vc, ldv, c, h + done, hsign, src, wout, dflag, partial,
+                                                            ldp, active, b.vec, b.res, sP, b.act, b.w());
     else if (c <= 32)
-      update_dot_kernel<R, 32><<<nb, RED_THREADS, 0, s>>>(n, V + (long long)done * ldv, ldv, c,
-                                                                  h + done, hsign, src, wout, dflag,
-                                                                  partial, ldp, active);
+      update_dot_kernel<R, 32><<<grid, RED_THREADS, 0, s>>>(n, Vc, ldv, c, h + done, hsign, src, wout, dflag, partial,
+                                                            ldp, active, b.vec, b.res, sP, b.act, b.w());
     else
-      update_dot_kernel<R, 64><<<nb, RED_THREADS, 0, s>>>(n, V + (long long)done * ldv, ldv, c,
-                                                                  h + done, hsign, src, wout, dflag,
-                                                                  partial, ldp, active);
+      update_dot_kernel<R, 64><<<grid, RED_THREADS, 0, s>>>(n, Vc, ldv, c, h + done, hsign, src, wout, dflag, partial,
+                                                            ldp, active, b.vec, b.res, sP, b.act, b.w());
     src = wout;
     done += c;
     if (last) break;
   }
   if (dot && ncol > 64) {
-    multidot(n, V, ldv, ncol, wout, out, accumulate, active, s);
+    multidot(n, V, ldv, ncol, wout, out, accumulate, active, s, b);
   } else if (mode == 1) {
-    reduce_cols_kernel<<<ncol, RED_THREADS, 0, s>>>(partial, (int)nb, ldp, ncol, out,
-                                                    accumulate ? 1 : 0, active);
+    reduce_cols_kernel<<<dim3(ncol, b.nsys), RED_THREADS, 0, s>>>(partial, (int)nb, ldp, ncol, out,
+                                                                  accumulate ? 1 : 0, active, b.res, sP, b.act);
   } else if (mode == 2) {
-    reduce_cols_kernel<<<1, RED_THREADS, 0, s>>>(partial, (int)nb, ldp, 1, out, accumulate ? 1 : 0,
-                                                 active);
+    reduce_cols_kernel<<<dim3(1, b.nsys), RED_THREADS, 0, s>>>(partial, (int)nb, ldp, 1, out, accumulate ? 1 : 0,
+                                                               active, b.res, sP, b.act);
   }
 }
 
 template <typename R>
-void Blas<R>::nrm2sq(long long n, const R* x, double* out, const int* active, hipStream_t s) const {
-  nrm2_kernel<R><<<grid_for(n), RED_THREADS, 0, s>>>(n, x, partial, ldp, active);
-  reduce_cols_kernel<<<1, RED_THREADS, 0, s>>>(partial, (int)grid_for(n), ldp, 1, out, 0, active);
+void Blas<R>::nrm2sq(long long n, const R* x, double* out, const int* active, hipStream_t s, const Batch& b) const {
+  const unsigned nb = grid_for(n);
+  const long long sP = part_stride(ldp);
+  nrm2_kernel<R><<<dim3(nb, 1, b.nsys), RED_THREADS, 0, s>>>(n, x, partial, ldp, active, b.vec, sP, b.act);
+  reduce_cols_kernel<<<dim3(1, b.nsys), RED_THREADS, 0, s>>>(partial, (int)nb, ldp, 1, out, 0, active, b.res, sP,
+                                                             b.act);
 }
 
 template <typename R>
-void Blas<R>::residual(long long n, const R* b, const R* y, R* r, double* out, const int* active,
-                       hipStream_t s) const {
-  residual_kernel<R><<<grid_for(n), RED_THREADS, 0, s>>>(n, b, y, r, partial, ldp, active);
-  reduce_cols_kernel<<<1, RED_THREADS, 0, s>>>(partial, (int)grid_for(n), ldp, 1, out, 0, active);
+void Blas<R>::residual(long long n, const R* bvec, const R* y, R* r, double* out, const int* active, hipStream_t s,
+                       const Batch& b, long long sB, long long sY) const {
+  const unsigned nb = grid_for(n);
+  const long long sP = part_stride(ldp);
+  residual_kernel<R><<<dim3(nb, 1, b.nsys), RED_THREADS, 0, s>>>(n, bvec, y, r, partial, ldp, active, b.vec, sB, sP,
+                                                                 b.act, sY);
+  reduce_cols_kernel<<<dim3(1, b.nsys), RED_THREADS, 0, s>>>(partial, (int)nb, ldp, 1, out, 0, active, b.res, sP,
+                                                             b.act);
 }
 
 template <typename R>
-void Blas<R>::scale(long long n, const R* x, R* out, const double* a, const int* active,
-                    hipStream_t s) const {
-  scale_kernel<R><<<grid_for(n), RED_THREADS, 0, s>>>(n, x, out, a, active);
+void Blas<R>::scale(long long n, const R* x, R* out, const double* a, const int* active, hipStream_t s,
+                    const Batch& b) const {
+  scale_kernel<R><<<dim3(grid_for(n), 1, b.nsys), RED_THREADS, 0, s>>>(n, x, out, a, active, b.vec, b.res, b.act);
 }
 
 template <typename R>

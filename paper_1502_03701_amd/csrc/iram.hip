@@ -42,7 +42,7 @@ int cayley_apply(Iram& w, const double* v, double* out) {
   if (o.lin.prec == SA_MIXED)
     rc = solve_ir(c, o.lin, o.sigma, w.tb, out, pci, &info);
   else
-    rc = solve_gmres<double>(c, o.lin, o.sigma, w.tb, out, pci, &info);
+    rc = solve_gmres<double>(c, o.lin, 1, &o.sigma, w.tb, out, pci, &info);
   if (rc < 0) return rc;
   w.res->n_cayley += 1;
   w.res->n_matvec += info.matvecs + 1;
@@ -82,7 +82,7 @@ int run_one(Ctx* c, const sa_eig_opts& o, const double* v0, sa_eig_result* res) 
   w.T = (double*)c->buffer("iramT", sizeof(double) * n * (m + 1));
   w.tb = (double*)c->buffer("iramB", sizeof(double) * n);
   w.st = (IState*)c->buffer("iramS", sizeof(IState));
-  w.bl.partial = (double*)c->buffer("partial", sizeof(double) * RED_BLOCKS * PARTIAL_LD);
+  w.bl.partial = (double*)c->buffer("iram_partial", sizeof(double) * RED_BLOCKS * PARTIAL_LD);
   w.bl.ldp = PARTIAL_LD;
   if (!w.V || !w.T || !w.tb || !w.st || !w.bl.partial) return c->fail(SA_ENOMEM, "iram: out of device memory");
   double* evr = res->evec_re_dev;

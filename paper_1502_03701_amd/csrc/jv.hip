@@ -266,6 +266,27 @@ hipError_t launch_jv(const OpParams& p, const R* base, const R* bdata, const R* 
   return launch_jv_tiled<R>(p, base, x, y, nrhs, shift, active, k == 1 ? nullptr : bdata, s);
 }
 
+template <typename R>
+hipError_t launch_jv_batch(const OpParams& p, const R* base, const R* bdata, const R* x, R* y, int nsys,
+                           long long sX, long long sY, const double* shifts_host, const double* shifts_dev,
+                           const int* active, long long sA, hipStream_t s) {
+  if (kernel_choice() == 0 && bdata)
+    return launch_jv_fast<R>(p, base, bdata, x, y, nsys, R(0), active, s, sX, sY, shifts_dev, sA);
+  for (int r = 0; r < nsys; ++r) {
+    hipError_t e = launch_jv<R>(p, base, bdata, x + r * sX, y + r * sY, 1, R(shifts_host[r]),
+                                active ? active + r * sA : nullptr, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+template hipError_t launch_jv_batch<double>(const OpParams&, const double*, const double*, const double*, double*,
+                                            int, long long, long long, const double*, const double*, const int*,
+                                            long long, hipStream_t);
+template hipError_t launch_jv_batch<float>(const OpParams&, const float*, const float*, const float*, float*, int,
+                                           long long, long long, const double*, const double*, const int*,
+                                           long long, hipStream_t);
+
 template hipError_t launch_jv<double>(const OpParams&, const double*, const double*, const double*, double*,
                                       int, double, const int*, hipStream_t);
 template hipError_t launch_jv<float>(const OpParams&, const float*, const float*, const float*, float*, int,

@@ -28,11 +28,21 @@ constexpr int NZC = 16;
 
 __device__ __forceinline__ int wrapi(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
 
+// A batch of systems shares one launch: blockIdx.z = sys * zchunks + chunk;
+// system sys reads x + sys*sV, writes y + sys*sV, uses shifts[sys] (or the
+// scalar shift) and the flag active[sys*sA].
 template <typename R, int ND>
 __global__ void __launch_bounds__(NT) jv_fast_kernel(OpParams op, const R* __restrict__ base,
                                                      const R* __restrict__ bdata, const R* __restrict__ x,
-                                                     R* __restrict__ y, R shift, const int* __restrict__ active) {
-  if (active && !*active) return;
+                                                     R* __restrict__ y, R shift, const int* __restrict__ active,
+                                                     long long strideX, long long strideY,
+                                                     const double* __restrict__ shifts, long long sA, int zchunks) {
+  const int sys = blockIdx.z / zchunks;
+  const int zc = blockIdx.z % zchunks;
+  if (active && !active[sys * sA]) return;
+  x += sys * strideX;
+  y += sys * strideY;
+  if (shifts) shift = R(shifts[sys]);
   constexpr int NF = ND + 3;   // p, u_i, s, T'
   __shared__ R sP[NF][PH][PW];
   __shared__ R sX[2][TY][PW];  // D_y v + D_z w, D_z u  (x halo)
@@ -81,7 +91,7 @@ __global__ void __launch_bounds__(NT) jv_fast_kernel(OpParams op, const R* __res
     return acc * ihz;
   };
 
-  const int kbeg = ND == 3 ? blockIdx.z * NZC : 0;
+  const int kbeg = ND == 3 ? zc * NZC : 0;
   const int kend = ND == 3 ? min(nz, kbeg + NZC) : 1;
   const int gi_own = wrapi(i, nx);
   const int gj_own = grow(tj + 3);
@@ -270,21 +280,25 @@ __global__ void __launch_bounds__(NT) jv_fast_kernel(OpParams op, const R* __res
 
 template <typename R>
 hipError_t launch_jv_fast(const OpParams& p, const R* base, const R* bdata, const R* x, R* y, int nrhs, R shift,
-                          const int* active, hipStream_t s) {
+                          const int* active, hipStream_t s, long long sX, long long sY, const double* shifts,
+                          long long sA) {
   const long long ndof = (long long)(p.ndim + 2) * p.npts;
-  dim3 grid((p.nx + TX - 1) / TX, (p.ny + TY - 1) / TY, p.ndim == 3 ? (p.nz + NZC - 1) / NZC : 1);
-  for (int r = 0; r < nrhs; ++r) {
-    if (p.ndim == 2)
-      jv_fast_kernel<R, 2><<<grid, NT, 0, s>>>(p, base, bdata, x + r * ndof, y + r * ndof, shift, active);
-    else
-      jv_fast_kernel<R, 3><<<grid, NT, 0, s>>>(p, base, bdata, x + r * ndof, y + r * ndof, shift, active);
-  }
+  const int zchunks = p.ndim == 3 ? (p.nz + NZC - 1) / NZC : 1;
+  if (sX == 0) sX = ndof;   // right-hand sides one after another
+  if (sY == 0) sY = ndof;
+  dim3 grid((p.nx + TX - 1) / TX, (p.ny + TY - 1) / TY, zchunks * nrhs);
+  if (p.ndim == 2)
+    jv_fast_kernel<R, 2><<<grid, NT, 0, s>>>(p, base, bdata, x, y, shift, active, sX, sY, shifts, sA, zchunks);
+  else
+    jv_fast_kernel<R, 3><<<grid, NT, 0, s>>>(p, base, bdata, x, y, shift, active, sX, sY, shifts, sA, zchunks);
   return hipGetLastError();
 }
 
 template hipError_t launch_jv_fast<double>(const OpParams&, const double*, const double*, const double*, double*,
-                                           int, double, const int*, hipStream_t);
+                                           int, double, const int*, hipStream_t, long long, long long,
+                                           const double*, long long);
 template hipError_t launch_jv_fast<float>(const OpParams&, const float*, const float*, const float*, float*, int,
-                                          float, const int*, hipStream_t);
+                                          float, const int*, hipStream_t, long long, long long, const double*,
+                                          long long);
 
 }  // namespace sa

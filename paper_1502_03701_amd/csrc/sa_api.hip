@@ -166,21 +166,19 @@ int sa_gmres_solve(sa_ctx* c, const sa_gmres_opts* o, int nshift, const double* 
   }
   if (o->prec == SA_MIXED && (!(o->inner_tol > 0) || o->max_outer < 1))
     return c->fail(SA_EINVAL, "sa_gmres_solve: MIXED needs inner_tol > 0 and max_outer >= 1");
+  // FP64 / FP32: all shifts advance in lockstep in the same launches
+  if (o->prec == SA_F64)
+    return solve_gmres<double>(c, *o, nshift, sigma_host, (const double*)b_dev, (double*)x_dev,
+                               o->use_precond ? 0 : -1, info);
+  if (o->prec == SA_F32)
+    return solve_gmres<float>(c, *o, nshift, sigma_host, (const float*)b_dev, (float*)x_dev,
+                              o->use_precond ? 0 : -1, info);
+  if (o->prec != SA_MIXED) return c->fail(SA_EINVAL, "sa_gmres_solve: bad precision");
   int rc_all = SA_OK;
   for (int s = 0; s < nshift; ++s) {
-    int rc;
     const long long off = (long long)s * c->n;
-    const int pci = o->use_precond ? s : -1;
-    if (o->prec == SA_F64)
-      rc = solve_gmres<double>(c, *o, sigma_host[s], (const double*)b_dev + off, (double*)x_dev + off, pci,
-                               &info[s]);
-    else if (o->prec == SA_F32)
-      rc = solve_gmres<float>(c, *o, sigma_host[s], (const float*)b_dev + off, (float*)x_dev + off, pci,
-                              &info[s]);
-    else if (o->prec == SA_MIXED)
-      rc = solve_ir(c, *o, sigma_host[s], (const double*)b_dev + off, (double*)x_dev + off, pci, &info[s]);
-    else
-      return c->fail(SA_EINVAL, "sa_gmres_solve: bad precision");
+    const int rc = solve_ir(c, *o, sigma_host[s], (const double*)b_dev + off, (double*)x_dev + off,
+                            o->use_precond ? s : -1, &info[s]);
     if (rc < 0) return rc;
     if (rc > 0) rc_all = rc;
   }

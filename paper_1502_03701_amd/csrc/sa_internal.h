@@ -34,10 +34,20 @@ template <typename R>
 hipError_t launch_jv_tiled(const OpParams& p, const R* base, const R* x, R* y, int nrhs, R shift,
                            const int* active, const R* bdata, hipStream_t s);
 int base_data_fields(int ndim);
-// Perturbation-only kernel with a register z-queue (needs bdata).
+// Perturbation-only kernel with a register z-queue (needs bdata).  nrhs
+// systems in one launch: system r uses x/y + r*sV (sV = 0: n), the shift
+// shifts[r] (device array; null: the scalar shift) and active[r*sA].
 template <typename R>
 hipError_t launch_jv_fast(const OpParams& p, const R* base, const R* bdata, const R* x, R* y, int nrhs, R shift,
-                          const int* active, hipStream_t s);
+                          const int* active, hipStream_t s, long long sX = 0, long long sY = 0,
+                          const double* shifts = nullptr, long long sA = 0);
+// A batch of systems: one launch with the default kernel, else one launch per
+// system.  System r reads x + r*sX, writes y + r*sY; shifts_host / shifts_dev
+// hold the per-system shifts.
+template <typename R>
+hipError_t launch_jv_batch(const OpParams& p, const R* base, const R* bdata, const R* x, R* y, int nsys,
+                           long long sX, long long sY, const double* shifts_host, const double* shifts_dev,
+                           const int* active, long long sA, hipStream_t s);
 hipError_t launch_base_data(const OpParams& p, const double* base, double* bdata, hipStream_t s);
 // Reference kernel (one thread per point, stencil taps straight from memory).
 template <typename R>

@@ -55,14 +55,15 @@ struct Ctx {
 };
 
 template <typename R>
-int solve_gmres(Ctx* c, const sa_gmres_opts& o, double sigma, const R* b, R* x, int pc_shift,
+int solve_gmres(Ctx* c, const sa_gmres_opts& o, int nsys, const double* sigma_host, const R* b, R* x, int pc_shift0,
                 sa_gmres_info* info, const std::string& tag = "g");
 int solve_ir(Ctx* c, const sa_gmres_opts& o, double sigma, const double* b, double* x, int pc_shift,
              sa_gmres_info* info);
 
 // block-Jacobi apply z = P M^{-1} r (bjac.hip)
 template <typename R>
-hipError_t precond_apply(Ctx* c, int ishift, int nrhs, const R* r, R* z, const int* active);
+hipError_t precond_apply(Ctx* c, int ishift, int nrhs, const R* r, R* z, const int* active, int shift_step = 0,
+                         long long sV = 0, long long sA = 0);
 
 }  // namespace sa
 

@@ -1,115 +1,157 @@
-// Restarted GMRES (Section "Iterative solvers") for (J - sigma I) x = b, with
-// classical Gram-Schmidt applied twice and optional right block-Jacobi
+// Restarted GMRES (Section "Iterative solvers") for (J - sigma_s I) x_s = b_s,
+// with classical Gram-Schmidt applied twice and optional right block-Jacobi
 // preconditioning in the flexible form (the preconditioned directions are
 // kept), plus the FP64-outer / FP32-inner iterative refinement form.
 //
-// One cycle is enqueued in full: residual, then per Arnoldi step the
-// preconditioner, the operator, the two Gram-Schmidt passes and the Givens
-// update.  Every kernel reads the device flag `active`, which the Givens
-// kernel clears on convergence or breakdown, so the host synchronises only
-// once per cycle to read the status.
+// Several systems (Cayley shifts) advance in lockstep: every kernel of an
+// Arnoldi step handles all systems in one launch, each system with its own
+// basis, device state and active flag.  One cycle is enqueued in full:
+// residual, then per step the preconditioner, the operator, the two
+// Gram-Schmidt passes and the Givens update.  The Givens kernel clears a
+// system's active flag on convergence, breakdown or budget exhaustion, so the
+// host synchronises once per cycle to read the states.
 #include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include "sa_runtime.h"
 
 namespace sa {
 namespace {
 
-hipError_t read_tail(GState* st, GTail& h, hipStream_t s) {
-  hipError_t e = hipMemcpyAsync(&h, &st->t, sizeof(GTail), hipMemcpyDeviceToHost, s);
+hipError_t read_tails(GState* st, int nsys, std::vector<GTail>& h, hipStream_t s) {
+  h.resize(nsys);
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < nsys && e == hipSuccess; ++i)
+    e = hipMemcpyAsync(&h[i], &st[i].t, sizeof(GTail), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   return e;
+}
+
+template <typename R>
+const R* base_of(const Ctx* c) {
+  return nullptr;
+}
+template <>
+const double* base_of<double>(const Ctx* c) {
+  return c->base64;
+}
+template <>
+const float* base_of<float>(const Ctx* c) {
+  return c->base32;
+}
+template <typename R>
+const R* bdata_of(const Ctx* c) {
+  return nullptr;
+}
+template <>
+const double* bdata_of<double>(const Ctx* c) {
+  return c->bdata64;
+}
+template <>
+const float* bdata_of<float>(const Ctx* c) {
+  return c->bdata32;
 }
 
 }  // namespace
 
 template <typename R>
-int solve_gmres(Ctx* c, const sa_gmres_opts& o, double sigma, const R* b, R* x, int pc_shift,
+int solve_gmres(Ctx* c, const sa_gmres_opts& o, int nsys, const double* sigma, const R* b, R* x, int pc_shift0,
                 sa_gmres_info* info, const std::string& tag) {
   hipStream_t s = c->stream;
   const long long n = c->n;
   const int m = o.restart;
-  const bool pc = pc_shift >= 0;
-  const size_t vbytes = (size_t)n * sizeof(R);
-  R* V = (R*)c->buffer(tag + "V", vbytes * (m + 1));
-  R* Z = pc ? (R*)c->buffer(tag + "Z", vbytes * m) : V;
-  GState* st = (GState*)c->buffer(tag + "state", sizeof(GState));
+  const bool pc = pc_shift0 >= 0;
+  const long long sv = n * (m + 1);   // basis stride between systems
+  R* V = (R*)c->buffer(tag + "V", sizeof(R) * sv * nsys);
+  R* Z = pc ? (R*)c->buffer(tag + "Z", sizeof(R) * sv * nsys) : V;
+  R* T = (R*)c->buffer(tag + "T", sizeof(R) * n * nsys, false);
+  GState* st = (GState*)c->buffer(tag + "state", sizeof(GState) * nsys);
+  double* sig = (double*)c->buffer(tag + "sigma", sizeof(double) * nsys, false);
   Blas<R> bl;
-  bl.partial = (double*)c->buffer("partial", sizeof(double) * RED_BLOCKS * PARTIAL_LD);
-  bl.ldp = PARTIAL_LD;
-  if (!V || !Z || !st || !bl.partial) return c->fail(SA_ENOMEM, "gmres: out of device memory");
+  bl.partial = (double*)c->buffer(tag + "partial", sizeof(double) * RED_BLOCKS * PARTIAL_LD * nsys);
+  if (!V || !Z || !T || !st || !sig || !bl.partial) return c->fail(SA_ENOMEM, "gmres: out of device memory");
+  hipError_t e = hipMemcpyAsync(sig, sigma, sizeof(double) * nsys, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return c->hip_fail(e, "gmres shifts");
+  const R* base = base_of<R>(c);
+  const R* bdata = bdata_of<R>(c);
   const int* act = &st->t.active;
-  *info = sa_gmres_info{};
+  Batch bb;                       // basis operations
+  bb.nsys = nsys;
+  bb.vec = sv;
+  bb.res = GS_DOUBLES;
+  bb.act = GS_INTS;
+  Batch bn = bb;                  // vectors one after another (b, x)
+  bn.vec = n;
+  Batch bx = bb;                  // x += Z y: basis stride for Z, n for x
+  bx.wvec = n;
 
-  gstate_init(st, o.tol, m, s);
-  bl.nrm2sq(n, b, &st->t.bnorm2, nullptr, s);
-  gstate_set_bnorm(st, s);
-  long long matvecs = 0;
+  for (int i = 0; i < nsys; ++i) info[i] = sa_gmres_info{};
+  gstate_init(st, nsys, o.tol, m, o.max_matvec, s);
+  bl.nrm2sq(n, b, &st->t.bnorm2, nullptr, s, bn);
+  gstate_set_bnorm(st, nsys, s);
+  std::vector<GTail> h;
   int cycles = 0;
-  hipError_t e;
   for (;;) {
-    // r = b - (J - sigma I) x  -> V[:,0]
-    e = c->jv<R>(x, V + n, 1, sigma, nullptr);
+    // r = b - (J - sigma I) x  -> V_s[:,0]
+    e = launch_jv_batch<R>(c->op, base, bdata, x, T, nsys, n, n, sigma, sig, nullptr, 0, s);
     if (e != hipSuccess) return c->hip_fail(e, "gmres residual");
-    bl.residual(n, b, V + n, V, &st->t.rnorm2, nullptr, s);
-    gstate_cycle_start(st, s);
-    GTail h;
-    e = read_tail(st, h, s);
+    bl.residual(n, b, T, V, &st->t.rnorm2, nullptr, s, bb, n, n);
+    gstate_cycle_start(st, nsys, s);
+    e = read_tails(st, nsys, h, s);
     if (e != hipSuccess) return c->hip_fail(e, "gmres status");
-    matvecs = h.matvecs;
-    info->iters = h.iters;
-    info->matvecs = h.matvecs;
-    info->cycles = cycles;
-    info->relres = h.relres;
-    if (h.nonfinite) {
-      info->status = SA_ENONFINITE;
-      return c->fail(SA_ENONFINITE, "gmres: non-finite residual");
+    bool any_active = false;
+    for (int i = 0; i < nsys; ++i) {
+      info[i].iters = h[i].iters;
+      info[i].matvecs = h[i].matvecs;
+      info[i].cycles = cycles;
+      info[i].relres = h[i].relres;
+      info[i].precond_applies = pc ? h[i].iters : 0;
+      if (h[i].nonfinite) {
+        info[i].status = SA_ENONFINITE;
+        return c->fail(SA_ENONFINITE, "gmres: non-finite residual (system %d)", i);
+      }
+      info[i].status = h[i].converged ? SA_OK : SA_NOT_CONVERGED;
+      any_active = any_active || h[i].active;
     }
-    if (h.converged) {
-      info->status = SA_OK;
-      return SA_OK;
-    }
-    if (matvecs >= o.max_matvec) {
-      info->status = SA_NOT_CONVERGED;
-      return SA_NOT_CONVERGED;
-    }
-    const int jl = (int)std::min<long long>(m, o.max_matvec - matvecs);
-    gstate_set_jlimit(st, jl, s);
-    bl.scale(n, V, V, &st->t.inv, act, s);
-    for (int j = 0; j < jl; ++j) {
+    if (!any_active) break;
+    bl.scale(n, V, V, &st->t.inv, act, s, bb);
+    for (int j = 0; j < m; ++j) {
       R* vj = V + (long long)j * n;
       R* w = V + (long long)(j + 1) * n;
       const R* zj = vj;
       if (pc) {
         R* zz = Z + (long long)j * n;
-        e = precond_apply<R>(c, pc_shift, 1, vj, zz, act);
+        e = precond_apply<R>(c, pc_shift0, nsys, vj, zz, act, 1, sv, GS_INTS);
         if (e != hipSuccess) return c->hip_fail(e, "gmres precond");
         zj = zz;
       }
-      e = c->jv<R>(zj, w, 1, sigma, act);
+      e = launch_jv_batch<R>(c->op, base, bdata, zj, w, nsys, sv, sv, sigma, sig, act, GS_INTS, s);
       if (e != hipSuccess) return c->hip_fail(e, "gmres jv");
       // CGS pass 1: d1 = V[0..j]^T w and ||w||^2
-      bl.multidot(n, V, n, j + 2, w, st->d1, false, act, s);
+      bl.multidot(n, V, n, j + 2, w, st->d1, false, act, s, bb);
       // pass 2: w -= V d1, d2 = V^T w
-      bl.update(n, V, n, j + 1, st->d1, -1.0, w, w, 1, st->d2, false, act, s);
+      bl.update(n, V, n, j + 1, st->d1, -1.0, w, w, 1, st->d2, false, act, s, bb);
       // pass 3: w -= V d2, wn2 = ||w||^2
-      bl.update(n, V, n, j + 1, st->d2, -1.0, w, w, 2, &st->wn2, false, act, s);
-      gstate_step(st, j, s);
-      bl.scale(n, w, w, &st->t.inv, act, s);
+      bl.update(n, V, n, j + 1, st->d2, -1.0, w, w, 2, &st->wn2, false, act, s, bb);
+      gstate_step(st, nsys, j, s);
+      bl.scale(n, w, w, &st->t.inv, act, s, bb);
     }
-    gstate_finish(st, s);
+    gstate_finish(st, nsys, s);
     // x += Z y  (Z = V without preconditioning)
-    bl.update(n, Z, n, jl, st->y, 1.0, x, x, 0, nullptr, false, &st->t.have_update, s);
+    bl.update(n, Z, n, m, st->y, 1.0, x, x, 0, nullptr, false, &st->t.have_update, s, bx);
     e = hipGetLastError();
     if (e != hipSuccess) return c->hip_fail(e, "gmres cycle");
     ++cycles;
   }
+  bool all = true;
+  for (int i = 0; i < nsys; ++i) all = all && info[i].status == SA_OK;
+  return all ? SA_OK : SA_NOT_CONVERGED;
 }
 
-template int solve_gmres<double>(Ctx*, const sa_gmres_opts&, double, const double*, double*, int,
+template int solve_gmres<double>(Ctx*, const sa_gmres_opts&, int, const double*, const double*, double*, int,
                                  sa_gmres_info*, const std::string&);
-template int solve_gmres<float>(Ctx*, const sa_gmres_opts&, double, const float*, float*, int,
+template int solve_gmres<float>(Ctx*, const sa_gmres_opts&, int, const double*, const float*, float*, int,
                                 sa_gmres_info*, const std::string&);
 
 // Iterative refinement: FP64 residual and update, FP32 GMRES on the scaled
@@ -124,40 +166,40 @@ int solve_ir(Ctx* c, const sa_gmres_opts& o, double sigma, const double* b, doub
   float* d32 = (float*)c->buffer("ir_d32", sizeof(float) * n);
   GState* st = (GState*)c->buffer("ir_state", sizeof(GState));
   Blas<double> bl;
-  bl.partial = (double*)c->buffer("partial", sizeof(double) * RED_BLOCKS * PARTIAL_LD);
-  bl.ldp = PARTIAL_LD;
+  bl.partial = (double*)c->buffer("ir_partial", sizeof(double) * RED_BLOCKS * PARTIAL_LD);
   Blas<float> bl32;
   bl32.partial = bl.partial;
-  bl32.ldp = PARTIAL_LD;
   if (!r || !y || !r32 || !d32 || !st || !bl.partial) return c->fail(SA_ENOMEM, "ir: out of device memory");
   *info = sa_gmres_info{};
-  gstate_init(st, o.tol, 0, s);
+  // the outer state only tracks ||b||, ||r|| and the tolerance; no budget
+  gstate_init(st, 1, o.tol, 1, (long long)1 << 62, s);
   bl.nrm2sq(n, b, &st->t.bnorm2, nullptr, s);
-  gstate_set_bnorm(st, s);
+  gstate_set_bnorm(st, 1, s);
   sa_gmres_opts in = o;
   in.prec = SA_F32;
   in.tol = o.inner_tol;
-  long long inner_mv = 0, inner_it = 0;
+  long long inner_mv = 0, inner_it = 0, inner_pc = 0;
   int inner_cycles = 0;
   hipError_t e;
+  std::vector<GTail> h;
   for (int outer = 0;; ++outer) {
     e = c->jv<double>(x, y, 1, sigma, nullptr);
     if (e != hipSuccess) return c->hip_fail(e, "ir residual");
     bl.residual(n, b, y, r, &st->t.rnorm2, nullptr, s);
-    gstate_cycle_start(st, s);  // beta = ||r||, inv = 1/||r||, converged flag
-    GTail h;
-    e = read_tail(st, h, s);
+    gstate_cycle_start(st, 1, s);  // beta = ||r||, inv = 1/||r||, converged flag
+    e = read_tails(st, 1, h, s);
     if (e != hipSuccess) return c->hip_fail(e, "ir status");
     info->outer = outer;
-    info->relres = h.relres;
+    info->relres = h[0].relres;
     info->iters = inner_it;
-    info->matvecs = inner_mv + h.matvecs;
+    info->matvecs = inner_mv + h[0].matvecs;
     info->cycles = inner_cycles;
-    if (h.nonfinite) {
+    info->precond_applies = inner_pc;
+    if (h[0].nonfinite) {
       info->status = SA_ENONFINITE;
       return c->fail(SA_ENONFINITE, "ir: non-finite residual");
     }
-    if (h.converged) {
+    if (h[0].converged) {
       info->status = SA_OK;
       return SA_OK;
     }
@@ -170,12 +212,13 @@ int solve_ir(Ctx* c, const sa_gmres_opts& o, double sigma, const double* b, doub
     bl32.fill(n, d32, 0.0f, s);
     sa_gmres_info ii{};
     in.max_matvec = std::max<long long>(1, o.max_matvec - info->matvecs);
-    int rc = solve_gmres<float>(c, in, sigma, r32, d32, pc_shift, &ii, "ir32");
+    int rc = solve_gmres<float>(c, in, 1, &sigma, r32, d32, pc_shift, &ii, "ir32");
     if (rc < 0) return rc;
     inner_mv += ii.matvecs;
     inner_it += ii.iters;
+    inner_pc += ii.precond_applies;
     inner_cycles += ii.cycles;
-        // x += ||r|| d
+    // x += ||r|| d
     axpy_f2d(n, d32, x, &st->t.beta, s);
   }
 }
