@@ -9,11 +9,13 @@ one point = one update).
 
 Also reported: the roofline record of the operator kernel (algorithmic bytes
 = read x + read q0 + write y = 3 nv 8 B per point, against 8 TB/s), the same
-operator in FP32, optional extras (--extras: GMRES iteration time at the 2D
-512 x 512 case, block-Jacobi apply, time to eigenpairs FP64 vs mixed on a
-small case), and the oracle timed on the host cores on a bounded sample.
+operator in FP32, optional extras (--extras: GMRES(40) at 2D 512 x 512, the
+block-Jacobi preconditioner of the 3D grid with 8 shifts, 8-shift batched
+GMRES cycles, time to eigenpairs FP64 vs mixed on a small case), and the
+oracle timed on the host cores on a bounded sample.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--extras]
+       [--no-cpu] [--calib-copy]
 """
 import argparse
 import json
@@ -28,8 +30,9 @@ METRIC = "Gpt-updates/s of matrix-free Jv; time to 6 eigenpairs, mixed vs FP64 G
 HBM_PEAK_GBS = 8000.0
 
 
-def timed_launches(fn, steps, warmup, torch):
-    """HIP events on the current stream (the stream the library launches on)."""
+def timed(fn, steps, warmup, torch):
+    """Seconds for `steps` calls, HIP events on the current stream (the
+    stream the library launches on)."""
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
@@ -40,20 +43,20 @@ def timed_launches(fn, steps, warmup, torch):
         fn()
     stop.record()
     torch.cuda.synchronize()
-    return start.elapsed_time(stop) / 1e3   # seconds
+    return start.elapsed_time(stop) / 1e3
 
 
 def cpu_baseline(prob, q0, v):
     """Oracle complex-step Jv on a bounded window of the workload (a 16-wide
-    slab in x and z over the full y range, about 10 s of CPU work), scaled
+    slab in x and z over the full y range), repeated for about 10 s, scaled
     to Gpt/s."""
-    import numpy as np
     import synth
     from oracle import operator as op
     W = 16
     nx, ny, nz = prob.n
     sub = synth.mixing_layer_3d(W, ny, W, prob.mach, prob.re, lx=W * prob.length[0] / nx,
                                 ly=prob.length[1], lz=W * prob.length[2] / nz)
+    import numpy as np
     qs = np.ascontiguousarray(q0[:, :W, :, :W])
     vs = np.ascontiguousarray(v[:, :W, :, :W])
     op.jv_cstep(sub, qs, vs)            # warm-up
@@ -63,7 +66,7 @@ def cpu_baseline(prob, q0, v):
         op.jv_cstep(sub, qs, vs)
         reps += 1
         el = time.perf_counter() - t0
-        if el > 10.0 or reps >= 50:
+        if el > 10.0 or reps >= 2000:
             break
     rate = reps * sub.npts / el / 1e9
     try:
@@ -71,8 +74,8 @@ def cpu_baseline(prob, q0, v):
     except AttributeError:
         cores = os.cpu_count()
     return {"value": rate, "unit": "Gpt/s", "cores": 1, "kind": "oracle",
-            "sample": "complex-step Jv (NumPy, one thread for elementwise work) on a "
-                      "%dx%dx%d window of the workload, %d repetitions in %.1f s; host has %d cores"
+            "sample": "complex-step Jv (NumPy, elementwise work on one thread) on a %dx%dx%d "
+                      "window of the workload, %d repetitions in %.1f s; the host has %d cores"
                       % (W, ny, W, reps, el, cores)}
 
 
@@ -83,13 +86,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a device copy of known size (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(the sharding design is documented, not built).", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import synth
@@ -106,7 +110,7 @@ def main():
     npts = prob.npts
     nv = prob.nv
 
-    sec = timed_launches(lambda: ctx.op_apply(x, y, shift=0.2), args.steps, args.warmup, torch)
+    sec = timed(lambda: ctx.op_apply(x, y, shift=0.2), args.steps, args.warmup, torch)
     per = sec / args.steps
     value = npts / per / 1e9
     alg_bytes = 3 * nv * 8 * npts
@@ -114,8 +118,16 @@ def main():
 
     x32 = x.float()
     y32 = torch.empty_like(x32)
-    sec32 = timed_launches(lambda: ctx.op_apply(x32, y32, shift=0.2), args.steps, args.warmup, torch)
+    sec32 = timed(lambda: ctx.op_apply(x32, y32, shift=0.2), args.steps, args.warmup, torch)
     per32 = sec32 / args.steps
+
+    if args.calib_copy:
+        # device copy of known size, 16x the 256 MB last-level cache: reads and
+        # writes 4 GiB each (the reference for the rocprof byte counters)
+        ca = torch.ones(512 * 1024 * 1024, dtype=torch.float64, device=dev)
+        cb = torch.empty_like(ca)
+        timed(lambda: cb.copy_(ca), 2, 0, torch)
+        del ca, cb
 
     out = {
         "metric": METRIC,
@@ -136,46 +148,75 @@ def main():
                    "grid": [256, 128, 128], "nv": nv, "shift": 0.2},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "jv (FP64, 3D)", "alg_bytes_per_point": 3 * nv * 8},
+                     "kernel": "jv_fast_kernel<double,3>", "alg_bytes_per_point": 3 * nv * 8},
         "fp32_jv": {"gpts": npts / per32 / 1e9, "ms": per32 * 1e3,
                     "achieved_GBs": 3 * nv * 4 * npts / per32 / 1e9},
     }
     if args.extras:
-        out["extras"] = extras(torch, dev)
+        out["extras"] = extras(torch, dev, ctx, prob)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(prob, q0, v)
     print(json.dumps(out))
 
 
-def extras(torch, dev):
+def extras(torch, dev, ctx3, prob3):
     """Secondary measurements (not the headline value)."""
     import synth
-    from paper_1502_03701_amd import SA_MIXED, Context, arnoldi_eigs
+    from paper_1502_03701_amd import SA_F32, SA_MIXED, Context, arnoldi_eigs
     res = {}
+
+    def wall(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return r, time.perf_counter() - t0
+
+    # block-Jacobi of the 3D grid: 4x4x1-cell blocks x 5 vars = 80x80, 262144
+    # blocks, 8 shifts 0.05..0.40, FP32 factors
+    shifts = synth.config3_shifts()
+    _, t_setup = wall(lambda: ctx3.precond_setup(shifts, 4, 4, 1, diag_add=0.1, noise_std=0.01, seed=3))
+    r = torch.from_numpy(synth.random_vector(prob3, 3).ravel()).to(dev)
+    r32 = r.float()
+    z32 = torch.empty_like(r32)
+    t_apply = timed(lambda: ctx3.precond_apply(0, r32, z32), 5, 1, torch) / 5
+    nblocks = prob3.npts // 16
+    res["bjac_256x128x128_8shifts"] = {
+        "setup_s": t_setup, "nblocks": nblocks, "nb": 80,
+        "apply_ms_per_shift": t_apply * 1e3,
+        "apply_factor_GBs": nblocks * 80 * 80 * 4 / t_apply / 1e9}
+    # 8 shifts advanced together: one GMRES(30) cycle, FP32, preconditioned vs not
+    B = torch.from_numpy(synth.random_vector(prob3, 4, nrhs=8).ravel()).to(dev).float()
+    for use_pc in (False, True):
+        X = torch.zeros_like(B)
+        (rc, info), el = wall(lambda: ctx3.gmres_solve(shifts, B, X, restart=30, tol=1e-6, max_matvec=31,
+                                                      use_precond=use_pc, prec=SA_F32))
+        res["gmres30_fp32_8shifts_" + ("bjac" if use_pc else "plain")] = {
+            "seconds_one_cycle": el, "relres": [i["relres"] for i in info], "iters": [i["iters"] for i in info]}
+    del B, X
     # GMRES(40) iteration cost at 512 x 512 (2D, FP64), capped solve
     p1 = synth.config1()
     c1 = Context()
     c1.base_set(p1, torch.from_numpy(synth.base_flow(p1).ravel()).to(dev))
     b = torch.from_numpy(synth.random_vector(p1, 1).ravel()).to(dev)
     x = torch.zeros_like(b)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    rc, info = c1.gmres_solve([0.2], b, x, restart=40, tol=1e-10, max_matvec=2000)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
+    (rc, info), el = wall(lambda: c1.gmres_solve([0.2], b, x, restart=40, tol=1e-10, max_matvec=2000))
     res["gmres40_512x512"] = {"iters": info[0]["iters"], "relres": info[0]["relres"],
                               "ms_per_iter": el / max(1, info[0]["iters"]) * 1e3}
+    # 8 shifts in lockstep at 512 x 512: one launch per kernel for all shifts
+    B8 = torch.from_numpy(synth.random_vector(p1, 5, nrhs=8).ravel()).to(dev)
+    X8 = torch.zeros_like(B8)
+    (rc, info), el = wall(lambda: c1.gmres_solve(shifts, B8, X8, restart=40, tol=1e-10, max_matvec=401))
+    res["gmres40_512x512_8shifts"] = {"ms_per_iter_all_shifts": el / max(1, info[0]["iters"]) * 1e3,
+                                      "iters": info[0]["iters"]}
     # time to eigenpairs, FP64 vs mixed, small case (KH pair)
     pe = synth.mixing_layer_2d(32, 32, 0.5, 1000.0)
     ce = Context()
     ce.base_set(pe, torch.from_numpy(synth.base_flow(pe).ravel()).to(dev))
     v0 = torch.from_numpy(synth.random_vector(pe, 0).ravel()).to(dev)
     for name, prec in (("fp64", 0), ("mixed", SA_MIXED)):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        rc, r = arnoldi_eigs([ce], [v0], nev=2, ncv=16, tol=1e-10, restart=40, lin_tol=1e-12,
-                             prec=prec, inner_tol=1e-4, max_outer=20)
-        el = time.perf_counter() - t0
+        (rc, r), el = wall(lambda: arnoldi_eigs([ce], [v0], nev=2, ncv=16, tol=1e-10, restart=40, lin_tol=1e-12,
+                                                prec=prec, inner_tol=1e-4, max_outer=20))
         res["eigs_kh_32x32_" + name] = {"seconds": el, "nconv": r[0]["nconv"],
                                         "lam": [[l.real, l.imag] for l in r[0]["lam"]],
                                         "n_matvec": r[0]["n_matvec"]}

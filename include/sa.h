@@ -79,6 +79,10 @@ typedef struct {
                           MIXED: FP64 iterative refinement around FP32 GMRES */
   double inner_tol;    /* MIXED: relative tolerance of each inner solve     */
   int max_outer;       /* MIXED: maximum refinement sweeps                  */
+  int use_graph;       /* 1: each restart cycle (all its kernels, all shifts)
+                          is captured once into a hipGraph and replayed; the
+                          graph is cached in the context.  0: plain launches.
+                          Results are identical either way.                 */
 } sa_gmres_opts;
 
 typedef struct {

@@ -298,22 +298,22 @@ inline unsigned blocks_for(long long n, int threads) { return (unsigned)((n + th
 
 template <typename R>
 hipError_t precond_apply(Ctx* c, int ishift, int nrhs, const R* r, R* z, const int* active, int shift_step,
-                         long long sV, long long sA) {
+                         long long sV, long long sA, hipStream_t s) {
   BLayout L = layout_of(c);
   dim3 grid((unsigned)L.nblocks, (unsigned)nrhs);
   if (sV == 0) sV = c->n;
   if (c->pc_f64)
-    apply_kernel<double, R><<<grid, 64, 0, c->stream>>>(L, (const double*)c->pc_lu, c->pc_perm, ishift, shift_step,
+    apply_kernel<double, R><<<grid, 64, 0, s>>>(L, (const double*)c->pc_lu, c->pc_perm, ishift, shift_step,
                                                         r, z, sV, active, sA);
   else
-    apply_kernel<float, R><<<grid, 64, 0, c->stream>>>(L, (const float*)c->pc_lu, c->pc_perm, ishift, shift_step,
+    apply_kernel<float, R><<<grid, 64, 0, s>>>(L, (const float*)c->pc_lu, c->pc_perm, ishift, shift_step,
                                                        r, z, sV, active, sA);
   return hipGetLastError();
 }
 template hipError_t precond_apply<double>(Ctx*, int, int, const double*, double*, const int*, int, long long,
-                                          long long);
+                                          long long, hipStream_t);
 template hipError_t precond_apply<float>(Ctx*, int, int, const float*, float*, const int*, int, long long,
-                                         long long);
+                                         long long, hipStream_t);
 
 }  // namespace sa
 
@@ -330,6 +330,7 @@ extern "C" int sa_precond_setup(sa_ctx* c, const sa_precond_opts* o, int nshift,
   if (o->factor_prec != SA_F32 && o->factor_prec != SA_F64)
     return c->fail(SA_EINVAL, "sa_precond_setup: factor precision must be SA_F32 or SA_F64");
   c->has_precond = false;
+  c->drop_graphs();
   c->pc_bx = o->bx;
   c->pc_by = o->by;
   c->pc_bz = bz;
@@ -402,9 +403,9 @@ extern "C" int sa_precond_apply(sa_ctx* c, sa_prec prec, int ishift, int nrhs, c
     return c->fail(SA_EINVAL, "sa_precond_apply: bad shift index, nrhs or pointer");
   hipError_t e;
   if (prec == SA_F64)
-    e = precond_apply<double>(c, ishift, nrhs, (const double*)r_dev, (double*)z_dev, nullptr);
+    e = precond_apply<double>(c, ishift, nrhs, (const double*)r_dev, (double*)z_dev, nullptr, 0, 0, 0, c->stream);
   else if (prec == SA_F32)
-    e = precond_apply<float>(c, ishift, nrhs, (const float*)r_dev, (float*)z_dev, nullptr);
+    e = precond_apply<float>(c, ishift, nrhs, (const float*)r_dev, (float*)z_dev, nullptr, 0, 0, 0, c->stream);
   else
     return c->fail(SA_EINVAL, "sa_precond_apply: precision must be SA_F64 or SA_F32");
   if (e != hipSuccess) return c->hip_fail(e, "sa_precond_apply");

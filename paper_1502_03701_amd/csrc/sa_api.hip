@@ -31,6 +31,7 @@ void* Ctx::buffer(const std::string& name, size_t bytes, bool zero) {
   auto it = bufs.find(name);
   if (it != bufs.end() && it->second.bytes >= bytes) return it->second.ptr;
   if (it != bufs.end()) {
+    drop_graphs();   // a cached graph may reference the old address
     hipStreamSynchronize(stream);
     hipFree(it->second.ptr);
     bufs.erase(it);
@@ -42,8 +43,17 @@ void* Ctx::buffer(const std::string& name, size_t bytes, bool zero) {
   return p;
 }
 
+void Ctx::drop_graphs() {
+  if (graphs.empty()) return;
+  hipStreamSynchronize(stream);
+  for (auto& g : graphs) hipGraphExecDestroy(g.exec);
+  graphs.clear();
+}
+
 Ctx::~Ctx() {
-  if (stream) hipStreamSynchronize(stream);
+  hipStreamSynchronize(stream);
+  drop_graphs();
+  if (cap_stream) hipStreamDestroy(cap_stream);
   for (auto& kv : bufs) hipFree(kv.second.ptr);
 }
 
@@ -107,6 +117,7 @@ int sa_base_set(sa_ctx* c, const sa_problem* pb, const double* q0_dev) {
   const size_t nf = (size_t)(c->nv + 3) * op.npts;
   c->has_base = false;
   c->has_precond = false;
+  c->drop_graphs();
   c->base64 = (double*)c->buffer("base64", nf * sizeof(double));
   c->base32 = (float*)c->buffer("base32", nf * sizeof(float));
   const size_t nbd = (size_t)base_data_fields(op.ndim) * op.npts;

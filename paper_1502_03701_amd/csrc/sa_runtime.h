@@ -4,6 +4,7 @@
 #include <cstdarg>
 #include <map>
 #include <string>
+#include <vector>
 
 #include "../../include/sa.h"
 #include "blas.h"
@@ -15,6 +16,13 @@ namespace sa {
 struct Buf {
   void* ptr;
   size_t bytes;
+};
+
+// An instantiated hipGraph of one GMRES restart cycle and the launch
+// parameters it was captured with (buffer addresses, sizes, shifts).
+struct CycleGraph {
+  std::vector<unsigned char> key;
+  hipGraphExec_t exec = nullptr;
 };
 
 struct Ctx {
@@ -47,6 +55,12 @@ struct Ctx {
   int* pc_perm = nullptr;  // [nshift][nblocks][nb] row permutation of the pivoting
   bool pc_f64 = false;     // factor precision
 
+  // cached cycle graphs (captured on cap_stream, launched on stream); dropped
+  // whenever the base state or the preconditioner changes
+  std::vector<CycleGraph> graphs;
+  hipStream_t cap_stream = nullptr;
+  void drop_graphs();
+
   int fail(int code, const char* fmt, ...);
   int hip_fail(hipError_t e, const char* where);
   // Named, context-owned device buffer of at least `bytes` (kept across calls).
@@ -62,8 +76,8 @@ int solve_ir(Ctx* c, const sa_gmres_opts& o, double sigma, const double* b, doub
 
 // block-Jacobi apply z = P M^{-1} r (bjac.hip)
 template <typename R>
-hipError_t precond_apply(Ctx* c, int ishift, int nrhs, const R* r, R* z, const int* active, int shift_step = 0,
-                         long long sV = 0, long long sA = 0);
+hipError_t precond_apply(Ctx* c, int ishift, int nrhs, const R* r, R* z, const int* active, int shift_step,
+                         long long sV, long long sA, hipStream_t s);
 
 }  // namespace sa
 

@@ -55,6 +55,21 @@ const float* bdata_of<float>(const Ctx* c) {
 
 }  // namespace
 
+// Key of a cycle graph: everything the captured launches bake in.
+template <typename T>
+void put(std::vector<unsigned char>& k, const T& v) {
+  const unsigned char* b = reinterpret_cast<const unsigned char*>(&v);
+  k.insert(k.end(), b, b + sizeof(T));
+}
+
+hipGraphExec_t find_graph(Ctx* c, const std::vector<unsigned char>& key) {
+  for (auto& g : c->graphs)
+    if (g.key == key) return g.exec;
+  return nullptr;
+}
+
+constexpr size_t MAX_GRAPHS = 16;
+
 template <typename R>
 int solve_gmres(Ctx* c, const sa_gmres_opts& o, int nsys, const double* sigma, const R* b, R* x, int pc_shift0,
                 sa_gmres_info* info, const std::string& tag) {
@@ -62,6 +77,7 @@ int solve_gmres(Ctx* c, const sa_gmres_opts& o, int nsys, const double* sigma, c
   const long long n = c->n;
   const int m = o.restart;
   const bool pc = pc_shift0 >= 0;
+  const bool graph = o.use_graph != 0;
   const long long sv = n * (m + 1);   // basis stride between systems
   R* V = (R*)c->buffer(tag + "V", sizeof(R) * sv * nsys);
   R* Z = pc ? (R*)c->buffer(tag + "Z", sizeof(R) * sv * nsys) : V;
@@ -70,9 +86,20 @@ int solve_gmres(Ctx* c, const sa_gmres_opts& o, int nsys, const double* sigma, c
   double* sig = (double*)c->buffer(tag + "sigma", sizeof(double) * nsys, false);
   Blas<R> bl;
   bl.partial = (double*)c->buffer(tag + "partial", sizeof(double) * RED_BLOCKS * PARTIAL_LD * nsys);
-  if (!V || !Z || !T || !st || !sig || !bl.partial) return c->fail(SA_ENOMEM, "gmres: out of device memory");
+  // a captured cycle works on context-owned copies of b and x, so that one
+  // graph serves every caller buffer
+  R* X = graph ? (R*)c->buffer(tag + "X", sizeof(R) * n * nsys, false) : x;
+  R* B = graph ? (R*)c->buffer(tag + "B", sizeof(R) * n * nsys, false) : const_cast<R*>(b);
+  if (!V || !Z || !T || !st || !sig || !bl.partial || !X || !B)
+    return c->fail(SA_ENOMEM, "gmres: out of device memory");
+  if (graph && !c->cap_stream) {
+    hipError_t e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return c->hip_fail(e, "gmres capture stream");
+  }
   hipError_t e = hipMemcpyAsync(sig, sigma, sizeof(double) * nsys, hipMemcpyHostToDevice, s);
-  if (e != hipSuccess) return c->hip_fail(e, "gmres shifts");
+  if (e == hipSuccess && graph) e = hipMemcpyAsync(X, x, sizeof(R) * n * nsys, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess && graph) e = hipMemcpyAsync(B, b, sizeof(R) * n * nsys, hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) return c->hip_fail(e, "gmres inputs");
   const R* base = base_of<R>(c);
   const R* bdata = bdata_of<R>(c);
   const int* act = &st->t.active;
@@ -86,18 +113,92 @@ int solve_gmres(Ctx* c, const sa_gmres_opts& o, int nsys, const double* sigma, c
   Batch bx = bb;                  // x += Z y: basis stride for Z, n for x
   bx.wvec = n;
 
+  // r = b - (J - sigma I) x -> V_s[:,0]; beta, convergence and budget tests
+  auto start_cycle = [&](hipStream_t q) -> hipError_t {
+    hipError_t r = launch_jv_batch<R>(c->op, base, bdata, X, T, nsys, n, n, sigma, sig, nullptr, 0, q);
+    if (r != hipSuccess) return r;
+    bl.residual(n, B, T, V, &st->t.rnorm2, nullptr, q, bb, n, n);
+    gstate_cycle_start(st, nsys, q);
+    return hipGetLastError();
+  };
+  // m Arnoldi steps, the least-squares solve and x += Z y
+  auto arnoldi_cycle = [&](hipStream_t q) -> hipError_t {
+    bl.scale(n, V, V, &st->t.inv, act, q, bb);
+    for (int j = 0; j < m; ++j) {
+      R* vj = V + (long long)j * n;
+      R* w = V + (long long)(j + 1) * n;
+      const R* zj = vj;
+      if (pc) {
+        R* zz = Z + (long long)j * n;
+        hipError_t r = precond_apply<R>(c, pc_shift0, nsys, vj, zz, act, 1, sv, GS_INTS, q);
+        if (r != hipSuccess) return r;
+        zj = zz;
+      }
+      hipError_t r = launch_jv_batch<R>(c->op, base, bdata, zj, w, nsys, sv, sv, sigma, sig, act, GS_INTS, q);
+      if (r != hipSuccess) return r;
+      // CGS pass 1: d1 = V[0..j]^T w and ||w||^2
+      bl.multidot(n, V, n, j + 2, w, st->d1, false, act, q, bb);
+      // pass 2: w -= V d1, d2 = V^T w
+      bl.update(n, V, n, j + 1, st->d1, -1.0, w, w, 1, st->d2, false, act, q, bb);
+      // pass 3: w -= V d2, wn2 = ||w||^2
+      bl.update(n, V, n, j + 1, st->d2, -1.0, w, w, 2, &st->wn2, false, act, q, bb);
+      gstate_step(st, nsys, j, q);
+      bl.scale(n, w, w, &st->t.inv, act, q, bb);
+    }
+    gstate_finish(st, nsys, q);
+    // x += Z y  (Z = V without preconditioning)
+    bl.update(n, Z, n, m, st->y, 1.0, X, X, 0, nullptr, false, &st->t.have_update, q, bx);
+    return hipGetLastError();
+  };
+
+  // one graph = one cycle followed by the next cycle's start
+  hipGraphExec_t exec = nullptr;
+  if (graph) {
+    std::vector<unsigned char> key;
+    put(key, (int)sizeof(R));
+    put(key, nsys);
+    put(key, m);
+    put(key, pc_shift0);
+    put(key, n);
+    for (const void* ptr : {(const void*)V, (const void*)Z, (const void*)T, (const void*)st, (const void*)sig,
+                            (const void*)bl.partial, (const void*)X, (const void*)B, (const void*)base,
+                            (const void*)bdata, (const void*)c->pc_lu, (const void*)c->pc_perm})
+      put(key, ptr);
+    for (int i = 0; i < nsys; ++i) put(key, sigma[i]);
+    exec = find_graph(c, key);
+    if (!exec) {
+      hipGraph_t g = nullptr;
+      e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+      if (e != hipSuccess) return c->hip_fail(e, "gmres begin capture");
+      hipError_t ec = arnoldi_cycle(c->cap_stream);
+      if (ec == hipSuccess) ec = start_cycle(c->cap_stream);
+      e = hipStreamEndCapture(c->cap_stream, &g);
+      if (ec != hipSuccess) {
+        if (g) hipGraphDestroy(g);
+        return c->hip_fail(ec, "gmres capture");
+      }
+      if (e != hipSuccess) return c->hip_fail(e, "gmres end capture");
+      e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+      hipGraphDestroy(g);
+      if (e != hipSuccess) return c->hip_fail(e, "gmres graph instantiate");
+      if (c->graphs.size() >= MAX_GRAPHS) {
+        hipStreamSynchronize(s);
+        hipGraphExecDestroy(c->graphs.front().exec);
+        c->graphs.erase(c->graphs.begin());
+      }
+      c->graphs.push_back(CycleGraph{key, exec});
+    }
+  }
+
   for (int i = 0; i < nsys; ++i) info[i] = sa_gmres_info{};
   gstate_init(st, nsys, o.tol, m, o.max_matvec, s);
-  bl.nrm2sq(n, b, &st->t.bnorm2, nullptr, s, bn);
+  bl.nrm2sq(n, B, &st->t.bnorm2, nullptr, s, bn);
   gstate_set_bnorm(st, nsys, s);
+  e = start_cycle(s);
+  if (e != hipSuccess) return c->hip_fail(e, "gmres residual");
   std::vector<GTail> h;
   int cycles = 0;
   for (;;) {
-    // r = b - (J - sigma I) x  -> V_s[:,0]
-    e = launch_jv_batch<R>(c->op, base, bdata, x, T, nsys, n, n, sigma, sig, nullptr, 0, s);
-    if (e != hipSuccess) return c->hip_fail(e, "gmres residual");
-    bl.residual(n, b, T, V, &st->t.rnorm2, nullptr, s, bb, n, n);
-    gstate_cycle_start(st, nsys, s);
     e = read_tails(st, nsys, h, s);
     if (e != hipSuccess) return c->hip_fail(e, "gmres status");
     bool any_active = false;
@@ -115,34 +216,19 @@ int solve_gmres(Ctx* c, const sa_gmres_opts& o, int nsys, const double* sigma, c
       any_active = any_active || h[i].active;
     }
     if (!any_active) break;
-    bl.scale(n, V, V, &st->t.inv, act, s, bb);
-    for (int j = 0; j < m; ++j) {
-      R* vj = V + (long long)j * n;
-      R* w = V + (long long)(j + 1) * n;
-      const R* zj = vj;
-      if (pc) {
-        R* zz = Z + (long long)j * n;
-        e = precond_apply<R>(c, pc_shift0, nsys, vj, zz, act, 1, sv, GS_INTS);
-        if (e != hipSuccess) return c->hip_fail(e, "gmres precond");
-        zj = zz;
-      }
-      e = launch_jv_batch<R>(c->op, base, bdata, zj, w, nsys, sv, sv, sigma, sig, act, GS_INTS, s);
-      if (e != hipSuccess) return c->hip_fail(e, "gmres jv");
-      // CGS pass 1: d1 = V[0..j]^T w and ||w||^2
-      bl.multidot(n, V, n, j + 2, w, st->d1, false, act, s, bb);
-      // pass 2: w -= V d1, d2 = V^T w
-      bl.update(n, V, n, j + 1, st->d1, -1.0, w, w, 1, st->d2, false, act, s, bb);
-      // pass 3: w -= V d2, wn2 = ||w||^2
-      bl.update(n, V, n, j + 1, st->d2, -1.0, w, w, 2, &st->wn2, false, act, s, bb);
-      gstate_step(st, nsys, j, s);
-      bl.scale(n, w, w, &st->t.inv, act, s, bb);
+    if (graph) {
+      e = hipGraphLaunch(exec, s);
+      if (e != hipSuccess) return c->hip_fail(e, "gmres graph launch");
+    } else {
+      e = arnoldi_cycle(s);
+      if (e == hipSuccess) e = start_cycle(s);
+      if (e != hipSuccess) return c->hip_fail(e, "gmres cycle");
     }
-    gstate_finish(st, nsys, s);
-    // x += Z y  (Z = V without preconditioning)
-    bl.update(n, Z, n, m, st->y, 1.0, x, x, 0, nullptr, false, &st->t.have_update, s, bx);
-    e = hipGetLastError();
-    if (e != hipSuccess) return c->hip_fail(e, "gmres cycle");
     ++cycles;
+  }
+  if (graph) {
+    e = hipMemcpyAsync(x, X, sizeof(R) * n * nsys, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return c->hip_fail(e, "gmres solution");
   }
   bool all = true;
   for (int i = 0; i < nsys; ++i) all = all && info[i].status == SA_OK;
