@@ -243,8 +243,9 @@ hipError_t launch_base_derive(const OpParams& p, double* base, float* base32, in
 
 namespace sa {
 
-// 0: perturbation-only queue kernel (jv_fast.hip), 1: tiled, base state
-// differentiated on the fly, 2: reference, 3: tiled with precomputed base data
+// 0: perturbation-only kernel of the precision, 1: tiled, base state
+// differentiated on the fly, 2: reference, 3: tiled with precomputed base
+// data, 4: prefetching perturbation-only kernel, 5: staging one
 static int kernel_choice() {
   static const int k = [] {
     const char* e = std::getenv("SA_JV_KERNEL");
@@ -252,9 +253,23 @@ static int kernel_choice() {
     if (std::strcmp(e, "onthefly") == 0) return 1;
     if (std::strcmp(e, "reference") == 0) return 2;
     if (std::strcmp(e, "tiled") == 0) return 3;
+    if (std::strcmp(e, "prefetch") == 0) return 4;
+    if (std::strcmp(e, "stage") == 0) return 5;
     return 0;
   }();
   return k;
+}
+
+static bool pert_kernel(int k) { return k == 0 || k == 4 || k == 5; }
+
+template <typename R>
+hipError_t launch_jv_pert(const OpParams& p, const R* base, const R* bdata, const R* x, R* y, int nrhs, R shift,
+                          const int* active, hipStream_t s, long long sX, long long sY, const double* shifts,
+                          long long sA) {
+  const int k = kernel_choice();
+  const bool prefetch = k == 4 || (k != 5 && sizeof(R) == 8);
+  if (prefetch) return launch_jv_prefetch<R>(p, base, bdata, x, y, nrhs, shift, active, s, sX, sY, shifts, sA);
+  return launch_jv_stage<R>(p, base, bdata, x, y, nrhs, shift, active, s, sX, sY, shifts, sA);
 }
 
 template <typename R>
@@ -262,7 +277,7 @@ hipError_t launch_jv(const OpParams& p, const R* base, const R* bdata, const R* 
                      const int* active, hipStream_t s) {
   const int k = kernel_choice();
   if (k == 2) return launch_jv_direct<R>(p, base, x, y, nrhs, shift, active, s);
-  if (k == 0 && bdata) return launch_jv_fast<R>(p, base, bdata, x, y, nrhs, shift, active, s);
+  if (pert_kernel(k) && bdata) return launch_jv_pert<R>(p, base, bdata, x, y, nrhs, shift, active, s);
   return launch_jv_tiled<R>(p, base, x, y, nrhs, shift, active, k == 1 ? nullptr : bdata, s);
 }
 
@@ -270,8 +285,8 @@ template <typename R>
 hipError_t launch_jv_batch(const OpParams& p, const R* base, const R* bdata, const R* x, R* y, int nsys,
                            long long sX, long long sY, const double* shifts_host, const double* shifts_dev,
                            const int* active, long long sA, hipStream_t s) {
-  if (kernel_choice() == 0 && bdata)
-    return launch_jv_fast<R>(p, base, bdata, x, y, nsys, R(0), active, s, sX, sY, shifts_dev, sA);
+  if (pert_kernel(kernel_choice()) && bdata)
+    return launch_jv_pert<R>(p, base, bdata, x, y, nsys, R(0), active, s, sX, sY, shifts_dev, sA);
   for (int r = 0; r < nsys; ++r) {
     hipError_t e = launch_jv<R>(p, base, bdata, x + r * sX, y + r * sY, 1, R(shifts_host[r]),
                                 active ? active + r * sA : nullptr, s);

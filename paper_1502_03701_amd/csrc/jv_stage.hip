@@ -1,5 +1,5 @@
-// Perturbation-only operator kernel y = (J(q0) - shift I) x, the default
-// path once the base state's derivative data exist (sa_base_set computes them
+// Perturbation-only operator kernel y = (J(q0) - shift I) x (staging
+// variant, the FP32 default), used once the base state's derivative data exist (sa_base_set computes them
 // with the tiled kernel of jv_tiled.hip).  Same discrete operator and the
 // same pointwise algebra (jv_common.h); organised for throughput:
 //   * a workgroup owns a TX x TY column tile and marches over NZC planes;
@@ -13,7 +13,11 @@
 //     G_z = D2_z w + D_x(D_z u) + D_y(D_z v)); the z-derivatives on the halo
 //     columns are formed from direct loads by spare threads;
 //   * loads are branch-free (wall rows are clamped and masked), indices are
-//     32-bit within a field.
+//     32-bit within a field;
+//   * workgroups are numbered so that tiles adjacent in x run on the same
+//     XCD (and share its L2).
+// In FP32 this kernel fits two waves per SIMD, which hides latency better
+// than the explicit prefetching of jv_prefetch.hip; in FP64 it does not.
 #include "jv_common.h"
 
 namespace sa {
@@ -26,19 +30,36 @@ constexpr int PH = TY + 6;
 constexpr int NT = TX * TY;
 constexpr int NZC = 16;
 
-__device__ __forceinline__ int wrapi(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
+constexpr int NXCD = 8;
+
+// Periodic index of a in [-n, 2n).  Indices beyond n + 3 only feed points
+// outside the grid (tiles are padded), so they are clamped into range.
+__device__ __forceinline__ int wrapi(int a, int n) { return a < 0 ? a + n : (a >= n ? min(a - n, n - 1) : a); }
 
 // A batch of systems shares one launch: blockIdx.z = sys * zchunks + chunk;
 // system sys reads x + sys*sV, writes y + sys*sV, uses shifts[sys] (or the
 // scalar shift) and the flag active[sys*sA].
 template <typename R, int ND>
-__global__ void __launch_bounds__(NT) jv_fast_kernel(OpParams op, const R* __restrict__ base,
+__global__ void __launch_bounds__(NT) jv_stage_kernel(OpParams op, const R* __restrict__ base,
                                                      const R* __restrict__ bdata, const R* __restrict__ x,
                                                      R* __restrict__ y, R shift, const int* __restrict__ active,
                                                      long long strideX, long long strideY,
-                                                     const double* __restrict__ shifts, long long sA, int zchunks) {
-  const int sys = blockIdx.z / zchunks;
-  const int zc = blockIdx.z % zchunks;
+                                                     const double* __restrict__ shifts, long long sA, int zchunks,
+                                                     int gx, int gy, int ntot) {
+  // XCD-aware numbering: hardware block L runs on XCD L % 8; each XCD gets a
+  // contiguous range of logical tiles (x fastest).
+  int lb;
+  {
+    const int L = blockIdx.x;
+    const int per = ntot / NXCD, rem = ntot % NXCD;
+    const int xcd = L % NXCD, idx = L / NXCD;
+    lb = xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
+  }
+  const int bxi = lb % gx;
+  const int byi = (lb / gx) % gy;
+  const int bz = lb / (gx * gy);
+  const int sys = bz / zchunks;
+  const int zc = bz % zchunks;
   if (active && !active[sys * sA]) return;
   x += sys * strideX;
   y += sys * strideY;
@@ -51,7 +72,7 @@ __global__ void __launch_bounds__(NT) jv_fast_kernel(OpParams op, const R* __res
   const int tid = threadIdx.x;
   const int ti = tid % TX, tj = tid / TX;
   const int nx = op.nx, ny = op.ny, nz = op.nz;
-  const int i0 = blockIdx.x * TX, j0 = blockIdx.y * TY;
+  const int i0 = bxi * TX, j0 = byi * TY;
   const int i = i0 + ti, j = j0 + tj;
   const int plane = nx * ny;
   const long long npts = op.npts;
@@ -279,25 +300,32 @@ __global__ void __launch_bounds__(NT) jv_fast_kernel(OpParams op, const R* __res
 }  // namespace
 
 template <typename R>
-hipError_t launch_jv_fast(const OpParams& p, const R* base, const R* bdata, const R* x, R* y, int nrhs, R shift,
+hipError_t launch_jv_stage(const OpParams& p, const R* base, const R* bdata, const R* x, R* y, int nrhs, R shift,
                           const int* active, hipStream_t s, long long sX, long long sY, const double* shifts,
                           long long sA) {
   const long long ndof = (long long)(p.ndim + 2) * p.npts;
+  // 32-bit indices within the base data (the widest per-point array)
+  if ((long long)base_data_fields(p.ndim) * p.npts >= (1LL << 31)) return hipErrorInvalidValue;
   const int zchunks = p.ndim == 3 ? (p.nz + NZC - 1) / NZC : 1;
   if (sX == 0) sX = ndof;   // right-hand sides one after another
   if (sY == 0) sY = ndof;
-  dim3 grid((p.nx + TX - 1) / TX, (p.ny + TY - 1) / TY, zchunks * nrhs);
+  const int gx = (p.nx + TX - 1) / TX, gy = (p.ny + TY - 1) / TY;
+  const long long ntot = (long long)gx * gy * zchunks * nrhs;
+  if (ntot >= (1LL << 31)) return hipErrorInvalidValue;
+  dim3 grid((unsigned)ntot);
   if (p.ndim == 2)
-    jv_fast_kernel<R, 2><<<grid, NT, 0, s>>>(p, base, bdata, x, y, shift, active, sX, sY, shifts, sA, zchunks);
+    jv_stage_kernel<R, 2><<<grid, NT, 0, s>>>(p, base, bdata, x, y, shift, active, sX, sY, shifts, sA, zchunks, gx,
+                                              gy, (int)ntot);
   else
-    jv_fast_kernel<R, 3><<<grid, NT, 0, s>>>(p, base, bdata, x, y, shift, active, sX, sY, shifts, sA, zchunks);
+    jv_stage_kernel<R, 3><<<grid, NT, 0, s>>>(p, base, bdata, x, y, shift, active, sX, sY, shifts, sA, zchunks, gx,
+                                              gy, (int)ntot);
   return hipGetLastError();
 }
 
-template hipError_t launch_jv_fast<double>(const OpParams&, const double*, const double*, const double*, double*,
+template hipError_t launch_jv_stage<double>(const OpParams&, const double*, const double*, const double*, double*,
                                            int, double, const int*, hipStream_t, long long, long long,
                                            const double*, long long);
-template hipError_t launch_jv_fast<float>(const OpParams&, const float*, const float*, const float*, float*, int,
+template hipError_t launch_jv_stage<float>(const OpParams&, const float*, const float*, const float*, float*, int,
                                           float, const int*, hipStream_t, long long, long long, const double*,
                                           long long);
 

@@ -29,9 +29,11 @@ constexpr int PH = TY + 6;
 constexpr int NT = TX * TY;
 constexpr int NZC = 8;       // z planes per workgroup
 
+// Periodic index of a in [-n, 2n).  Indices beyond n + 3 only feed points
+// outside the grid (tiles are padded), so they are clamped into range.
 template <typename R>
 __device__ __forceinline__ int wrap(int a, int n) {
-  return a < 0 ? a + n : (a >= n ? a - n : a);
+  return a < 0 ? a + n : (a >= n ? min(a - n, n - 1) : a);
 }
 
 // MODE_FULL: perturbation and base stencils every call.

@@ -34,11 +34,22 @@ template <typename R>
 hipError_t launch_jv_tiled(const OpParams& p, const R* base, const R* x, R* y, int nrhs, R shift,
                            const int* active, const R* bdata, hipStream_t s);
 int base_data_fields(int ndim);
-// Perturbation-only kernel with a register z-queue (needs bdata).  nrhs
+// Perturbation-only kernels with a register z-queue (need bdata).  nrhs
 // systems in one launch: system r uses x/y + r*sV (sV = 0: n), the shift
 // shifts[r] (device array; null: the scalar shift) and active[r*sA].
+// launch_jv_prefetch (jv_prefetch.hip) prefetches the next plane and is the FP64
+// default; launch_jv_stage (jv_stage.hip) stages whole planes and is the FP32
+// default; launch_jv_pert picks by precision.
 template <typename R>
-hipError_t launch_jv_fast(const OpParams& p, const R* base, const R* bdata, const R* x, R* y, int nrhs, R shift,
+hipError_t launch_jv_prefetch(const OpParams& p, const R* base, const R* bdata, const R* x, R* y, int nrhs, R shift,
+                              const int* active, hipStream_t s, long long sX = 0, long long sY = 0,
+                              const double* shifts = nullptr, long long sA = 0);
+template <typename R>
+hipError_t launch_jv_stage(const OpParams& p, const R* base, const R* bdata, const R* x, R* y, int nrhs, R shift,
+                           const int* active, hipStream_t s, long long sX = 0, long long sY = 0,
+                           const double* shifts = nullptr, long long sA = 0);
+template <typename R>
+hipError_t launch_jv_pert(const OpParams& p, const R* base, const R* bdata, const R* x, R* y, int nrhs, R shift,
                           const int* active, hipStream_t s, long long sX = 0, long long sY = 0,
                           const double* shifts = nullptr, long long sA = 0);
 // A batch of systems: one launch with the default kernel, else one launch per
@@ -53,10 +64,12 @@ hipError_t launch_base_data(const OpParams& p, const double* base, double* bdata
 template <typename R>
 hipError_t launch_jv_direct(const OpParams& p, const R* base, const R* x, R* y, int nrhs, R shift,
                             const int* active, hipStream_t s);
-// Operator dispatch: the tiled kernel with precomputed base data (default),
-// the tiled kernel differentiating the base state every call
-// (SA_JV_KERNEL=onthefly) or the reference kernel (SA_JV_KERNEL=reference);
-// the variable is read once per process and serves to cross-check kernels.
+// Operator dispatch: the perturbation-only kernel of the precision (default),
+// one of them for both precisions (SA_JV_KERNEL=prefetch or stage), the tiled
+// kernel with precomputed base data (SA_JV_KERNEL=tiled), the tiled kernel
+// differentiating the base state every call (SA_JV_KERNEL=onthefly) or the
+// reference kernel (SA_JV_KERNEL=reference); the variable is read once per
+// process and serves to cross-check kernels.
 template <typename R>
 hipError_t launch_jv(const OpParams& p, const R* base, const R* bdata, const R* x, R* y, int nrhs, R shift,
                      const int* active, hipStream_t s);
