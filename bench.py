@@ -30,6 +30,34 @@ METRIC = "Gpt-updates/s of matrix-free Jv; time to 6 eigenpairs, mixed vs FP64 G
 HBM_PEAK_GBS = 8000.0
 
 
+COUNTERS = os.path.join(ROOT, "profiles", "jv_prefetch_fp64_256x128x128_hbm_counters.md")
+KERNEL_SOURCES = ["paper_1502_03701_amd/csrc/jv_prefetch.hip", "paper_1502_03701_amd/csrc/jv_common.h"]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the FP64 operator kernel from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary (calibrated against a copy of
+    known size), or None if the kernel source changed since it was taken."""
+    import hashlib
+    try:
+        text = open(COUNTERS).read()
+    except OSError:
+        return None
+    fields = {}
+    for line in text.splitlines():
+        if ":" in line:
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    key = "kernel_source_sha256 (jv_prefetch.hip + jv_common.h at measurement)"
+    if fields.get(key) != h.hexdigest() or "traffic_bytes_per_launch" not in fields:
+        return None
+    return int(fields["traffic_bytes_per_launch"])
+
+
 def timed(fn, steps, warmup, torch):
     """Seconds for `steps` calls, HIP events on the current stream (the
     stream the library launches on)."""
@@ -147,7 +175,7 @@ def main():
                                "one FP64 sa_op_apply per step",
                    "grid": [256, 128, 128], "nv": nv, "shift": 0.2},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": "jv_prefetch_kernel<double,3>", "alg_bytes_per_point": 3 * nv * 8},
         "fp32_jv": {"gpts": npts / per32 / 1e9, "ms": per32 * 1e3,
                     "achieved_GBs": 3 * nv * 4 * npts / per32 / 1e9},
