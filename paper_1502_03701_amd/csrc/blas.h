@@ -1,6 +1,7 @@
 // Launchers of the Krylov vector kernels (see blas.hip).
 #pragma once
 
+#include "gmres_small.h"
 #include "sa_internal.h"
 
 namespace sa {
@@ -19,20 +20,31 @@ struct Batch {
   long long w() const { return wvec < 0 ? vec : wvec; }
 };
 
-// A partial-sum workspace (nsys x RED_BLOCKS x ldp doubles) bound to the launchers.
+// Reductions over at most this many blocks finish inside the reducing kernel
+// (the last block to arrive sums the partials), larger ones in a second kernel.
+constexpr int FUSE_MAX_BLOCKS = 256;
+
+// A partial-sum workspace (nsys x RED_BLOCKS x ldp doubles) bound to the
+// launchers, and nsys zero-initialised arrival counters (null: reductions
+// always finish in a second kernel).
 template <typename R>
 struct Blas {
   double* partial = nullptr;
+  int* ticket = nullptr;
   int ldp = PARTIAL_LD;
 
   // out[0..ncol) (+)= V^T w, V column c at V + c*ldv.
   void multidot(long long n, const R* V, long long ldv, int ncol, const R* w, double* out, bool accumulate,
                 const int* active, hipStream_t s, const Batch& b = Batch()) const;
   // wout = w + hsign * V h; mode 0: nothing else, 1: out (+)= V^T wout,
-  // 2: out (+)= ||wout||^2.  wout may alias w.
-  void update(long long n, const R* V, long long ldv, int ncol, const double* h, double hsign, const R* w,
+  // 2: out (+)= ||wout||^2.  wout may alias w.  With mode 2 and a GMRES state
+  // array `step` (one per system, stride b.res), the Arnoldi step j of each
+  // system follows the norm (gstate_step semantics), fused into the same
+  // launch when the reduction is; returns whether it was fused (else the
+  // caller launches the step).
+  bool update(long long n, const R* V, long long ldv, int ncol, const double* h, double hsign, const R* w,
               R* wout, int mode, double* out, bool accumulate, const int* active, hipStream_t s,
-              const Batch& b = Batch()) const;
+              const Batch& b = Batch(), GState* step = nullptr, int step_j = 0) const;
   void nrm2sq(long long n, const R* x, double* out, const int* active, hipStream_t s,
               const Batch& b = Batch()) const;
   // r = b - y, out = ||r||^2; r uses the batch's vec stride, b and y their own

@@ -4,7 +4,9 @@
 //
 // Every reduction is deterministic: a fixed number of blocks (a function of
 // n only) writes one partial per block and per column in double precision,
-// and a second kernel sums the partials in a fixed order.  All kernels take
+// and the partials are summed in a fixed order, by a second kernel or, for
+// up to FUSE_MAX_BLOCKS blocks, by the last block of the reducing kernel to
+// finish (arrival counter); GMRES's Arnoldi step then runs in that block too.  All kernels take
 // an `active` device flag and return at once when it is zero, so that a whole
 // GMRES cycle can be enqueued ahead and stop on the device when it converges.
 // A batch of independent systems runs in one launch: blockIdx.z (blockIdx.y
@@ -46,6 +48,51 @@ __device__ __forceinline__ void block_sum_cols(double (&acc)[MAXC], int ncol, do
   }
 }
 
+// Where a reduction ends: out[c] (+)= sum over the partials of the system.
+// With a ticket, the last block of the system to arrive does the sum (fixed
+// order over blocks and lanes, so deterministic) and, for a GMRES state,
+// the Arnoldi step that consumes it.
+struct RedEnd {
+  double* out;
+  long long sR;     // out stride between systems (doubles)
+  int accumulate;
+  int* ticket;      // per system arrival counter (zero between launches), or null
+  GState* step;     // GMRES states (stride sR doubles), or null
+  int step_j;
+};
+
+// nblk partial rows; narrive blocks of the system take part (all write
+// their partials before arriving).
+__device__ __forceinline__ void finish_reduction(const double* __restrict__ partial, int nblk, int narrive, int ldp,
+                                                 int ncol, const RedEnd& e) {
+  if (!e.ticket) return;
+  const long long sys = blockIdx.z;
+  __shared__ int is_last;
+  __syncthreads();   // this block's partials are written
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const int t = atomicAdd(e.ticket + sys, 1);
+    is_last = t == narrive - 1;
+    if (is_last) atomicExch(e.ticket + sys, 0);
+  }
+  __syncthreads();
+  if (!is_last) return;
+  __threadfence();
+  double* out = e.out + sys * e.sR;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int c = wid; c < ncol; c += RED_THREADS / 64) {
+    double s = 0.0;
+    for (int b = lane; b < nblk; b += 64) s += partial[(long long)b * ldp + c];
+    s = wave_sum(s);
+    if (lane == 0) out[c] = e.accumulate ? out[c] + s : s;
+  }
+  if (e.step) {
+    __syncthreads();
+    __threadfence_block();
+    gstate_step_block(reinterpret_cast<GState*>(reinterpret_cast<double*>(e.step) + sys * e.sR), e.step_j);
+  }
+}
+
 // partial[b*ldp + c0 + c] = sum over this block's elements of V[c0+c][i] w[i]
 // (blockIdx.y: column chunk, blockIdx.z: system)
 template <typename R, int MAXC>
@@ -53,7 +100,7 @@ __global__ void __launch_bounds__(RED_THREADS) multidot_kernel(long long n, cons
                                                                int ncol, const R* __restrict__ w,
                                                                double* __restrict__ partial, int ldp,
                                                                const int* __restrict__ active, long long sV,
-                                                               long long sP, long long sA) {
+                                                               long long sP, long long sA, RedEnd e) {
   if (inactive(active, sA)) return;
   const long long sys = blockIdx.z;
   V += sys * sV;
@@ -65,6 +112,7 @@ __global__ void __launch_bounds__(RED_THREADS) multidot_kernel(long long n, cons
 #pragma unroll
   for (int c = 0; c < MAXC; ++c) acc[c] = 0.0;
   const long long stride = (long long)gridDim.x * blockDim.x;
+#pragma unroll 1
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
     const double wi = (double)w[i];
 #pragma unroll
@@ -72,15 +120,16 @@ __global__ void __launch_bounds__(RED_THREADS) multidot_kernel(long long n, cons
       if (c < nc) acc[c] += (double)V[(long long)(c0 + c) * ldv + i] * wi;
   }
   block_sum_cols<MAXC>(acc, nc, partial + (long long)blockIdx.x * ldp + c0);
+  finish_reduction(partial, gridDim.x, gridDim.x * gridDim.y, ldp, ncol, e);
 }
 
-// w_new = w + hsign * sum_c V[c] h[c]; writes w_new to wout (may alias w).  If dot:
-// partial dots V^T w_new, else partial ||w_new||^2 in column 0.
+// w_new = w + hsign * sum_c V[c] h[c]; writes w_new to wout (may alias w).
+// norm: partial ||w_new||^2 in column 0.  The coefficients sit in LDS.
 template <typename R, int MAXC>
-__global__ void __launch_bounds__(RED_THREADS) update_dot_kernel(
+__global__ void __launch_bounds__(RED_THREADS) update_kernel(
     long long n, const R* __restrict__ V, long long ldv, int ncol, const double* __restrict__ h, double hsign,
-    const R* w, R* wout, int dot, double* __restrict__ partial, int ldp, const int* __restrict__ active,
-    long long sV, long long sR, long long sP, long long sA, long long sW) {
+    const R* w, R* wout, int norm, double* __restrict__ partial, int ldp, const int* __restrict__ active,
+    long long sV, long long sR, long long sP, long long sA, long long sW, RedEnd e) {
   if (inactive(active, sA)) return;
   const long long sys = blockIdx.z;
   V += sys * sV;
@@ -88,35 +137,94 @@ __global__ void __launch_bounds__(RED_THREADS) update_dot_kernel(
   wout += sys * sW;
   h += sys * sR;
   partial += sys * sP;
-  double hc[MAXC];
-#pragma unroll
-  for (int c = 0; c < MAXC; ++c) hc[c] = c < ncol ? hsign * h[c] : 0.0;
-  double acc[MAXC];
-#pragma unroll
-  for (int c = 0; c < MAXC; ++c) acc[c] = 0.0;
+  __shared__ double hc[MAXC];
+  for (int c = threadIdx.x; c < MAXC; c += blockDim.x) hc[c] = c < ncol ? hsign * h[c] : 0.0;
+  __syncthreads();
+  double acc[1] = {0.0};
   const long long stride = (long long)gridDim.x * blockDim.x;
+#pragma unroll 1
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    double vc[MAXC];
     double s = (double)w[i];
-#pragma unroll
-    for (int c = 0; c < MAXC; ++c) {
-      if (c < ncol) {
-        vc[c] = (double)V[(long long)c * ldv + i];
-        s += vc[c] * hc[c];
-      }
-    }
+#pragma unroll 8
+    for (int c = 0; c < ncol; ++c) s += (double)V[(long long)c * ldv + i] * hc[c];
     const R wn = (R)s;
     wout[i] = wn;
-    const double wd = (double)wn;
-    if (dot) {
+    acc[0] += (double)wn * (double)wn;
+  }
+  if (!norm) return;
+  block_sum_cols<1>(acc, 1, partial + (long long)blockIdx.x * ldp);
+  finish_reduction(partial, gridDim.x, gridDim.x, ldp, 1, e);
+}
+
+// The same update followed by the dots V^T w_new (partial per block and
+// column).  Blocks walk tiles of RED_THREADS elements: each thread forms one
+// element of w_new, the tile of w_new goes to LDS, and then wave q owns
+// columns q, q + 4, ...: its lanes re-read their V entries (from cache) and
+// accumulate.  Per thread only ceil(MAXC/4) accumulators are live.
+template <typename R, int MAXC>
+__global__ void __launch_bounds__(RED_THREADS) update_dot_kernel(
+    long long n, const R* __restrict__ V, long long ldv, int ncol, const double* __restrict__ h, double hsign,
+    const R* w, R* wout, double* __restrict__ partial, int ldp, const int* __restrict__ active, long long sV,
+    long long sR, long long sP, long long sA, long long sW, RedEnd e) {
+  constexpr int NW = RED_THREADS / 64;
+  constexpr int KC = (MAXC + NW - 1) / NW;
+  if (inactive(active, sA)) return;
+  const long long sys = blockIdx.z;
+  V += sys * sV;
+  w += sys * sW;
+  wout += sys * sW;
+  h += sys * sR;
+  partial += sys * sP;
+  __shared__ double hc[MAXC];
+  __shared__ double tile[RED_THREADS];
+  for (int c = threadIdx.x; c < MAXC; c += blockDim.x) hc[c] = c < ncol ? hsign * h[c] : 0.0;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  double acc[KC];
 #pragma unroll
-      for (int c = 0; c < MAXC; ++c)
-        if (c < ncol) acc[c] += vc[c] * wd;
-    } else {
-      acc[0] += wd * wd;
+  for (int k = 0; k < KC; ++k) acc[k] = 0.0;
+  const long long tstride = (long long)gridDim.x * RED_THREADS;
+#pragma unroll 1
+  for (long long base = (long long)blockIdx.x * RED_THREADS; base < n; base += tstride) {
+    __syncthreads();   // hc ready / previous tile consumed
+    const long long i = base + threadIdx.x;
+    double wd = 0.0;
+    if (i < n) {
+      double s = (double)w[i];
+#pragma unroll 8
+      for (int c = 0; c < ncol; ++c) s += (double)V[(long long)c * ldv + i] * hc[c];
+      const R wn = (R)s;
+      wout[i] = wn;
+      wd = (double)wn;
+    }
+    tile[threadIdx.x] = wd;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+      const int c = wid + NW * k;
+      if (c < ncol) {
+        const R* Vc = V + (long long)c * ldv + base;
+        double a = acc[k];
+#pragma unroll
+        for (int q = 0; q < RED_THREADS / 64; ++q) {
+          const int t = lane + 64 * q;
+          if (base + t < n) a += (double)__hip_atomic_load(Vc + t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT) *
+                                 tile[t];
+        }
+        acc[k] = a;
+      }
     }
   }
-  block_sum_cols<MAXC>(acc, dot ? ncol : 1, partial + (long long)blockIdx.x * ldp);
+  // each column belongs to one wave: reduce over its lanes and store
+  double* prow = partial + (long long)blockIdx.x * ldp;
+#pragma unroll
+  for (int k = 0; k < KC; ++k) {
+    const int c = wid + NW * k;
+    if (c < ncol) {
+      const double sum = wave_sum(acc[k]);
+      if (lane == 0) prow[c] = sum;
+    }
+  }
+  finish_reduction(partial, gridDim.x, gridDim.x, ldp, ncol, e);
 }
 
 // out[c] = (accumulate ? out[c] : 0) + sum_b partial[b*ldp + c]  (fixed order)
@@ -147,7 +255,7 @@ template <typename R>
 __global__ void __launch_bounds__(RED_THREADS) nrm2_kernel(long long n, const R* __restrict__ x,
                                                            double* __restrict__ partial, int ldp,
                                                            const int* __restrict__ active, long long sV,
-                                                           long long sP, long long sA) {
+                                                           long long sP, long long sA, RedEnd e) {
   if (inactive(active, sA)) return;
   x += blockIdx.z * sV;
   partial += blockIdx.z * sP;
@@ -158,6 +266,7 @@ __global__ void __launch_bounds__(RED_THREADS) nrm2_kernel(long long n, const R*
     acc[0] += v * v;
   }
   block_sum_cols<1>(acc, 1, partial + (long long)blockIdx.x * ldp);
+  finish_reduction(partial, gridDim.x, gridDim.x, ldp, 1, e);
 }
 
 // r = b - y, partial ||r||^2 (b uses its own stride sB)
@@ -167,7 +276,7 @@ __global__ void __launch_bounds__(RED_THREADS) residual_kernel(long long n, cons
                                                                double* __restrict__ partial, int ldp,
                                                                const int* __restrict__ active, long long sV,
                                                                long long sB, long long sP, long long sA,
-                                                               long long sY) {
+                                                               long long sY, RedEnd e) {
   if (inactive(active, sA)) return;
   b += blockIdx.z * sB;
   y += blockIdx.z * sY;
@@ -181,6 +290,7 @@ __global__ void __launch_bounds__(RED_THREADS) residual_kernel(long long n, cons
     acc[0] += (double)v * (double)v;
   }
   block_sum_cols<1>(acc, 1, partial + (long long)blockIdx.x * ldp);
+  finish_reduction(partial, gridDim.x, gridDim.x, ldp, 1, e);
 }
 
 // out = x * (*scale)   (scale read from device memory)
@@ -226,65 +336,89 @@ inline long long part_stride(int ldp) { return (long long)RED_BLOCKS * ldp; }
 }  // namespace
 
 template <typename R>
+RedEnd reduction_end(const Blas<R>& bl, unsigned nb, double* out, bool accumulate, const Batch& b,
+                     GState* step = nullptr, int step_j = 0) {
+  const bool fused = bl.ticket && nb <= (unsigned)FUSE_MAX_BLOCKS;
+  return RedEnd{out, b.res, accumulate ? 1 : 0, fused ? bl.ticket : nullptr, fused ? step : nullptr, step_j};
+}
+
+template <typename R>
 void Blas<R>::multidot(long long n, const R* V, long long ldv, int ncol, const R* w, double* out, bool accumulate,
                        const int* active, hipStream_t s, const Batch& b) const {
   const int chunks = (ncol + 15) / 16;
   const unsigned nb = grid_for(n);
   const long long sP = part_stride(ldp);
+  const RedEnd e = reduction_end(*this, nb, out, accumulate, b);
   multidot_kernel<R, 16><<<dim3(nb, chunks, b.nsys), RED_THREADS, 0, s>>>(n, V, ldv, ncol, w, partial, ldp, active,
-                                                                          b.vec, sP, b.act);
-  reduce_cols_kernel<<<dim3(ncol, b.nsys), RED_THREADS, 0, s>>>(partial, (int)nb, ldp, ncol, out,
-                                                                accumulate ? 1 : 0, active, b.res, sP, b.act);
+                                                                          b.vec, sP, b.act, e);
+  if (!e.ticket)
+    reduce_cols_kernel<<<dim3(ncol, b.nsys), RED_THREADS, 0, s>>>(partial, (int)nb, ldp, ncol, out,
+                                                                  accumulate ? 1 : 0, active, b.res, sP, b.act);
 }
 
 template <typename R>
-void Blas<R>::update(long long n, const R* V, long long ldv, int ncol, const double* h, double hsign, const R* w,
+bool Blas<R>::update(long long n, const R* V, long long ldv, int ncol, const double* h, double hsign, const R* w,
                      R* wout, int mode, double* out, bool accumulate, const int* active, hipStream_t s,
-                     const Batch& b) const {
+                     const Batch& b, GState* step, int step_j) const {
   // mode: 0 = no reduction, 1 = dots V^T w_new, 2 = ||w_new||^2
+  constexpr int CH = 48;   // columns per launch
   const bool dot = mode == 1;
   const unsigned nb = grid_for(n);
   const long long sP = part_stride(ldp);
   const dim3 grid(nb, 1, b.nsys);
+  const RedEnd none{nullptr, 0, 0, nullptr, nullptr, 0};
+  const RedEnd e = reduction_end(*this, nb, out, accumulate, b, mode == 2 ? step : nullptr, step_j);
   int done = 0;
   const R* src = w;
-  while (done < ncol || (ncol == 0 && done == 0)) {
-    const int nc = ncol - done;
-    const bool last = nc <= 64;
-    const int c = last ? nc : 64;
-    const int dflag = (last && dot && ncol <= 64) ? 1 : 0;
+  bool reduced = false;   // the reduction ran inside the last launch
+  for (;;) {
+    const int c = ncol - done < CH ? ncol - done : CH;
+    const bool last = done + c >= ncol;
     const R* Vc = V + (long long)done * ldv;
-    if (c <= 16)
-      update_dot_kernel<R, 16><<<grid, RED_THREADS, 0, s>>>(n, Vc, ldv, c, h + done, hsign, src, wout, dflag, partial,
-                                                            ldp, active, b.vec, b.res, sP, b.act, b.w());
-    else if (c <= 32)
-      update_dot_kernel<R, 32><<<grid, RED_THREADS, 0, s>>>(n, Vc, ldv, c, h + done, hsign, src, wout, dflag, partial,
-                                                            ldp, active, b.vec, b.res, sP, b.act, b.w());
-    else
-      update_dot_kernel<R, 64><<<grid, RED_THREADS, 0, s>>>(n, Vc, ldv, c, h + done, hsign, src, wout, dflag, partial,
-                                                            ldp, active, b.vec, b.res, sP, b.act, b.w());
+    if (last && dot && ncol <= CH) {
+      if (c <= 16)
+        update_dot_kernel<R, 16><<<grid, RED_THREADS, 0, s>>>(n, Vc, ldv, c, h + done, hsign, src, wout, partial, ldp,
+                                                              active, b.vec, b.res, sP, b.act, b.w(), e);
+      else
+        update_dot_kernel<R, CH><<<grid, RED_THREADS, 0, s>>>(n, Vc, ldv, c, h + done, hsign, src, wout, partial, ldp,
+                                                              active, b.vec, b.res, sP, b.act, b.w(), e);
+      reduced = e.ticket != nullptr;
+    } else {
+      const int norm = last && mode == 2 ? 1 : 0;
+      const RedEnd& ee = norm ? e : none;
+      if (c <= 16)
+        update_kernel<R, 16><<<grid, RED_THREADS, 0, s>>>(n, Vc, ldv, c, h + done, hsign, src, wout, norm, partial,
+                                                          ldp, active, b.vec, b.res, sP, b.act, b.w(), ee);
+      else
+        update_kernel<R, CH><<<grid, RED_THREADS, 0, s>>>(n, Vc, ldv, c, h + done, hsign, src, wout, norm, partial,
+                                                          ldp, active, b.vec, b.res, sP, b.act, b.w(), ee);
+      reduced = norm && e.ticket != nullptr;
+    }
     src = wout;
     done += c;
     if (last) break;
   }
-  if (dot && ncol > 64) {
+  if (dot && ncol > CH) {
     multidot(n, V, ldv, ncol, wout, out, accumulate, active, s, b);
-  } else if (mode == 1) {
+  } else if (mode == 1 && !reduced) {
     reduce_cols_kernel<<<dim3(ncol, b.nsys), RED_THREADS, 0, s>>>(partial, (int)nb, ldp, ncol, out,
                                                                   accumulate ? 1 : 0, active, b.res, sP, b.act);
-  } else if (mode == 2) {
+  } else if (mode == 2 && !reduced) {
     reduce_cols_kernel<<<dim3(1, b.nsys), RED_THREADS, 0, s>>>(partial, (int)nb, ldp, 1, out, accumulate ? 1 : 0,
                                                                active, b.res, sP, b.act);
   }
+  return mode == 2 && step && reduced;
 }
 
 template <typename R>
 void Blas<R>::nrm2sq(long long n, const R* x, double* out, const int* active, hipStream_t s, const Batch& b) const {
   const unsigned nb = grid_for(n);
   const long long sP = part_stride(ldp);
-  nrm2_kernel<R><<<dim3(nb, 1, b.nsys), RED_THREADS, 0, s>>>(n, x, partial, ldp, active, b.vec, sP, b.act);
-  reduce_cols_kernel<<<dim3(1, b.nsys), RED_THREADS, 0, s>>>(partial, (int)nb, ldp, 1, out, 0, active, b.res, sP,
-                                                             b.act);
+  const RedEnd e = reduction_end(*this, nb, out, false, b);
+  nrm2_kernel<R><<<dim3(nb, 1, b.nsys), RED_THREADS, 0, s>>>(n, x, partial, ldp, active, b.vec, sP, b.act, e);
+  if (!e.ticket)
+    reduce_cols_kernel<<<dim3(1, b.nsys), RED_THREADS, 0, s>>>(partial, (int)nb, ldp, 1, out, 0, active, b.res, sP,
+                                                               b.act);
 }
 
 template <typename R>
@@ -292,10 +426,12 @@ void Blas<R>::residual(long long n, const R* bvec, const R* y, R* r, double* out
                        const Batch& b, long long sB, long long sY) const {
   const unsigned nb = grid_for(n);
   const long long sP = part_stride(ldp);
+  const RedEnd e = reduction_end(*this, nb, out, false, b);
   residual_kernel<R><<<dim3(nb, 1, b.nsys), RED_THREADS, 0, s>>>(n, bvec, y, r, partial, ldp, active, b.vec, sB, sP,
-                                                                 b.act, sY);
-  reduce_cols_kernel<<<dim3(1, b.nsys), RED_THREADS, 0, s>>>(partial, (int)nb, ldp, 1, out, 0, active, b.res, sP,
-                                                             b.act);
+                                                                 b.act, sY, e);
+  if (!e.ticket)
+    reduce_cols_kernel<<<dim3(1, b.nsys), RED_THREADS, 0, s>>>(partial, (int)nb, ldp, 1, out, 0, active, b.res, sP,
+                                                               b.act);
 }
 
 template <typename R>

@@ -67,61 +67,52 @@ __global__ void cycle_start_kernel(GState* base) {
   st->t.active = 1;
 }
 
-// Column j of H is d1[0..j] + d2[0..j] (the two Gram-Schmidt passes) with
-// H(j+1, j) = sqrt(wn2); d1[j+1] holds ||A z_j||^2 before orthogonalisation.
-__global__ void step_kernel(GState* base, int j) {
-  if (threadIdx.x != 0) return;
-  GState* st = base + blockIdx.x;
-  if (!st->t.active) return;
-  const int ld = GMAX + 1;
-  double* Hj = st->H + (long long)j * ld;
-  for (int i = 0; i <= j; ++i) Hj[i] = st->d1[i] + st->d2[i];
-  const double hn = sqrt(st->wn2);
-  Hj[j + 1] = hn;
-  for (int i = 0; i < j; ++i) {
-    const double t = st->cs[i] * Hj[i] + st->sn[i] * Hj[i + 1];
-    Hj[i + 1] = -st->sn[i] * Hj[i] + st->cs[i] * Hj[i + 1];
-    Hj[i] = t;
-  }
-  const double a = Hj[j], b = Hj[j + 1];
-  double c = 1.0, s = 0.0;
-  if (b != 0.0) {
-    const double r = hypot(a, b);
-    c = a / r;
-    s = b / r;
-  }
-  st->cs[j] = c;
-  st->sn[j] = s;
-  Hj[j] = c * a + s * b;
-  Hj[j + 1] = 0.0;
-  st->g[j + 1] = -s * st->g[j];
-  st->g[j] = c * st->g[j];
-  st->t.jdone = j + 1;
-  st->t.have_update = 1;
-  st->t.iters += 1;
-  st->t.matvecs += 1;
-  const double est = fabs(st->g[j + 1]);
-  st->t.relres = est / st->t.bnorm;
-  if (!isfinite(hn) || !isfinite(est)) {
-    st->t.nonfinite = 1;
-    st->t.active = 0;
-    return;
-  }
-  if (hn <= 1e-14 * sqrt(st->d1[j + 1])) {
-    st->t.breakdown = 1;
-    st->t.active = 0;
-    return;
-  }
-  st->t.inv = 1.0 / hn;
-  if (est <= st->t.tol * st->t.bnorm || j + 1 >= st->t.jlimit) st->t.active = 0;
-}
+__global__ void step_kernel(GState* base, int j) { gstate_step_block(base + blockIdx.x, j); }
 
-// y = R^{-1} g(0..jdone) by back substitution.
-__global__ void finish_kernel(GState* base) {
-  if (threadIdx.x != 0) return;
+// y = R^{-1} g(0..jdone) by back substitution.  Up to 64 columns: the
+// triangle is staged in LDS (all loads issued at once) and lane k keeps the
+// running right-hand side of row k; column i is eliminated after y_i is
+// known (fixed order, deterministic).  Longer cycles: one thread, in place.
+constexpr int FIN_MAX = 64;
+__global__ void __launch_bounds__(64) finish_kernel(GState* base) {
   GState* st = base + blockIdx.x;
   const int n = st->t.jdone;
   const int ld = GMAX + 1;
+  const int lane = threadIdx.x;
+  if (n <= FIN_MAX) {
+    __shared__ double Rt[FIN_MAX * (FIN_MAX + 1) / 2];   // column k at k(k+1)/2, rows 0..k
+    constexpr int PER = (FIN_MAX * (FIN_MAX + 1) / 2 + 63) / 64;
+    const int total = n * (n + 1) / 2;
+    double v[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int f = lane + 64 * q;
+      v[q] = 0.0;
+      if (f < total) {
+        int k = (int)((sqrt(8.0 * f + 1.0) - 1.0) * 0.5);
+        if ((k + 1) * (k + 2) / 2 <= f) ++k;
+        if (k * (k + 1) / 2 > f) --k;
+        v[q] = st->H[(long long)k * ld + (f - k * (k + 1) / 2)];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int f = lane + 64 * q;
+      if (f < total) Rt[f] = v[q];
+    }
+    __syncthreads();
+    double rhs = lane < n ? st->g[lane] : 0.0;
+    double yk = 0.0;
+    for (int i = n - 1; i >= 0; --i) {
+      const double yi = __shfl(rhs, i, 64) / Rt[i * (i + 1) / 2 + i];
+      if (lane == i) yk = yi;
+      if (lane < i) rhs -= Rt[i * (i + 1) / 2 + lane] * yi;
+    }
+    for (int i = lane; i < GMAX; i += 64) st->y[i] = (i == lane && i < n) ? yk : 0.0;
+    if (lane == 0) st->t.active = 0;
+    return;
+  }
+  if (lane != 0) return;
   for (int i = n - 1; i >= 0; --i) {
     double s = st->g[i];
     for (int k = i + 1; k < n; ++k) s -= st->H[(long long)k * ld + i] * st->y[k];

@@ -83,8 +83,10 @@ int run_one(Ctx* c, const sa_eig_opts& o, const double* v0, sa_eig_result* res) 
   w.tb = (double*)c->buffer("iramB", sizeof(double) * n);
   w.st = (IState*)c->buffer("iramS", sizeof(IState));
   w.bl.partial = (double*)c->buffer("iram_partial", sizeof(double) * RED_BLOCKS * PARTIAL_LD);
+  w.bl.ticket = (int*)c->buffer("iram_ticket", sizeof(int));
   w.bl.ldp = PARTIAL_LD;
-  if (!w.V || !w.T || !w.tb || !w.st || !w.bl.partial) return c->fail(SA_ENOMEM, "iram: out of device memory");
+  if (!w.V || !w.T || !w.tb || !w.st || !w.bl.partial || !w.bl.ticket)
+    return c->fail(SA_ENOMEM, "iram: out of device memory");
   double* evr = res->evec_re_dev;
   double* evi = res->evec_im_dev;
   std::memset(res, 0, sizeof(*res));

@@ -86,11 +86,12 @@ int solve_gmres(Ctx* c, const sa_gmres_opts& o, int nsys, const double* sigma, c
   double* sig = (double*)c->buffer(tag + "sigma", sizeof(double) * nsys, false);
   Blas<R> bl;
   bl.partial = (double*)c->buffer(tag + "partial", sizeof(double) * RED_BLOCKS * PARTIAL_LD * nsys);
+  bl.ticket = (int*)c->buffer(tag + "ticket", sizeof(int) * nsys);
   // a captured cycle works on context-owned copies of b and x, so that one
   // graph serves every caller buffer
   R* X = graph ? (R*)c->buffer(tag + "X", sizeof(R) * n * nsys, false) : x;
   R* B = graph ? (R*)c->buffer(tag + "B", sizeof(R) * n * nsys, false) : const_cast<R*>(b);
-  if (!V || !Z || !T || !st || !sig || !bl.partial || !X || !B)
+  if (!V || !Z || !T || !st || !sig || !bl.partial || !bl.ticket || !X || !B)
     return c->fail(SA_ENOMEM, "gmres: out of device memory");
   if (graph && !c->cap_stream) {
     hipError_t e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
@@ -140,9 +141,10 @@ int solve_gmres(Ctx* c, const sa_gmres_opts& o, int nsys, const double* sigma, c
       bl.multidot(n, V, n, j + 2, w, st->d1, false, act, q, bb);
       // pass 2: w -= V d1, d2 = V^T w
       bl.update(n, V, n, j + 1, st->d1, -1.0, w, w, 1, st->d2, false, act, q, bb);
-      // pass 3: w -= V d2, wn2 = ||w||^2
-      bl.update(n, V, n, j + 1, st->d2, -1.0, w, w, 2, &st->wn2, false, act, q, bb);
-      gstate_step(st, nsys, j, q);
+      // pass 3: w -= V d2, wn2 = ||w||^2, then the Givens step (fused when
+      // the reduction finishes inside the kernel)
+      if (!bl.update(n, V, n, j + 1, st->d2, -1.0, w, w, 2, &st->wn2, false, act, q, bb, st, j))
+        gstate_step(st, nsys, j, q);
       bl.scale(n, w, w, &st->t.inv, act, q, bb);
     }
     gstate_finish(st, nsys, q);
@@ -161,7 +163,7 @@ int solve_gmres(Ctx* c, const sa_gmres_opts& o, int nsys, const double* sigma, c
     put(key, pc_shift0);
     put(key, n);
     for (const void* ptr : {(const void*)V, (const void*)Z, (const void*)T, (const void*)st, (const void*)sig,
-                            (const void*)bl.partial, (const void*)X, (const void*)B, (const void*)base,
+                            (const void*)bl.partial, (const void*)bl.ticket, (const void*)X, (const void*)B, (const void*)base,
                             (const void*)bdata, (const void*)c->pc_lu, (const void*)c->pc_perm})
       put(key, ptr);
     for (int i = 0; i < nsys; ++i) put(key, sigma[i]);
@@ -253,9 +255,12 @@ int solve_ir(Ctx* c, const sa_gmres_opts& o, double sigma, const double* b, doub
   GState* st = (GState*)c->buffer("ir_state", sizeof(GState));
   Blas<double> bl;
   bl.partial = (double*)c->buffer("ir_partial", sizeof(double) * RED_BLOCKS * PARTIAL_LD);
+  bl.ticket = (int*)c->buffer("ir_ticket", sizeof(int));
   Blas<float> bl32;
   bl32.partial = bl.partial;
-  if (!r || !y || !r32 || !d32 || !st || !bl.partial) return c->fail(SA_ENOMEM, "ir: out of device memory");
+  bl32.ticket = bl.ticket;
+  if (!r || !y || !r32 || !d32 || !st || !bl.partial || !bl.ticket)
+    return c->fail(SA_ENOMEM, "ir: out of device memory");
   *info = sa_gmres_info{};
   // the outer state only tracks ||b||, ||r|| and the tolerance; no budget
   gstate_init(st, 1, o.tol, 1, (long long)1 << 62, s);
