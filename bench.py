@@ -11,8 +11,9 @@ Also reported: the roofline record of the operator kernel (algorithmic bytes
 = read x + read q0 + write y = 3 nv 8 B per point, against 8 TB/s), the same
 operator in FP32, optional extras (--extras: GMRES(40) at 2D 512 x 512, the
 block-Jacobi preconditioner of the 3D grid with 8 shifts, 8-shift batched
-GMRES cycles, time to eigenpairs FP64 vs mixed on a small case), and the
-oracle timed on the host cores on a bounded sample.
+GMRES cycles, time to eigenpairs FP64 vs mixed on a small case, a reduced
+sweep of uneven base flows run in turn and concurrently), and the oracle
+timed on the host cores on a bounded sample.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--extras]
        [--no-cpu] [--calib-copy]
@@ -248,7 +249,57 @@ def extras(torch, dev, ctx3, prob3):
         res["eigs_kh_32x32_" + name] = {"seconds": el, "nconv": r[0]["nconv"],
                                         "lam": [[l.real, l.imag] for l in r[0]["lam"]],
                                         "n_matvec": r[0]["n_matvec"]}
+    res.update(sweep(torch, dev, log=lambda m: print(m, file=sys.stderr, flush=True)))
     return res
+
+
+def sweep(torch, dev, nev=2, log=None):
+    """Reduced sweep of uneven base flows (the sweep's Mach/Re recipe on sides
+    16-32), each its own mixed-precision Cayley-IRAM: the problems one after
+    another on one stream, then all at once on one stream each (run
+    concurrently by the library)."""
+    import numpy as np
+    import synth
+    from paper_1502_03701_amd import SA_MIXED, Context, arnoldi_eigs
+    items = synth.config4_reduced(sides=(16, 24, 32))
+    kw = dict(nev=nev, ncv=16, sigma=0.2, mu=-0.2, tol=1e-8, max_restarts=100, restart=40, lin_tol=1e-10,
+              prec=SA_MIXED, inner_tol=1e-4, max_outer=20)
+    out = {}
+    for mode in ("sequential", "concurrent"):
+        if mode == "sequential":
+            streams = [torch.cuda.current_stream()] * len(items)
+        else:
+            streams = [torch.cuda.Stream() for _ in items]
+        ctxs, v0s = [], []
+        for it, st in zip(items, streams):
+            c = Context(stream=st)
+            c.base_set(it.problem, torch.from_numpy(synth.base_flow(it.problem).ravel()).to(dev))
+            ctxs.append(c)
+            v0s.append(torch.from_numpy(synth.random_vector(it.problem, it.seed).ravel()).to(dev))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if mode == "sequential":
+            r = []
+            for i, (c, v) in enumerate(zip(ctxs, v0s)):
+                r += arnoldi_eigs([c], [v], **kw)[1]
+                if log:
+                    log("sweep problem %d (%dx%d): %.2f s" % (i, items[i].problem.n[0], items[i].problem.n[1],
+                                                             r[-1]["seconds"]))
+        else:
+            r = arnoldi_eigs(ctxs, v0s, **kw)[1]
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        secs = np.array([x["seconds"] for x in r])
+        pairs = int(sum(min(x["nconv"], nev) for x in r))
+        out["sweep_reduced_" + mode] = {
+            "problems": len(items), "sides": [it.problem.n[0] for it in items], "eigenpairs": pairs,
+            "seconds": el, "eigenpairs_per_s": pairs / el, "p50_s": float(np.percentile(secs, 50)),
+            "p99_s": float(np.percentile(secs, 99)), "n_matvec": int(sum(x["n_matvec"] for x in r))}
+        if log:
+            log("sweep %s: %.2f s" % (mode, el))
+        for c in ctxs:
+            c.close()
+    return out
 
 
 if __name__ == "__main__":

@@ -123,6 +123,7 @@ typedef struct {
   double ritz_est[32];               /* ||f_m|| |e_m^T y|                    */
   double resid[32];    /* ||J x - lam x|| / (|lam| ||x||) if vectors given   */
   double *evec_re_dev, *evec_im_dev; /* caller buffers of nev*n doubles or NULL */
+  double wall_seconds; /* host wall time of this problem's solve              */
 } sa_eig_result;
 
 /* Context life cycle.  hip_stream is a hipStream_t (may be NULL: the null
@@ -186,8 +187,13 @@ int sa_gmres_solve(sa_ctx *ctx, const sa_gmres_opts *opts, int nshift,
 /* Leading eigenpairs of J for nprob problems (Algorithm 1 on the Cayley
  * transform; eigenvalues ordered by decreasing |theta|, theta = (lam - mu)/
  * (lam - sigma)).  ctxs[p] holds problem p's base state; v0_dev[p] its start
- * vector (n doubles).  All contexts must share one stream.  res_host[nprob].
- * Returns SA_OK if all problems converged, SA_NOT_CONVERGED otherwise. */
+ * vector (n doubles).  res_host[nprob].  If all contexts share one stream
+ * the problems run one after another; if their streams are pairwise
+ * distinct they run concurrently, one host thread per problem (at most 16
+ * at a time), so that the GPU overlaps their kernels.  Any other mix is
+ * SA_EINVAL.  On an error the message of the failing problem is copied to
+ * ctxs[0].  Returns SA_OK if all problems converged, SA_NOT_CONVERGED
+ * otherwise. */
 int sa_arnoldi_eigs(sa_ctx *const *ctxs, int nprob, const sa_eig_opts *opts,
                     const double *const *v0_dev, sa_eig_result *res_host);
 

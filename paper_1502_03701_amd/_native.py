@@ -64,7 +64,8 @@ class EigResult(C.Structure):
                 ("lam_re", C.c_double * 32), ("lam_im", C.c_double * 32),
                 ("theta_re", C.c_double * 32), ("theta_im", C.c_double * 32),
                 ("ritz_est", C.c_double * 32), ("resid", C.c_double * 32),
-                ("evec_re_dev", C.c_void_p), ("evec_im_dev", C.c_void_p)]
+                ("evec_re_dev", C.c_void_p), ("evec_im_dev", C.c_void_p),
+                ("wall_seconds", C.c_double)]
 
 
 _lib = None
@@ -219,7 +220,9 @@ def arnoldi_eigs(ctxs, v0s, nev=6, ncv=30, sigma=0.2, mu=-0.2, tol=1e-10, max_re
                  restart=40, lin_tol=1e-12, max_matvec=10 ** 7, use_precond=False, prec=SA_F64,
                  inner_tol=1e-4, max_outer=10, evecs=None, use_graph=True):
     """Leading eigenpairs for several problems (one context each).  evecs: optional
-    list of (re, im) device float64 tensors of nev*n entries per problem."""
+    list of (re, im) device float64 tensors of nev*n entries per problem.
+    Contexts on one shared stream run in turn; contexts on pairwise distinct
+    streams run concurrently."""
     import torch
     lib = load()
     npb = len(ctxs)
@@ -246,5 +249,5 @@ def arnoldi_eigs(ctxs, v0s, nev=6, ncv=30, sigma=0.2, mu=-0.2, tol=1e-10, max_re
                         lam=[complex(r.lam_re[i], r.lam_im[i]) for i in range(k)],
                         theta=[complex(r.theta_re[i], r.theta_im[i]) for i in range(k)],
                         ritz_est=[r.ritz_est[i] for i in range(k)],
-                        resid=[r.resid[i] for i in range(k)]))
+                        resid=[r.resid[i] for i in range(k)], seconds=r.wall_seconds))
     return rc, out

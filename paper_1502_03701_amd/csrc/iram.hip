@@ -7,8 +7,13 @@
 // arnoldi_small.hip; the basis update V_k = V_m Q(:,1:k) and
 // f_k = v_{k+1} beta_hat + f_m Q(m,k) are tall-skinny products.
 #include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <cmath>
 #include <cstring>
+#include <string>
+#include <thread>
+#include <vector>
 
 #include "arnoldi_small.h"
 #include "sa_runtime.h"
@@ -183,18 +188,52 @@ extern "C" int sa_arnoldi_eigs(sa_ctx* const* ctxs, int nprob, const sa_eig_opts
     return c0->fail(SA_EINVAL, "sa_arnoldi_eigs: need 1 <= nev <= 32 and nev+2 <= ncv <= %d", MMAX);
   if (!(o->tol > 0) || o->max_restarts < 0) return c0->fail(SA_EINVAL, "sa_arnoldi_eigs: bad tol/max_restarts");
   if (std::fabs(o->sigma - o->mu) == 0.0) return c0->fail(SA_EINVAL, "sa_arnoldi_eigs: sigma == mu");
+  bool same = true, distinct = true;
   for (int p = 0; p < nprob; ++p) {
     if (!ctxs[p] || !v0_dev[p]) return c0->fail(SA_EINVAL, "sa_arnoldi_eigs: null context or start vector");
     if (!ctxs[p]->has_base) return ctxs[p]->fail(SA_ESTATE, "sa_arnoldi_eigs: base state not set");
-    if (ctxs[p]->stream != c0->stream) return c0->fail(SA_EINVAL, "sa_arnoldi_eigs: contexts must share one stream");
     if (o->lin.use_precond && !ctxs[p]->has_precond)
       return ctxs[p]->fail(SA_ESTATE, "sa_arnoldi_eigs: preconditioner not set up");
+    same = same && ctxs[p]->stream == c0->stream;
+    for (int q = 0; q < p; ++q) distinct = distinct && ctxs[q]->stream != ctxs[p]->stream && ctxs[q] != ctxs[p];
+  }
+  if (!same && !distinct)
+    return c0->fail(SA_EINVAL, "sa_arnoldi_eigs: streams must be all one or pairwise distinct");
+  std::vector<int> rcs(nprob, SA_OK);
+  auto solve = [&](int p) {
+    const auto t0 = std::chrono::steady_clock::now();
+    rcs[p] = run_one(ctxs[p], *o, v0_dev[p], &res_host[p]);
+    res_host[p].wall_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  };
+  if (same || nprob == 1) {
+    for (int p = 0; p < nprob; ++p) {
+      solve(p);
+      if (rcs[p] < 0) break;
+    }
+  } else {
+    // one host thread per problem, at most 16 at a time
+    std::atomic<int> next{0};
+    auto worker = [&]() {
+      for (int p = next.fetch_add(1); p < nprob; p = next.fetch_add(1)) {
+        if (hipSetDevice(ctxs[p]->device) != hipSuccess) {
+          rcs[p] = ctxs[p]->fail(SA_EDEVICE, "sa_arnoldi_eigs: hipSetDevice failed");
+          continue;
+        }
+        solve(p);
+      }
+    };
+    const int nt = nprob < 16 ? nprob : 16;
+    std::vector<std::thread> pool;
+    for (int t = 0; t < nt; ++t) pool.emplace_back(worker);
+    for (auto& th : pool) th.join();
   }
   int rc_all = SA_OK;
   for (int p = 0; p < nprob; ++p) {
-    int rc = run_one(ctxs[p], *o, v0_dev[p], &res_host[p]);
-    if (rc < 0) return rc;
-    if (rc > 0) rc_all = rc;
+    if (rcs[p] < 0) {
+      if (p > 0) c0->err = "problem " + std::to_string(p) + ": " + ctxs[p]->err;
+      return rcs[p];
+    }
+    if (rcs[p] > 0) rc_all = rcs[p];
   }
   return rc_all;
 }

@@ -137,6 +137,21 @@ def config4_sweep(seed: int = 4, count: int = 48) -> List[SweepItem]:
     return out
 
 
+def config4_reduced(seed: int = 4, count: int = 8, sides=(24, 32, 40, 48)) -> List[SweepItem]:
+    """The sweep's recipe (M ~ U[0.1, 0.8], Re ~ U[300, 2000], side drawn
+    uniformly, all from the seed) on small sides, so that every problem's
+    Cayley-IRAM finishes in seconds with unpreconditioned inner solves."""
+    rng = np.random.default_rng(np.random.SeedSequence(seed).spawn(4)[3])
+    sides = np.asarray(sides)
+    out = []
+    for i in range(count):
+        side = int(rng.choice(sides))
+        mach = float(rng.uniform(0.1, 0.8))
+        re = float(rng.uniform(300.0, 2000.0))
+        out.append(SweepItem(mixing_layer_2d(side, side, mach, re), seed * 1000 + i))
+    return out
+
+
 # ---------------------------------------------------------------------------
 # Grids and base flows.
 # ---------------------------------------------------------------------------

@@ -113,3 +113,35 @@ def test_c0_leading_four():
     rc, r, _ = run(synth.config0(), nev=4, ncv=20, lin_tol=1e-12)
     assert rc == 0
     check(r["lam"], golden("c0_48x48_M0.3_Re500"), 2)
+
+
+def test_concurrent_problems_match_sequential():
+    """Problems on pairwise distinct streams run concurrently (one host
+    thread each) and give the same eigenvalues, bit for bit, as the same
+    problems run in turn on one stream."""
+    need_gpu()
+    from paper_1502_03701_amd import Context, arnoldi_eigs
+    items = synth.config4_reduced(count=3, sides=(16, 20))
+    def setup(streams):
+        ctxs, v0s = [], []
+        for it, st in zip(items, streams):
+            c = Context(stream=st)
+            c.base_set(it.problem, dev(synth.base_flow(it.problem)))
+            ctxs.append(c)
+            v0s.append(dev(synth.random_vector(it.problem, it.seed)))
+        return ctxs, v0s
+    kw = dict(nev=2, ncv=12, sigma=0.2, mu=-0.2, tol=1e-9, max_restarts=40, restart=30, lin_tol=1e-11)
+    ctxs, v0s = setup([torch.cuda.current_stream()] * len(items))
+    rc1, r1 = arnoldi_eigs(ctxs, v0s, **kw)
+    streams = [torch.cuda.Stream() for _ in items]
+    ctxs2, v0s2 = setup(streams)
+    torch.cuda.synchronize()
+    rc2, r2 = arnoldi_eigs(ctxs2, v0s2, **kw)
+    assert rc1 == rc2
+    for a, b in zip(r1, r2):
+        assert a["lam"] == b["lam"] and a["n_matvec"] == b["n_matvec"]
+        assert a["seconds"] > 0 and b["seconds"] > 0
+    # a mix of shared and distinct streams is refused
+    from paper_1502_03701_amd import SAError
+    with pytest.raises(SAError):
+        arnoldi_eigs([ctxs[0], ctxs[1], ctxs2[2]], v0s, **kw)
