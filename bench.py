@@ -145,6 +145,13 @@ def main():
     alg_bytes = 3 * nv * 8 * npts
     achieved = alg_bytes / per / 1e9
 
+    from paper_1502_03701_amd import SA_F32, SA_F64
+    from paper_1502_03701_amd._native import JV_VARIANTS
+    tuned = {}
+    for name, prec in (("f64", SA_F64), ("f32", SA_F32)):
+        var, times = ctx.jv_variant(prec)
+        tuned[name] = {"variant": JV_VARIANTS[var] if var >= 0 else "default", "tune_us": times}
+
     x32 = x.float()
     y32 = torch.empty_like(x32)
     sec32 = timed(lambda: ctx.op_apply(x32, y32, shift=0.2), args.steps, args.warmup, torch)
@@ -176,10 +183,13 @@ def main():
                                "one FP64 sa_op_apply per step",
                    "grid": [256, 128, 128], "nv": nv, "shift": 0.2},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                     "kernel": "jv_prefetch_kernel<double,3>", "alg_bytes_per_point": 3 * nv * 8},
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic() if tuned["f64"]["variant"] == "prefetch_z32" else None,
+                     "kernel": "jv_prefetch_kernel<double,3>" if tuned["f64"]["variant"].startswith("prefetch")
+                     else "jv_stage_kernel<double,3>", "alg_bytes_per_point": 3 * nv * 8},
         "fp32_jv": {"gpts": npts / per32 / 1e9, "ms": per32 * 1e3,
                     "achieved_GBs": 3 * nv * 4 * npts / per32 / 1e9},
+        "autotuned_jv": tuned,
     }
     if args.extras:
         out["extras"] = extras(torch, dev, ctx, prob)

@@ -134,12 +134,36 @@ const char *sa_last_error(const sa_ctx *ctx);
 /* Library version string. */
 const char *sa_version(void);
 
+/* Kernels of the operator product: a prefetching one (16 x 16 column tiles,
+ * the next plane's loads in flight during the pointwise algebra) and a
+ * plane-staging one (32 x 8 tiles, two waves per SIMD in FP32), each
+ * marching over 32 or 16 z planes per workgroup.  All give the same product
+ * to rounding. */
+typedef enum {
+  SA_JV_PREFETCH_Z32 = 0,
+  SA_JV_PREFETCH_Z16 = 1,
+  SA_JV_STAGE_Z16 = 2,
+  SA_JV_STAGE_Z32 = 3
+} sa_jv_variant;
+
 /* Set the base state q0 (eq. model_stabiity: J is linearised about q0).
  * q0_dev: nv*Npts doubles (wall rows included), copied into the context,
  * which also derives its FP32 shadow and pointwise thermodynamic fields.
  * Errors: SA_EINVAL (bad problem), SA_ENONFINITE (NaN/Inf or non-positive
  * pressure in q0), SA_ENOMEM. */
 int sa_base_set(sa_ctx *ctx, const sa_problem *prob, const double *q0_dev);
+
+/* Autotuning of the operator kernel.  sa_base_set times every sa_jv_variant
+ * on the problem (a warm-up and three launches per variant and precision,
+ * HIP events) and keeps the fastest per precision, unless a variant was
+ * pinned with sa_set_jv_variant (variant -1 unpins and selects the
+ * precision's default until the next sa_base_set; SA_JV_AUTOTUNE=0 in the
+ * environment skips the timing).  sa_get_jv_variant returns the variant in
+ * use (-1: default) and, if times_us is not NULL, fills times_us[4] with the
+ * measured microseconds per launch (0 where not measured).  Errors:
+ * SA_EINVAL (bad precision or variant). */
+int sa_set_jv_variant(sa_ctx *ctx, sa_prec prec, int variant);
+int sa_get_jv_variant(const sa_ctx *ctx, sa_prec prec, float *times_us);
 
 /* y = (J(q0) - shift I) x for nrhs vectors stored one after another
  * (x_dev, y_dev: nrhs*n entries, double for SA_F64, float for SA_F32).

@@ -27,7 +27,10 @@ SA_BC_PERIODIC, SA_BC_WALL = 0, 1
 
 EXPORTED = ["sa_create", "sa_destroy", "sa_last_error", "sa_version", "sa_base_set",
             "sa_op_apply", "sa_precond_setup", "sa_precond_apply", "sa_gmres_solve",
-            "sa_arnoldi_eigs"]
+            "sa_arnoldi_eigs", "sa_set_jv_variant", "sa_get_jv_variant"]
+
+# operator kernel variants (sa_jv_variant)
+JV_VARIANTS = ["prefetch_z32", "prefetch_z16", "stage_z16", "stage_z32"]
 
 
 class Problem(C.Structure):
@@ -102,6 +105,10 @@ def load(path: str = LIB_PATH):
     lib.sa_arnoldi_eigs.argtypes = [C.POINTER(vp), ip, C.POINTER(EigOpts), C.POINTER(vp),
                                     C.POINTER(EigResult)]
     lib.sa_arnoldi_eigs.restype = ip
+    lib.sa_set_jv_variant.argtypes = [vp, ip, ip]
+    lib.sa_set_jv_variant.restype = ip
+    lib.sa_get_jv_variant.argtypes = [vp, ip, C.POINTER(C.c_float)]
+    lib.sa_get_jv_variant.restype = ip
     _lib = lib
     return lib
 
@@ -185,6 +192,16 @@ class Context:
         _check_dev(x, x.dtype, nrhs * self.ndof)
         _check_dev(y, x.dtype, nrhs * self.ndof)
         return self._err(self.lib.sa_op_apply(self.h, prec, nrhs, _ptr(x), _ptr(y), float(shift)))
+
+    def set_jv_variant(self, prec, variant):
+        """Pin the operator kernel variant of a precision (-1: unpin)."""
+        return self._err(self.lib.sa_set_jv_variant(self.h, prec, variant))
+
+    def jv_variant(self, prec=SA_F64):
+        """(variant in use, {variant name: measured us per launch})."""
+        t = (C.c_float * len(JV_VARIANTS))()
+        v = self.lib.sa_get_jv_variant(self.h, prec, t)
+        return v, {n: float(t[i]) for i, n in enumerate(JV_VARIANTS)}
 
     def precond_setup(self, shifts, bx=4, by=4, bz=1, diag_add=0.1, noise_std=0.01, seed=3,
                       factor_prec=SA_F32):

@@ -262,34 +262,41 @@ static int kernel_choice() {
 
 static bool pert_kernel(int k) { return k == 0 || k == 4 || k == 5; }
 
+bool jv_kernel_forced() { return kernel_choice() != 0; }
+
 template <typename R>
 hipError_t launch_jv_pert(const OpParams& p, const R* base, const R* bdata, const R* x, R* y, int nrhs, R shift,
                           const int* active, hipStream_t s, long long sX, long long sY, const double* shifts,
-                          long long sA) {
+                          long long sA, int variant) {
   const int k = kernel_choice();
-  const bool prefetch = k == 4 || (k != 5 && sizeof(R) == 8);
-  if (prefetch) return launch_jv_prefetch<R>(p, base, bdata, x, y, nrhs, shift, active, s, sX, sY, shifts, sA);
-  return launch_jv_stage<R>(p, base, bdata, x, y, nrhs, shift, active, s, sX, sY, shifts, sA);
+  if (k == 4) variant = 0;
+  if (k == 5) variant = 2;
+  if (variant < 0 || variant >= JV_NVARIANTS) variant = sizeof(R) == 8 ? 0 : 2;
+  const int nzc = (variant == 0 || variant == 3) ? 32 : 16;
+  if (variant <= 1)
+    return launch_jv_prefetch<R>(p, base, bdata, x, y, nrhs, shift, active, s, sX, sY, shifts, sA, nzc);
+  return launch_jv_stage<R>(p, base, bdata, x, y, nrhs, shift, active, s, sX, sY, shifts, sA, nzc);
 }
 
 template <typename R>
 hipError_t launch_jv(const OpParams& p, const R* base, const R* bdata, const R* x, R* y, int nrhs, R shift,
-                     const int* active, hipStream_t s) {
+                     const int* active, hipStream_t s, int variant) {
   const int k = kernel_choice();
   if (k == 2) return launch_jv_direct<R>(p, base, x, y, nrhs, shift, active, s);
-  if (pert_kernel(k) && bdata) return launch_jv_pert<R>(p, base, bdata, x, y, nrhs, shift, active, s);
+  if (pert_kernel(k) && bdata)
+    return launch_jv_pert<R>(p, base, bdata, x, y, nrhs, shift, active, s, 0, 0, nullptr, 0, variant);
   return launch_jv_tiled<R>(p, base, x, y, nrhs, shift, active, k == 1 ? nullptr : bdata, s);
 }
 
 template <typename R>
 hipError_t launch_jv_batch(const OpParams& p, const R* base, const R* bdata, const R* x, R* y, int nsys,
                            long long sX, long long sY, const double* shifts_host, const double* shifts_dev,
-                           const int* active, long long sA, hipStream_t s) {
+                           const int* active, long long sA, hipStream_t s, int variant) {
   if (pert_kernel(kernel_choice()) && bdata)
-    return launch_jv_pert<R>(p, base, bdata, x, y, nsys, R(0), active, s, sX, sY, shifts_dev, sA);
+    return launch_jv_pert<R>(p, base, bdata, x, y, nsys, R(0), active, s, sX, sY, shifts_dev, sA, variant);
   for (int r = 0; r < nsys; ++r) {
     hipError_t e = launch_jv<R>(p, base, bdata, x + r * sX, y + r * sY, 1, R(shifts_host[r]),
-                                active ? active + r * sA : nullptr, s);
+                                active ? active + r * sA : nullptr, s, variant);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -297,14 +304,14 @@ hipError_t launch_jv_batch(const OpParams& p, const R* base, const R* bdata, con
 
 template hipError_t launch_jv_batch<double>(const OpParams&, const double*, const double*, const double*, double*,
                                             int, long long, long long, const double*, const double*, const int*,
-                                            long long, hipStream_t);
+                                            long long, hipStream_t, int);
 template hipError_t launch_jv_batch<float>(const OpParams&, const float*, const float*, const float*, float*, int,
                                            long long, long long, const double*, const double*, const int*,
-                                           long long, hipStream_t);
+                                           long long, hipStream_t, int);
 
 template hipError_t launch_jv<double>(const OpParams&, const double*, const double*, const double*, double*,
-                                      int, double, const int*, hipStream_t);
+                                      int, double, const int*, hipStream_t, int);
 template hipError_t launch_jv<float>(const OpParams&, const float*, const float*, const float*, float*, int,
-                                     float, const int*, hipStream_t);
+                                     float, const int*, hipStream_t, int);
 
 }  // namespace sa

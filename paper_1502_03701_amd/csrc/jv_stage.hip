@@ -28,7 +28,6 @@ constexpr int TY = 8;
 constexpr int PW = TX + 6;
 constexpr int PH = TY + 6;
 constexpr int NT = TX * TY;
-constexpr int NZC = 16;
 
 constexpr int NXCD = 8;
 
@@ -39,7 +38,7 @@ __device__ __forceinline__ int wrapi(int a, int n) { return a < 0 ? a + n : (a >
 // A batch of systems shares one launch: blockIdx.z = sys * zchunks + chunk;
 // system sys reads x + sys*sV, writes y + sys*sV, uses shifts[sys] (or the
 // scalar shift) and the flag active[sys*sA].
-template <typename R, int ND>
+template <typename R, int ND, int NZC>
 __global__ void __launch_bounds__(NT) jv_stage_kernel(OpParams op, const R* __restrict__ base,
                                                      const R* __restrict__ bdata, const R* __restrict__ x,
                                                      R* __restrict__ y, R shift, const int* __restrict__ active,
@@ -302,31 +301,36 @@ __global__ void __launch_bounds__(NT) jv_stage_kernel(OpParams op, const R* __re
 template <typename R>
 hipError_t launch_jv_stage(const OpParams& p, const R* base, const R* bdata, const R* x, R* y, int nrhs, R shift,
                           const int* active, hipStream_t s, long long sX, long long sY, const double* shifts,
-                          long long sA) {
+                          long long sA, int nzc) {
   const long long ndof = (long long)(p.ndim + 2) * p.npts;
   // 32-bit indices within the base data (the widest per-point array)
   if ((long long)base_data_fields(p.ndim) * p.npts >= (1LL << 31)) return hipErrorInvalidValue;
-  const int zchunks = p.ndim == 3 ? (p.nz + NZC - 1) / NZC : 1;
+  if (nzc != 16 && nzc != 32) return hipErrorInvalidValue;
+  const int zchunks = p.ndim == 3 ? (p.nz + nzc - 1) / nzc : 1;
   if (sX == 0) sX = ndof;   // right-hand sides one after another
   if (sY == 0) sY = ndof;
   const int gx = (p.nx + TX - 1) / TX, gy = (p.ny + TY - 1) / TY;
   const long long ntot = (long long)gx * gy * zchunks * nrhs;
   if (ntot >= (1LL << 31)) return hipErrorInvalidValue;
   dim3 grid((unsigned)ntot);
+#define SA_LAUNCH(ND_, NZ_)                                                                                      \
+  jv_stage_kernel<R, ND_, NZ_><<<grid, NT, 0, s>>>(p, base, bdata, x, y, shift, active, sX, sY, shifts, sA, zchunks, gx, gy, \
+                                       (int)ntot)
   if (p.ndim == 2)
-    jv_stage_kernel<R, 2><<<grid, NT, 0, s>>>(p, base, bdata, x, y, shift, active, sX, sY, shifts, sA, zchunks, gx,
-                                              gy, (int)ntot);
+    SA_LAUNCH(2, 16);   // one plane: the chunk depth is irrelevant
+  else if (nzc == 16)
+    SA_LAUNCH(3, 16);
   else
-    jv_stage_kernel<R, 3><<<grid, NT, 0, s>>>(p, base, bdata, x, y, shift, active, sX, sY, shifts, sA, zchunks, gx,
-                                              gy, (int)ntot);
+    SA_LAUNCH(3, 32);
+#undef SA_LAUNCH
   return hipGetLastError();
 }
 
 template hipError_t launch_jv_stage<double>(const OpParams&, const double*, const double*, const double*, double*,
                                            int, double, const int*, hipStream_t, long long, long long,
-                                           const double*, long long);
+                                           const double*, long long, int);
 template hipError_t launch_jv_stage<float>(const OpParams&, const float*, const float*, const float*, float*, int,
                                           float, const int*, hipStream_t, long long, long long, const double*,
-                                          long long);
+                                          long long, int);
 
 }  // namespace sa

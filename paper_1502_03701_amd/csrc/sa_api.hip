@@ -6,6 +6,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 using namespace sa;
@@ -48,6 +49,55 @@ void Ctx::drop_graphs() {
   hipStreamSynchronize(stream);
   for (auto& g : graphs) hipGraphExecDestroy(g.exec);
   graphs.clear();
+}
+
+// Time each operator kernel variant on this problem (one warm-up and three
+// timed launches, HIP events on the context's stream) and keep the fastest
+// per precision.  Inputs are the base fields themselves (finite values of
+// the right size); the output goes to a scratch buffer.
+static int autotune_jv(Ctx* c) {
+  if (jv_kernel_forced() || (std::getenv("SA_JV_AUTOTUNE") && std::strcmp(std::getenv("SA_JV_AUTOTUNE"), "0") == 0))
+    return SA_OK;
+  hipEvent_t ev0, ev1;
+  if (hipEventCreate(&ev0) != hipSuccess) return c->fail(SA_EDEVICE, "autotune: event");
+  if (hipEventCreate(&ev1) != hipSuccess) {
+    hipEventDestroy(ev0);
+    return c->fail(SA_EDEVICE, "autotune: event");
+  }
+  void* y = c->buffer("tune_y", sizeof(double) * c->n, false);
+  int rc = y ? SA_OK : c->fail(SA_ENOMEM, "autotune: out of device memory");
+  for (int pr = 0; pr < 2 && rc == SA_OK; ++pr) {
+    if (c->jv_pinned[pr]) continue;
+    float best = 0.0f;
+    int best_v = -1;
+    for (int v = 0; v < JV_NVARIANTS && rc == SA_OK; ++v) {
+      auto launch = [&]() -> hipError_t {
+        if (pr == 0)
+          return launch_jv<double>(c->op, c->base64, c->bdata64, c->base64, (double*)y, 1, 0.0, nullptr, c->stream, v);
+        return launch_jv<float>(c->op, c->base32, c->bdata32, c->base32, (float*)y, 1, 0.0f, nullptr, c->stream, v);
+      };
+      hipError_t e = launch();
+      if (e == hipSuccess) e = hipEventRecord(ev0, c->stream);
+      for (int it = 0; it < 3 && e == hipSuccess; ++it) e = launch();
+      if (e == hipSuccess) e = hipEventRecord(ev1, c->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(ev1);
+      float ms = 0.0f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev0, ev1);
+      if (e != hipSuccess) {
+        rc = c->hip_fail(e, "autotune");
+        break;
+      }
+      c->jv_tune_us[pr][v] = ms * 1000.0f / 3.0f;
+      if (best_v < 0 || ms < best) {
+        best = ms;
+        best_v = v;
+      }
+    }
+    if (rc == SA_OK) c->jv_variant[pr] = best_v;
+  }
+  hipEventDestroy(ev0);
+  hipEventDestroy(ev1);
+  return rc;
 }
 
 Ctx::~Ctx() {
@@ -143,8 +193,29 @@ int sa_base_set(sa_ctx* c, const sa_problem* pb, const double* q0_dev) {
   cast_d2f((long long)nbd, c->bdata64, c->bdata32, nullptr, c->stream);
   e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return c->hip_fail(e, "sa_base_set base data sync");
+  const int rc = autotune_jv(c);
+  if (rc != SA_OK) return rc;
   c->has_base = true;
   return SA_OK;
+}
+
+int sa_set_jv_variant(sa_ctx* c, sa_prec prec, int variant) {
+  if (!c) return SA_EINVAL;
+  if (prec != SA_F64 && prec != SA_F32) return c->fail(SA_EINVAL, "sa_set_jv_variant: precision must be F64 or F32");
+  if (variant < -1 || variant >= JV_NVARIANTS) return c->fail(SA_EINVAL, "sa_set_jv_variant: bad variant %d", variant);
+  const int pr = prec == SA_F64 ? 0 : 1;
+  c->drop_graphs();
+  c->jv_variant[pr] = variant;
+  c->jv_pinned[pr] = variant >= 0;
+  return SA_OK;
+}
+
+int sa_get_jv_variant(const sa_ctx* c, sa_prec prec, float* times_us) {
+  if (!c || (prec != SA_F64 && prec != SA_F32)) return SA_EINVAL;
+  const int pr = prec == SA_F64 ? 0 : 1;
+  if (times_us)
+    for (int v = 0; v < JV_NVARIANTS; ++v) times_us[v] = c->jv_tune_us[pr][v];
+  return c->jv_variant[pr];
 }
 
 int sa_op_apply(sa_ctx* c, sa_prec prec, int nrhs, const void* x_dev, void* y_dev, double shift) {

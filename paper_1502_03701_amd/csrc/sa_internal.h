@@ -37,42 +37,49 @@ int base_data_fields(int ndim);
 // Perturbation-only kernels with a register z-queue (need bdata).  nrhs
 // systems in one launch: system r uses x/y + r*sV (sV = 0: n), the shift
 // shifts[r] (device array; null: the scalar shift) and active[r*sA].
-// launch_jv_prefetch (jv_prefetch.hip) prefetches the next plane and is the FP64
-// default; launch_jv_stage (jv_stage.hip) stages whole planes and is the FP32
-// default; launch_jv_pert picks by precision.
+// launch_jv_prefetch (jv_prefetch.hip) prefetches the next plane (16 x 16
+// tiles); launch_jv_stage (jv_stage.hip) stages whole planes (32 x 8 tiles);
+// nzc (16 or 32) is the number of z planes a workgroup marches over.
 template <typename R>
 hipError_t launch_jv_prefetch(const OpParams& p, const R* base, const R* bdata, const R* x, R* y, int nrhs, R shift,
-                              const int* active, hipStream_t s, long long sX = 0, long long sY = 0,
-                              const double* shifts = nullptr, long long sA = 0);
+                              const int* active, hipStream_t s, long long sX, long long sY, const double* shifts,
+                              long long sA, int nzc);
 template <typename R>
 hipError_t launch_jv_stage(const OpParams& p, const R* base, const R* bdata, const R* x, R* y, int nrhs, R shift,
-                           const int* active, hipStream_t s, long long sX = 0, long long sY = 0,
-                           const double* shifts = nullptr, long long sA = 0);
+                           const int* active, hipStream_t s, long long sX, long long sY, const double* shifts,
+                           long long sA, int nzc);
+// The variants of the perturbation-only kernel (values of sa.h's
+// sa_jv_variant); -1 is the precision's default (prefetch z32 in FP64,
+// stage z16 in FP32).
+constexpr int JV_NVARIANTS = 4;   // prefetch z32, prefetch z16, stage z16, stage z32
 template <typename R>
 hipError_t launch_jv_pert(const OpParams& p, const R* base, const R* bdata, const R* x, R* y, int nrhs, R shift,
                           const int* active, hipStream_t s, long long sX = 0, long long sY = 0,
-                          const double* shifts = nullptr, long long sA = 0);
+                          const double* shifts = nullptr, long long sA = 0, int variant = -1);
 // A batch of systems: one launch with the default kernel, else one launch per
 // system.  System r reads x + r*sX, writes y + r*sY; shifts_host / shifts_dev
 // hold the per-system shifts.
 template <typename R>
 hipError_t launch_jv_batch(const OpParams& p, const R* base, const R* bdata, const R* x, R* y, int nsys,
                            long long sX, long long sY, const double* shifts_host, const double* shifts_dev,
-                           const int* active, long long sA, hipStream_t s);
+                           const int* active, long long sA, hipStream_t s, int variant = -1);
 hipError_t launch_base_data(const OpParams& p, const double* base, double* bdata, hipStream_t s);
 // Reference kernel (one thread per point, stencil taps straight from memory).
 template <typename R>
 hipError_t launch_jv_direct(const OpParams& p, const R* base, const R* x, R* y, int nrhs, R shift,
                             const int* active, hipStream_t s);
-// Operator dispatch: the perturbation-only kernel of the precision (default),
-// one of them for both precisions (SA_JV_KERNEL=prefetch or stage), the tiled
+// Operator dispatch: the perturbation-only kernel variant given (-1: the
+// precision's default), one of them for both precisions
+// (SA_JV_KERNEL=prefetch or stage), the tiled
 // kernel with precomputed base data (SA_JV_KERNEL=tiled), the tiled kernel
 // differentiating the base state every call (SA_JV_KERNEL=onthefly) or the
 // reference kernel (SA_JV_KERNEL=reference); the variable is read once per
 // process and serves to cross-check kernels.
 template <typename R>
 hipError_t launch_jv(const OpParams& p, const R* base, const R* bdata, const R* x, R* y, int nrhs, R shift,
-                     const int* active, hipStream_t s);
+                     const int* active, hipStream_t s, int variant = -1);
+// Whether SA_JV_KERNEL forces a kernel (then variants are not tuned).
+bool jv_kernel_forced();
 
 // Base-state preprocessing: fields T0, T_p, T_s appended after q0 (FP64),
 // and the FP32 shadow of the whole base array.  Returns via flag (device int)

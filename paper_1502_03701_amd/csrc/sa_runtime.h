@@ -44,6 +44,13 @@ struct Ctx {
   // y = (J - shift I) x in precision R on the context's stream
   template <typename R>
   hipError_t jv(const R* x, R* y, int nrhs, double shift, const int* active) const;
+  // operator kernel variant per precision ([0] FP64, [1] FP32; -1 default),
+  // chosen by timing at sa_base_set unless pinned by sa_set_jv_variant
+  int jv_variant[2] = {-1, -1};
+  bool jv_pinned[2] = {false, false};
+  float jv_tune_us[2][JV_NVARIANTS] = {};
+  template <typename R>
+  int variant_of() const { return jv_variant[sizeof(R) == 8 ? 0 : 1]; }
 
   // block-Jacobi preconditioner
   bool has_precond = false;
@@ -84,11 +91,11 @@ hipError_t precond_apply(Ctx* c, int ishift, int nrhs, const R* r, R* z, const i
 namespace sa {
 template <>
 inline hipError_t Ctx::jv<double>(const double* x, double* y, int nrhs, double shift, const int* active) const {
-  return launch_jv<double>(op, base64, bdata64, x, y, nrhs, shift, active, stream);
+  return launch_jv<double>(op, base64, bdata64, x, y, nrhs, shift, active, stream, jv_variant[0]);
 }
 template <>
 inline hipError_t Ctx::jv<float>(const float* x, float* y, int nrhs, double shift, const int* active) const {
-  return launch_jv<float>(op, base32, bdata32, x, y, nrhs, (float)shift, active, stream);
+  return launch_jv<float>(op, base32, bdata32, x, y, nrhs, (float)shift, active, stream, jv_variant[1]);
 }
 }  // namespace sa
 

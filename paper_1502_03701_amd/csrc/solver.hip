@@ -116,7 +116,8 @@ int solve_gmres(Ctx* c, const sa_gmres_opts& o, int nsys, const double* sigma, c
 
   // r = b - (J - sigma I) x -> V_s[:,0]; beta, convergence and budget tests
   auto start_cycle = [&](hipStream_t q) -> hipError_t {
-    hipError_t r = launch_jv_batch<R>(c->op, base, bdata, X, T, nsys, n, n, sigma, sig, nullptr, 0, q);
+    hipError_t r =
+        launch_jv_batch<R>(c->op, base, bdata, X, T, nsys, n, n, sigma, sig, nullptr, 0, q, c->variant_of<R>());
     if (r != hipSuccess) return r;
     bl.residual(n, B, T, V, &st->t.rnorm2, nullptr, q, bb, n, n);
     gstate_cycle_start(st, nsys, q);
@@ -135,7 +136,8 @@ int solve_gmres(Ctx* c, const sa_gmres_opts& o, int nsys, const double* sigma, c
         if (r != hipSuccess) return r;
         zj = zz;
       }
-      hipError_t r = launch_jv_batch<R>(c->op, base, bdata, zj, w, nsys, sv, sv, sigma, sig, act, GS_INTS, q);
+      hipError_t r = launch_jv_batch<R>(c->op, base, bdata, zj, w, nsys, sv, sv, sigma, sig, act, GS_INTS, q,
+                                        c->variant_of<R>());
       if (r != hipSuccess) return r;
       // CGS pass 1: d1 = V[0..j]^T w and ||w||^2
       bl.multidot(n, V, n, j + 2, w, st->d1, false, act, q, bb);
@@ -162,6 +164,7 @@ int solve_gmres(Ctx* c, const sa_gmres_opts& o, int nsys, const double* sigma, c
     put(key, m);
     put(key, pc_shift0);
     put(key, n);
+    put(key, c->variant_of<R>());
     for (const void* ptr : {(const void*)V, (const void*)Z, (const void*)T, (const void*)st, (const void*)sig,
                             (const void*)bl.partial, (const void*)bl.ticket, (const void*)X, (const void*)B, (const void*)base,
                             (const void*)bdata, (const void*)c->pc_lu, (const void*)c->pc_perm})

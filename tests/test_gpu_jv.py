@@ -61,6 +61,51 @@ def test_jv_fp32_parity(ctxs, name, prob, kind):
     assert rel(host(y), ref) < 1e-5
 
 
+VARIANT_CASES = [
+    ("2d-ragged-wall", synth.mixing_layer_2d(37, 29, 0.5, 1000.0), "random"),
+    ("3d-small", synth.mixing_layer_3d(12, 11, 10, 0.5, 1000.0), "random"),
+    ("3d-periodic", synth.mixing_layer_3d(9, 8, 7, 0.4, 500.0, bc_y=synth.BC_PERIODIC), "random"),
+    # 40 planes: a ragged last z chunk for both chunk depths (16, 32)
+    ("3d-zragged", synth.mixing_layer_3d(20, 13, 40, 0.5, 800.0), "noise"),
+]
+
+
+@pytest.mark.parametrize("variant", range(4))
+@pytest.mark.parametrize("name,prob,kind", VARIANT_CASES, ids=[c[0] for c in VARIANT_CASES])
+def test_jv_every_kernel_variant(ctxs, name, prob, kind, variant):
+    """Each operator kernel variant the autotuner may pick, pinned, in both
+    precisions, against the oracle (also with two right-hand sides)."""
+    from paper_1502_03701_amd import SA_F32, SA_F64
+    q0 = base_for(prob, kind)
+    v = synth.random_vector(prob, 5, nrhs=2)
+    ctx = ctxs()
+    ctx.base_set(prob, dev(q0))
+    ctx.set_jv_variant(SA_F64, variant)
+    ctx.set_jv_variant(SA_F32, variant)
+    assert ctx.jv_variant(SA_F64)[0] == variant and ctx.jv_variant(SA_F32)[0] == variant
+    ref = np.stack([op.jv_cstep(prob, q0, v[r]) - 0.1 * op.project(prob, v[r]) for r in range(2)])
+    y = torch.empty(2 * prob.ndof, dtype=torch.float64, device="cuda:0")
+    ctx.op_apply(dev(v), y, shift=0.1, nrhs=2)
+    assert rel(host(y), ref.ravel()) < 1e-12, (name, variant)
+    y32 = torch.empty(2 * prob.ndof, dtype=torch.float32, device="cuda:0")
+    ctx.op_apply(dev(v, torch.float32), y32, shift=0.1, nrhs=2)
+    assert rel(host(y32), ref.ravel()) < 1e-5, (name, variant)
+
+
+def test_autotuner_picks_a_measured_variant(ctxs):
+    from paper_1502_03701_amd import SA_F32, SA_F64, SAError
+    prob = synth.mixing_layer_3d(32, 16, 40, 0.5, 1000.0)
+    ctx = ctxs()
+    ctx.base_set(prob, dev(synth.base_flow(prob, seed=1, w_noise=1e-3)))
+    for prec in (SA_F64, SA_F32):
+        var, times = ctx.jv_variant(prec)
+        assert 0 <= var < 4
+        assert all(t > 0 for t in times.values())
+        assert list(times.values())[var] == min(times.values())
+    with pytest.raises(SAError):
+        ctx.set_jv_variant(SA_F64, 4)
+
+
 def test_jv_multi_rhs_and_wall_inputs_ignored(ctxs):
     prob = synth.mixing_layer_2d(24, 19, 0.5, 800.0)
     q0 = synth.random_base(prob, 9)
