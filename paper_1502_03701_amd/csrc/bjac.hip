@@ -12,9 +12,11 @@
 //    kept in FP64; the factor kernel rounds once to the factor precision.
 //  * One workgroup per (shift, block) factors a block in LDS by LU with
 //    partial pivoting and stores L\U column-major plus the row permutation.
-//  * The apply gathers r_b from the struct-of-arrays vector, solves
-//    L U z = P r with one wavefront per block (a lane per row, columns read
-//    coalesced), and scatters z back; wall DOFs give 0.
+//  * Factors are stored block-interleaved: 64 consecutive blocks form a
+//    group whose entry t is contiguous over the blocks.  The apply solves
+//    one block per lane, so each factor load is a coalesced row across the
+//    wave; it gathers r_b from the struct-of-arrays vector, solves
+//    L U z = P r and scatters z back; wall DOFs give 0.
 #include <cmath>
 #include <vector>
 
@@ -207,13 +209,25 @@ __global__ void __launch_bounds__(256) lu_kernel(BLayout L, const double* __rest
     }
     __syncthreads();
   }
-  F* out = LU + ((long long)s * L.nblocks + b) * nb * nb;
-  for (int t = threadIdx.x; t < nb * nb; t += blockDim.x) out[t] = A[t];
-  int* pout = perm + ((long long)s * L.nblocks + b) * nb;
-  for (int t = threadIdx.x; t < nb; t += blockDim.x) pout[t] = s_perm[t];
+  // block-interleaved output: group g = b / 64 holds entry t of its 64 blocks
+  // contiguously, so that the apply (one lane per block) reads coalesced
+  const long long g = b / 64;
+  const int lane = (int)(b % 64);
+  const long long ngroups = (L.nblocks + 63) / 64;
+  F* out = LU + ((long long)s * ngroups + g) * nb * nb * 64 + lane;
+  for (int t = threadIdx.x; t < nb * nb; t += blockDim.x) out[(long long)t * 64] = A[t];
+  int* pout = perm + ((long long)s * ngroups + g) * nb * 64 + lane;
+  for (int t = threadIdx.x; t < nb; t += blockDim.x) pout[t * 64] = s_perm[t];
 }
 
-// z_b = U^{-1} L^{-1} (P r_b) for one block per 64-lane workgroup; rows lane, lane+64
+// z_b = U^{-1} L^{-1} (P r_b), one lane per block: a wavefront solves the 64
+// blocks of one interleaved group, so every factor load is one coalesced
+// 256-byte row across the wave, and the loads (independent of the solve)
+// stream while the substitutions run.  The right-hand side / solution of a
+// lane lives in LDS (column lane, conflict-free), solved in place.
+// Dot-product form:
+//   forward  y_i = (P r)_i - sum_{j<i} L_ij y_j      (unit lower)
+//   backward z_i = (y_i - sum_{j>i} U_ij z_j) / U_ii
 template <typename F, typename R>
 __global__ void __launch_bounds__(64) apply_kernel(BLayout L, const F* __restrict__ LU, const int* __restrict__ perm,
                                                    int shift0, int shift_step, const R* __restrict__ r,
@@ -221,46 +235,48 @@ __global__ void __launch_bounds__(64) apply_kernel(BLayout L, const F* __restric
                                                    long long sA) {
   const int rhs = blockIdx.y;
   if (active && !active[rhs * sA]) return;
-  __shared__ F sr[128];
+  extern __shared__ unsigned char smem[];
+  F* xs = reinterpret_cast<F*>(smem);   // [nb][64]: column lane is this lane's vector
   const int nb = L.nb;
-  const long long b = blockIdx.x;
   const int lane = threadIdx.x;
+  const long long g = blockIdx.x;
+  const long long b = g * 64 + lane;
+  const bool valid = b < L.nblocks;
+  const long long bb = valid ? b : L.nblocks - 1;   // padding lanes solve a real block, store nothing
+  const long long ngroups = (L.nblocks + 63) / 64;
   const int shift = shift0 + rhs * shift_step;
   const R* rr = r + (long long)rhs * sV;
   R* zz = z + (long long)rhs * sV;
-  for (int l = lane; l < nb; l += 64) {
+  const F* A = LU + ((long long)shift * ngroups + g) * nb * nb * 64 + lane;   // entry (i, j) at (j nb + i) 64
+  const int* pg = perm + ((long long)shift * ngroups + g) * nb * 64 + lane;
+  if (!valid) A = LU + ((long long)shift * ngroups + g) * nb * nb * 64 + (bb % 64);
+  if (!valid) pg = perm + ((long long)shift * ngroups + g) * nb * 64 + (bb % 64);
+  // gather the permuted right-hand side (P r_b)_i = r_b[p(i)] into LDS
+  F* ys = xs;
+  for (int i = 0; i < nb; ++i) {
+    bool wall;
+    const long long d = block_dof(L, bb, pg[(long long)i * 64], wall);
+    ys[i * 64 + lane] = wall ? F(0) : (F)rr[d];
+  }
+  // forward, in place: y_i = (P r)_i - sum_{j<i} L_ij y_j
+  for (int i = 0; i < nb; ++i) {
+    F acc = ys[i * 64 + lane];
+#pragma unroll 8
+    for (int j = 0; j < i; ++j) acc -= A[((long long)j * nb + i) * 64] * ys[j * 64 + lane];
+    ys[i * 64 + lane] = acc;
+  }
+  // backward: z_i = (y_i - sum_{j>i} U_ij z_j) / U_ii, in place over y
+  for (int i = nb - 1; i >= 0; --i) {
+    F acc = ys[i * 64 + lane];
+#pragma unroll 8
+    for (int j = i + 1; j < nb; ++j) acc -= A[((long long)j * nb + i) * 64] * ys[j * 64 + lane];
+    ys[i * 64 + lane] = acc / A[((long long)i * nb + i) * 64];
+  }
+  if (!valid) return;
+  for (int l = 0; l < nb; ++l) {
     bool wall;
     const long long d = block_dof(L, b, l, wall);
-    sr[l] = wall ? F(0) : (F)rr[d];
-  }
-  __syncthreads();
-  const int* pb = perm + ((long long)shift * L.nblocks + b) * nb;
-  const F* A = LU + ((long long)shift * L.nblocks + b) * nb * nb;
-  F x0 = F(0), x1 = F(0);
-  if (lane < nb) x0 = sr[pb[lane]];
-  if (lane + 64 < nb) x1 = sr[pb[lane + 64]];
-  // forward: unit lower triangular
-  for (int j = 0; j < nb; ++j) {
-    const F yj = j < 64 ? __shfl(x0, j, 64) : __shfl(x1, j - 64, 64);
-    const F* col = A + (long long)j * nb;
-    if (lane > j && lane < nb) x0 -= col[lane] * yj;
-    if (lane + 64 > j && lane + 64 < nb) x1 -= col[lane + 64] * yj;
-  }
-  // backward: upper triangular
-  for (int j = nb - 1; j >= 0; --j) {
-    const F* col = A + (long long)j * nb;
-    F zj = j < 64 ? __shfl(x0, j, 64) : __shfl(x1, j - 64, 64);
-    zj = zj / col[j];
-    if (lane == j) x0 = zj;
-    if (lane + 64 == j) x1 = zj;
-    if (lane < j) x0 -= col[lane] * zj;
-    if (lane + 64 < j) x1 -= col[lane + 64] * zj;
-  }
-  for (int l = lane; l < nb; l += 64) {
-    bool wall;
-    const long long d = block_dof(L, b, l, wall);
-    const F v = l < 64 ? x0 : x1;
-    zz[d] = wall ? R(0) : (R)v;
+    zz[d] = wall ? R(0) : (R)ys[l * 64 + lane];
   }
 }
 
@@ -300,14 +316,14 @@ template <typename R>
 hipError_t precond_apply(Ctx* c, int ishift, int nrhs, const R* r, R* z, const int* active, int shift_step,
                          long long sV, long long sA, hipStream_t s) {
   BLayout L = layout_of(c);
-  dim3 grid((unsigned)L.nblocks, (unsigned)nrhs);
+  dim3 grid((unsigned)((L.nblocks + 63) / 64), (unsigned)nrhs);
   if (sV == 0) sV = c->n;
   if (c->pc_f64)
-    apply_kernel<double, R><<<grid, 64, 0, s>>>(L, (const double*)c->pc_lu, c->pc_perm, ishift, shift_step,
-                                                        r, z, sV, active, sA);
+    apply_kernel<double, R><<<grid, 64, sizeof(double) * L.nb * 64, s>>>(
+        L, (const double*)c->pc_lu, c->pc_perm, ishift, shift_step, r, z, sV, active, sA);
   else
-    apply_kernel<float, R><<<grid, 64, 0, s>>>(L, (const float*)c->pc_lu, c->pc_perm, ishift, shift_step,
-                                                       r, z, sV, active, sA);
+    apply_kernel<float, R><<<grid, 64, sizeof(float) * L.nb * 64, s>>>(
+        L, (const float*)c->pc_lu, c->pc_perm, ishift, shift_step, r, z, sV, active, sA);
   return hipGetLastError();
 }
 template hipError_t precond_apply<double>(Ctx*, int, int, const double*, double*, const int*, int, long long,
@@ -350,8 +366,9 @@ extern "C" int sa_precond_setup(sa_ctx* c, const sa_precond_opts* o, int nshift,
   double* sh = (double*)c->buffer("pc_shifts", sizeof(double) * nshift, false);
   int* flag = (int*)c->buffer("flag", sizeof(int));
   const size_t fsz = o->factor_prec == SA_F64 ? sizeof(double) : sizeof(float);
-  void* LU = c->buffer("pc_LU", fsz * (size_t)nshift * L.nblocks * L.nb * L.nb, false);
-  int* perm = (int*)c->buffer("pc_perm", sizeof(int) * (size_t)nshift * L.nblocks * L.nb, false);
+  const size_t padded = (size_t)((L.nblocks + 63) / 64) * 64;   // blocks, interleaved in groups of 64
+  void* LU = c->buffer("pc_LU", fsz * (size_t)nshift * padded * L.nb * L.nb, false);
+  int* perm = (int*)c->buffer("pc_perm", sizeof(int) * (size_t)nshift * padded * L.nb, false);
   const int batch = L.nb < 16 ? L.nb : 16;
   double* E = (double*)c->buffer("pc_probe", sizeof(double) * n * batch, false);
   double* Y = (double*)c->buffer("pc_resp", sizeof(double) * n * batch, false);

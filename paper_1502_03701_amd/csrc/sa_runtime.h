@@ -58,8 +58,9 @@ struct Ctx {
   int pc_nb = 0;           // block order
   long long pc_nblocks = 0;
   int pc_bx = 0, pc_by = 0, pc_bz = 0;
-  void* pc_lu = nullptr;   // [nshift][nblocks][nb x nb] L\U factors, column-major
-  int* pc_perm = nullptr;  // [nshift][nblocks][nb] row permutation of the pivoting
+  // factors, block-interleaved: [nshift][group][nb x nb entry, column-major][64 blocks]
+  void* pc_lu = nullptr;   // L\U of each block
+  int* pc_perm = nullptr;  // [nshift][group][nb][64] row permutation of the pivoting
   bool pc_f64 = false;     // factor precision
 
   // cached cycle graphs (captured on cap_stream, launched on stream); dropped
