@@ -11,7 +11,8 @@
 //    seeded standard normals (Philox4x32-10 + Box-Muller, one per entry),
 //    kept in FP64; the factor kernel rounds once to the factor precision.
 //  * One workgroup per (shift, block) factors a block in LDS by LU with
-//    partial pivoting and stores L\U column-major plus the row permutation.
+//    partial pivoting (wave-butterfly pivot search, three barriers per
+//    elimination step) and stores L\U plus the row permutation.
 //  * Factors are stored block-interleaved: 64 consecutive blocks form a
 //    group whose entry t is contiguous over the blocks.  The apply solves
 //    one block per lane, so each factor load is a coalesced row across the
@@ -129,7 +130,12 @@ __global__ void add_noise_kernel(BLayout L, double* __restrict__ B, double noise
   B[t] += noise_std * noise_entry(seed, b, row * L.nb + col);
 }
 
-// Factor B_b + (diag_add - shift_s) I.  One workgroup per (shift, block).
+// Factor B_b + (diag_add - shift_s) I, one workgroup of 256 threads per
+// (block, shift).  The block sits in LDS (column-major, nb x nb).  Per
+// elimination step the first wave finds the pivot (first largest |a_ik|,
+// i >= k) by a butterfly over its lanes, then all threads swap rows k and p,
+// scale the column and update the trailing matrix (one element per thread
+// and pass): three workgroup barriers per step.
 template <typename F>
 __global__ void __launch_bounds__(256) lu_kernel(BLayout L, const double* __restrict__ B, const double* __restrict__ shifts,
                                                  double diag_add, F* __restrict__ LU, int* __restrict__ perm,
@@ -137,60 +143,56 @@ __global__ void __launch_bounds__(256) lu_kernel(BLayout L, const double* __rest
   extern __shared__ unsigned char smem[];
   F* A = reinterpret_cast<F*>(smem);            // nb x nb column-major
   __shared__ int s_perm[128];
-  __shared__ F s_redv[256];
-  __shared__ int s_redi[256];
   __shared__ int s_piv;
   const int nb = L.nb;
+  const int tid = threadIdx.x;
   const long long b = blockIdx.x;
   const int s = blockIdx.y;
   const double dshift = diag_add - shifts[s];
   const double* Bb = B + b * nb * nb;
-  for (int t = threadIdx.x; t < nb * nb; t += blockDim.x) {
+  for (int t = tid; t < nb * nb; t += blockDim.x) {
     const int col = t / nb, row = t % nb;
     double v = Bb[t];
     if (row == col) v += dshift;
     A[t] = (F)v;
   }
-  for (int t = threadIdx.x; t < nb; t += blockDim.x) s_perm[t] = t;
+  for (int t = tid; t < nb; t += blockDim.x) s_perm[t] = t;
   __syncthreads();
+  bool sing = false;
   for (int k = 0; k < nb; ++k) {
-    // pivot: argmax |A[i][k]|, i >= k (first maximum)
-    F best = F(-1);
-    int bi = k;
-    for (int i = k + threadIdx.x; i < nb; i += blockDim.x) {
-      const F v = fabs(A[k * nb + i]);
-      if (v > best) {
-        best = v;
-        bi = i;
-      }
-    }
-    s_redv[threadIdx.x] = best;
-    s_redi[threadIdx.x] = bi;
-    __syncthreads();
-    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
-      if (threadIdx.x < off) {
-        const F v2 = s_redv[threadIdx.x + off];
-        const int i2 = s_redi[threadIdx.x + off];
-        if (v2 > s_redv[threadIdx.x] || (v2 == s_redv[threadIdx.x] && i2 < s_redi[threadIdx.x])) {
-          s_redv[threadIdx.x] = v2;
-          s_redi[threadIdx.x] = i2;
+    if (tid < 64) {
+      F best = F(-1);
+      int bi = nb;
+      for (int i = k + tid; i < nb; i += 64) {
+        const F v = fabs(A[k * nb + i]);
+        if (v > best) {
+          best = v;
+          bi = i;
         }
       }
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-      s_piv = s_redi[0];
-      if (!(s_redv[0] > F(0))) atomicOr(singular, 1);
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const F ov = __shfl_xor(best, off, 64);
+        const int oi = __shfl_xor(bi, off, 64);
+        if (ov > best || (ov == best && oi < bi)) {
+          best = ov;
+          bi = oi;
+        }
+      }
+      if (tid == 0) {
+        s_piv = bi < nb ? bi : k;
+        if (!(best > F(0))) sing = true;
+      }
     }
     __syncthreads();
     const int p = s_piv;
     if (p != k) {
-      for (int c = threadIdx.x; c < nb; c += blockDim.x) {
+      for (int c = tid; c < nb; c += blockDim.x) {
         const F t1 = A[c * nb + k];
         A[c * nb + k] = A[c * nb + p];
         A[c * nb + p] = t1;
       }
-      if (threadIdx.x == 0) {
+      if (tid == 0) {
         const int t2 = s_perm[k];
         s_perm[k] = s_perm[p];
         s_perm[p] = t2;
@@ -199,25 +201,26 @@ __global__ void __launch_bounds__(256) lu_kernel(BLayout L, const double* __rest
     __syncthreads();
     const F piv = A[k * nb + k];
     const F ipiv = piv != F(0) ? F(1) / piv : F(0);
-    for (int i = k + 1 + threadIdx.x; i < nb; i += blockDim.x) A[k * nb + i] *= ipiv;
-    __syncthreads();
-    // trailing update A[i][c] -= A[i][k] A[k][c], i, c > k
+    // trailing update with the scaled column: a_ic -= (a_ik / a_kk) a_kc
     const int rem = nb - k - 1;
-    for (int t = threadIdx.x; t < rem * rem; t += blockDim.x) {
+    for (int t = tid; t < rem * rem; t += blockDim.x) {
       const int c = k + 1 + t / rem, i = k + 1 + t % rem;
-      A[c * nb + i] -= A[k * nb + i] * A[c * nb + k];
+      A[c * nb + i] -= A[k * nb + i] * ipiv * A[c * nb + k];
     }
     __syncthreads();
+    for (int i = k + 1 + tid; i < nb; i += blockDim.x) A[k * nb + i] *= ipiv;
   }
+  __syncthreads();
+  if (sing) atomicOr(singular, 1);
   // block-interleaved output: group g = b / 64 holds entry t of its 64 blocks
-  // contiguously, so that the apply (one lane per block) reads coalesced
+  // contiguously, so that the apply (one lane per block) reads coalesced rows
   const long long g = b / 64;
-  const int lane = (int)(b % 64);
+  const int gl = (int)(b % 64);
   const long long ngroups = (L.nblocks + 63) / 64;
-  F* out = LU + ((long long)s * ngroups + g) * nb * nb * 64 + lane;
-  for (int t = threadIdx.x; t < nb * nb; t += blockDim.x) out[(long long)t * 64] = A[t];
-  int* pout = perm + ((long long)s * ngroups + g) * nb * 64 + lane;
-  for (int t = threadIdx.x; t < nb; t += blockDim.x) pout[t * 64] = s_perm[t];
+  F* out = LU + ((long long)s * ngroups + g) * nb * nb * 64 + gl;
+  for (int t = tid; t < nb * nb; t += blockDim.x) out[(long long)t * 64] = A[t];
+  int* pout = perm + ((long long)s * ngroups + g) * nb * 64 + gl;
+  for (int t = tid; t < nb; t += blockDim.x) pout[t * 64] = s_perm[t];
 }
 
 // z_b = U^{-1} L^{-1} (P r_b), one lane per block: a wavefront solves the 64
@@ -390,8 +393,8 @@ extern "C" int sa_precond_setup(sa_ctx* c, const sa_precond_opts* o, int nshift,
   if (o->noise_std != 0.0)
     add_noise_kernel<<<blocks_for(L.nblocks * L.nb * L.nb, 256), 256, 0, s>>>(L, B, o->noise_std, o->seed);
   hipMemsetAsync(flag, 0, sizeof(int), s);
-  dim3 grid((unsigned)L.nblocks, (unsigned)nshift);
   const size_t lds = fsz * L.nb * L.nb;
+  dim3 grid((unsigned)L.nblocks, (unsigned)nshift);
   if (o->factor_prec == SA_F64)
     lu_kernel<double><<<grid, 256, lds, s>>>(L, B, sh, o->diag_add, (double*)LU, perm, flag);
   else
