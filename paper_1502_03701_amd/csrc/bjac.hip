@@ -11,8 +11,10 @@
 //    seeded standard normals (Philox4x32-10 + Box-Muller, one per entry),
 //    kept in FP64; the factor kernel rounds once to the factor precision.
 //  * One workgroup per (shift, block) factors a block in LDS by LU with
-//    partial pivoting (wave-butterfly pivot search, three barriers per
-//    elimination step) and stores L\U plus the row permutation.
+//    partial pivoting and stores L\U plus the row permutation: FP32 blocks
+//    of order 16k by a blocked LU whose trailing updates run on the matrix
+//    cores (one wavefront per block), other blocks unblocked (wave-butterfly
+//    pivot search, three barriers per elimination step).
 //  * Factors are stored block-interleaved: 64 consecutive blocks form a
 //    group whose entry t is contiguous over the blocks.  The apply solves
 //    one block per lane, so each factor load is a coalesced row across the
@@ -130,6 +132,20 @@ __global__ void add_noise_kernel(BLayout L, double* __restrict__ B, double noise
   B[t] += noise_std * noise_entry(seed, b, row * L.nb + col);
 }
 
+// (block, shift) of a factorisation workgroup.  Hardware workgroup L runs on
+// XCD L % 8; consecutive blocks are given to one XCD so that the 64 blocks of
+// an interleaved output group merge their partial cache-line writes in that
+// XCD's L2.
+__device__ __forceinline__ void lu_work_item(long long nblocks, long long& b, int& s) {
+  const long long ntot = (long long)gridDim.x;
+  const long long L = blockIdx.x;
+  const long long per = ntot / 8, rem = ntot % 8;
+  const long long xcd = L % 8, idx = L / 8;
+  const long long lb = xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
+  b = lb % nblocks;
+  s = (int)(lb / nblocks);
+}
+
 // Factor B_b + (diag_add - shift_s) I, one workgroup of 256 threads per
 // (block, shift).  The block sits in LDS (column-major, nb x nb).  Per
 // elimination step the first wave finds the pivot (first largest |a_ik|,
@@ -146,15 +162,24 @@ __global__ void __launch_bounds__(256) lu_kernel(BLayout L, const double* __rest
   __shared__ int s_piv;
   const int nb = L.nb;
   const int tid = threadIdx.x;
-  const long long b = blockIdx.x;
-  const int s = blockIdx.y;
+  long long b;
+  int s;
+  lu_work_item(L.nblocks, b, s);
   const double dshift = diag_add - shifts[s];
   const double* Bb = B + b * nb * nb;
-  for (int t = tid; t < nb * nb; t += blockDim.x) {
-    const int col = t / nb, row = t % nb;
-    double v = Bb[t];
-    if (row == col) v += dshift;
-    A[t] = (F)v;
+  // all of a thread's loads in flight together (at most 64 per thread)
+  for (int t0 = 0; t0 < nb * nb; t0 += 256 * 16) {
+    double v[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int t = t0 + tid + 256 * q;
+      v[q] = t < nb * nb ? Bb[t] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int t = t0 + tid + 256 * q;
+      if (t < nb * nb) A[t] = (F)(t / nb == t % nb ? v[q] + dshift : v[q]);
+    }
   }
   for (int t = tid; t < nb; t += blockDim.x) s_perm[t] = t;
   __syncthreads();
@@ -221,6 +246,152 @@ __global__ void __launch_bounds__(256) lu_kernel(BLayout L, const double* __rest
   for (int t = tid; t < nb * nb; t += blockDim.x) out[(long long)t * 64] = A[t];
   int* pout = perm + ((long long)s * ngroups + g) * nb * 64 + gl;
   for (int t = tid; t < nb; t += blockDim.x) pout[t * 64] = s_perm[t];
+}
+
+// FP32 factors of orders that are multiples of 16 (the C3 blocks are 80):
+// blocked right-looking LU, one wavefront per (block, shift), the block in
+// LDS.  Per 16-column panel: unblocked elimination of the panel with partial
+// pivoting (wave butterfly for the pivot, rows swapped across the whole
+// block), the triangular solve U12 = L11^-1 A12 (a lane per column), and the
+// trailing update A22 -= L21 U12 on the matrix cores: 16 x 16 output tiles,
+// four v_mfma_f32_16x16x4f32 each (K = 16).  Operand layout of that
+// instruction for lane l: A[i][k] with i = l % 16, k = l / 16; B[k][j] with
+// j = l % 16, k = l / 16; accumulator v of D[i][j] with i = 4 (l / 16) + v,
+// j = l % 16.
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(64) lu_mfma_kernel(BLayout L, const double* __restrict__ B,
+                                                     const double* __restrict__ shifts, double diag_add,
+                                                     float* __restrict__ LU, int* __restrict__ perm,
+                                                     int* __restrict__ singular) {
+  extern __shared__ unsigned char smem[];
+  float* A = reinterpret_cast<float*>(smem);   // nb x nb column-major
+  __shared__ int s_perm[128];
+  const int nb = L.nb;
+  const int lane = threadIdx.x;
+  long long b;
+  int s;
+  lu_work_item(L.nblocks, b, s);
+  const double dshift = diag_add - shifts[s];
+  const double* Bb = B + b * nb * nb;
+  // 20 loads in flight per lane per batch (the block is 51 KB of FP64)
+  for (int t0 = 0; t0 < nb * nb; t0 += 64 * 20) {
+    double v[20];
+#pragma unroll
+    for (int q = 0; q < 20; ++q) {
+      const int t = t0 + lane + 64 * q;
+      v[q] = t < nb * nb ? Bb[t] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 20; ++q) {
+      const int t = t0 + lane + 64 * q;
+      if (t < nb * nb) A[t] = (float)(t / nb == t % nb ? v[q] + dshift : v[q]);
+    }
+  }
+  for (int t = lane; t < nb; t += 64) s_perm[t] = t;
+  __syncthreads();
+  bool sing = false;
+  const int li = lane % 16, lk = lane / 16;
+  for (int c0 = 0; c0 < nb; c0 += 16) {
+    // panel elimination, columns c0 .. c0+15
+    for (int k = c0; k < c0 + 16; ++k) {
+      float best = -1.0f;
+      int bi = nb;
+      for (int i = k + lane; i < nb; i += 64) {
+        const float v = fabsf(A[k * nb + i]);
+        if (v > best) {
+          best = v;
+          bi = i;
+        }
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const float ov = __shfl_xor(best, off, 64);
+        const int oi = __shfl_xor(bi, off, 64);
+        if (ov > best || (ov == best && oi < bi)) {
+          best = ov;
+          bi = oi;
+        }
+      }
+      if (!(best > 0.0f)) sing = true;
+      const int p = bi < nb ? bi : k;
+      if (p != k) {
+        for (int c = lane; c < nb; c += 64) {
+          const float t1 = A[c * nb + k];
+          A[c * nb + k] = A[c * nb + p];
+          A[c * nb + p] = t1;
+        }
+        if (lane == 0) {
+          const int t2 = s_perm[k];
+          s_perm[k] = s_perm[p];
+          s_perm[p] = t2;
+        }
+      }
+      __syncthreads();
+      const float piv = A[k * nb + k];
+      const float ipiv = piv != 0.0f ? 1.0f / piv : 0.0f;
+      // row k of the panel (broadcast) and this lane's rows, read in one go,
+      // updated in registers, written back: no load waits on a prior store
+      float urow[16];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) urow[c] = c0 + c > k ? A[(c0 + c) * nb + k] : 0.0f;
+      for (int i = k + 1 + lane; i < nb; i += 64) {
+        float mine[16];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) mine[c] = A[(c0 + c) * nb + i];
+        const float lik = A[k * nb + i] * ipiv;
+#pragma unroll
+        for (int c = 0; c < 16; ++c)
+          if (c0 + c > k) mine[c] -= lik * urow[c];
+#pragma unroll
+        for (int c = 0; c < 16; ++c)
+          if (c0 + c > k) A[(c0 + c) * nb + i] = mine[c];
+        A[k * nb + i] = lik;
+      }
+      __syncthreads();
+    }
+    const int c1 = c0 + 16;
+    if (c1 >= nb) break;
+    // U12 = L11^-1 A12 (unit lower L11), a lane per column
+    for (int c = c1 + lane; c < nb; c += 64) {
+      float x[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) x[i] = A[c * nb + c0 + i];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+#pragma unroll
+        for (int i = j + 1; i < 16; ++i) x[i] -= A[(c0 + j) * nb + c0 + i] * x[j];
+      }
+#pragma unroll
+      for (int i = 1; i < 16; ++i) A[c * nb + c0 + i] = x[i];
+    }
+    __syncthreads();
+    // A22 -= L21 U12, 16 x 16 tiles on the matrix cores
+    const int nt = (nb - c1) / 16;
+    for (int t = 0; t < nt * nt; ++t) {
+      const int r0 = c1 + 16 * (t % nt), q0 = c1 + 16 * (t / nt);
+      floatx4 acc;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[v] = A[(q0 + li) * nb + r0 + 4 * lk + v];
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const float a = -A[(c0 + 4 * kk + lk) * nb + r0 + li];    // -L21[r0+li][c0+4kk+lk]
+        const float bv = A[(q0 + li) * nb + c0 + 4 * kk + lk];    // U12[c0+4kk+lk][q0+li]
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv, acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) A[(q0 + li) * nb + r0 + 4 * lk + v] = acc[v];
+    }
+    __syncthreads();
+  }
+  if (sing && lane == 0) atomicOr(singular, 1);
+  const long long g = b / 64;
+  const int gl = (int)(b % 64);
+  const long long ngroups = (L.nblocks + 63) / 64;
+  float* out = LU + ((long long)s * ngroups + g) * nb * nb * 64 + gl;
+  for (int t = lane; t < nb * nb; t += 64) out[(long long)t * 64] = A[t];
+  int* pout = perm + ((long long)s * ngroups + g) * nb * 64 + gl;
+  for (int t = lane; t < nb; t += 64) pout[t * 64] = s_perm[t];
 }
 
 // z_b = U^{-1} L^{-1} (P r_b), one lane per block: a wavefront solves the 64
@@ -394,9 +565,12 @@ extern "C" int sa_precond_setup(sa_ctx* c, const sa_precond_opts* o, int nshift,
     add_noise_kernel<<<blocks_for(L.nblocks * L.nb * L.nb, 256), 256, 0, s>>>(L, B, o->noise_std, o->seed);
   hipMemsetAsync(flag, 0, sizeof(int), s);
   const size_t lds = fsz * L.nb * L.nb;
-  dim3 grid((unsigned)L.nblocks, (unsigned)nshift);
+  if ((long long)L.nblocks * nshift >= (1LL << 31)) return c->fail(SA_EINVAL, "sa_precond_setup: too many blocks");
+  const unsigned grid = (unsigned)(L.nblocks * nshift);
   if (o->factor_prec == SA_F64)
     lu_kernel<double><<<grid, 256, lds, s>>>(L, B, sh, o->diag_add, (double*)LU, perm, flag);
+  else if (L.nb % 16 == 0)
+    lu_mfma_kernel<<<grid, 64, lds, s>>>(L, B, sh, o->diag_add, (float*)LU, perm, flag);
   else
     lu_kernel<float><<<grid, 256, lds, s>>>(L, B, sh, o->diag_add, (float*)LU, perm, flag);
   hipError_t e = hipGetLastError();

@@ -26,6 +26,8 @@ CASES = [
     ("2d", synth.mixing_layer_2d(16, 16, 0.3, 500.0), (4, 4, 1)),
     ("2d-rect", synth.mixing_layer_2d(24, 12, 0.5, 1000.0), (4, 2, 1)),
     ("3d", synth.mixing_layer_3d(8, 8, 8, 0.5, 1000.0), (4, 4, 1)),
+    # order 40: not a multiple of 16, so FP32 factors take the unblocked kernel
+    ("2d-nb40", synth.mixing_layer_2d(20, 12, 0.5, 1000.0), (5, 2, 1)),
 ]
 
 
