@@ -260,7 +260,40 @@ def extras(torch, dev, ctx3, prob3):
                                         "lam": [[l.real, l.imag] for l in r[0]["lam"]],
                                         "n_matvec": r[0]["n_matvec"]}
     res.update(sweep(torch, dev, log=lambda m: print(m, file=sys.stderr, flush=True)))
+    res.update(eigs_3d(torch, dev, log=lambda m: print(m, file=sys.stderr, flush=True)))
     return res
+
+
+def eigs_3d(torch, dev, side=32, nev=2, ncv=16, max_restarts=60, log=None):
+    """Time to the leading eigenpairs of a 3D mixing layer (side^3, M = 0.5,
+    Re = 1000, 1e-3 spanwise noise), FP64 against the mixed form, and the
+    mixed eigenvalues' relative deviation from the FP64 ones."""
+    import synth
+    from paper_1502_03701_amd import SA_F64, SA_MIXED, Context, arnoldi_eigs
+    p = synth.mixing_layer_3d(side, side, side, 0.5, 1000.0)
+    ctx = Context()
+    ctx.base_set(p, torch.from_numpy(synth.base_flow(p, seed=1, w_noise=1e-3).ravel()).to(dev))
+    v0 = torch.from_numpy(synth.random_vector(p, 0).ravel()).to(dev)
+    out, lam = {}, {}
+    for name, prec in (("fp64", SA_F64), ("mixed", SA_MIXED)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, r = arnoldi_eigs([ctx], [v0], nev=nev, ncv=ncv, sigma=0.2, mu=-0.2, tol=1e-10, max_restarts=max_restarts,
+                             restart=40, lin_tol=1e-12, prec=prec, inner_tol=1e-4, max_outer=30)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        lam[name] = r[0]["lam"]
+        out["eigs_3d_%d_nev%d_%s" % (side, nev, name)] = {"seconds": el, "rc": rc, "nconv": r[0]["nconv"],
+                                                "n_matvec": r[0]["n_matvec"], "n_cayley": r[0]["n_cayley"],
+                                                "lam": [[l.real, l.imag] for l in r[0]["lam"]]}
+        if log:
+            log("eigs 3d %d %s: %.1f s, %d matvecs" % (side, name, el, r[0]["n_matvec"]))
+    dev_rel = [abs(a - b) / abs(a) for a, b in zip(sorted(lam["fp64"], key=abs), sorted(lam["mixed"], key=abs))]
+    key = "eigs_3d_%d_nev%d_" % (side, nev)
+    out[key + "mixed_vs_fp64"] = {"speedup": out[key + "fp64"]["seconds"] / out[key + "mixed"]["seconds"],
+                                  "max_rel_dev": max(dev_rel)}
+    ctx.close()
+    return out
 
 
 def sweep(torch, dev, nev=2, log=None):

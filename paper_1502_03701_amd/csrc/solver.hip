@@ -246,7 +246,8 @@ template int solve_gmres<float>(Ctx*, const sa_gmres_opts&, int, const double*, 
                                 sa_gmres_info*, const std::string&);
 
 // Iterative refinement: FP64 residual and update, FP32 GMRES on the scaled
-// residual equation.
+// residual equation r/||r||, solved to inner_tol relative, or only as far as
+// the outer tolerance still requires (so the last sweep does not overshoot).
 int solve_ir(Ctx* c, const sa_gmres_opts& o, double sigma, const double* b, double* x, int pc_shift,
              sa_gmres_info* info) {
   hipStream_t s = c->stream;
@@ -306,6 +307,9 @@ int solve_ir(Ctx* c, const sa_gmres_opts& o, double sigma, const double* b, doub
     bl32.fill(n, d32, 0.0f, s);
     sa_gmres_info ii{};
     in.max_matvec = std::max<long long>(1, o.max_matvec - info->matvecs);
+    // the last sweeps need only close the remaining gap: ask the inner solve
+    // for max(inner_tol, tol ||b|| / (2 ||r||)), never looser than 1/2
+    in.tol = std::min(0.5, std::max(o.inner_tol, 0.5 * o.tol / h[0].relres));
     int rc = solve_gmres<float>(c, in, 1, &sigma, r32, d32, pc_shift, &ii, "ir32");
     if (rc < 0) return rc;
     inner_mv += ii.matvecs;
