@@ -59,6 +59,15 @@ def measured_traffic():
     return int(fields["traffic_bytes_per_launch"])
 
 
+def calib_copy(torch, dev):
+    """A device copy of known size, 16x the 256 MB last-level cache: reads and
+    writes 4 GiB each (the reference for the rocprofv3 byte counters)."""
+    ca = torch.ones(512 * 1024 * 1024, dtype=torch.float64, device=dev)
+    cb = torch.empty_like(ca)
+    timed(lambda: cb.copy_(ca), 2, 0, torch)
+    del ca, cb
+
+
 def timed(fn, steps, warmup, torch):
     """Seconds for `steps` calls, HIP events on the current stream (the
     stream the library launches on)."""
@@ -117,6 +126,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a device copy of known size (counter calibration)")
+    ap.add_argument("--bjac-only", action="store_true",
+                    help="only the block-Jacobi setup and apply of the 3D grid (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -134,6 +145,12 @@ def main():
     v = synth.random_vector(prob, 2)
     ctx = Context()
     ctx.base_set(prob, torch.from_numpy(q0.ravel()).to(dev))
+    if args.bjac_only:
+        out = bjac(torch, dev, ctx, prob)
+        if args.calib_copy:
+            calib_copy(torch, dev)
+        print(json.dumps(out))
+        return
     x = torch.from_numpy(v.ravel()).to(dev)
     y = torch.empty_like(x)
     npts = prob.npts
@@ -158,12 +175,7 @@ def main():
     per32 = sec32 / args.steps
 
     if args.calib_copy:
-        # device copy of known size, 16x the 256 MB last-level cache: reads and
-        # writes 4 GiB each (the reference for the rocprof byte counters)
-        ca = torch.ones(512 * 1024 * 1024, dtype=torch.float64, device=dev)
-        cb = torch.empty_like(ca)
-        timed(lambda: cb.copy_(ca), 2, 0, torch)
-        del ca, cb
+        calib_copy(torch, dev)
 
     out = {
         "metric": METRIC,
@@ -198,6 +210,26 @@ def main():
     print(json.dumps(out))
 
 
+def bjac(torch, dev, ctx3, prob3):
+    """Block-Jacobi of the 3D grid: 4x4x1-cell blocks x 5 vars = 80x80,
+    262144 blocks, 8 shifts 0.05..0.40, FP32 factors; setup wall time and
+    apply time per shift (HIP events)."""
+    import synth
+    shifts = synth.config3_shifts()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx3.precond_setup(shifts, 4, 4, 1, diag_add=0.1, noise_std=0.01, seed=3)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    r32 = torch.from_numpy(synth.random_vector(prob3, 3).ravel()).to(dev).float()
+    z32 = torch.empty_like(r32)
+    t_apply = timed(lambda: ctx3.precond_apply(0, r32, z32), 10, 2, torch) / 10
+    nblocks = prob3.npts // 16
+    return {"bjac_256x128x128_8shifts": {
+        "setup_s": t_setup, "nblocks": nblocks, "nb": 80, "apply_ms_per_shift": t_apply * 1e3,
+        "apply_factor_GBs": nblocks * 80 * 80 * 4 / t_apply / 1e9}}
+
+
 def extras(torch, dev, ctx3, prob3):
     """Secondary measurements (not the headline value)."""
     import synth
@@ -211,19 +243,8 @@ def extras(torch, dev, ctx3, prob3):
         torch.cuda.synchronize()
         return r, time.perf_counter() - t0
 
-    # block-Jacobi of the 3D grid: 4x4x1-cell blocks x 5 vars = 80x80, 262144
-    # blocks, 8 shifts 0.05..0.40, FP32 factors
     shifts = synth.config3_shifts()
-    _, t_setup = wall(lambda: ctx3.precond_setup(shifts, 4, 4, 1, diag_add=0.1, noise_std=0.01, seed=3))
-    r = torch.from_numpy(synth.random_vector(prob3, 3).ravel()).to(dev)
-    r32 = r.float()
-    z32 = torch.empty_like(r32)
-    t_apply = timed(lambda: ctx3.precond_apply(0, r32, z32), 5, 1, torch) / 5
-    nblocks = prob3.npts // 16
-    res["bjac_256x128x128_8shifts"] = {
-        "setup_s": t_setup, "nblocks": nblocks, "nb": 80,
-        "apply_ms_per_shift": t_apply * 1e3,
-        "apply_factor_GBs": nblocks * 80 * 80 * 4 / t_apply / 1e9}
+    res.update(bjac(torch, dev, ctx3, prob3))
     # 8 shifts advanced together: one GMRES(30) cycle, FP32, preconditioned vs not
     B = torch.from_numpy(synth.random_vector(prob3, 4, nrhs=8).ravel()).to(dev).float()
     for use_pc in (False, True):
