@@ -128,6 +128,9 @@ def main():
                     help="also run a device copy of known size (counter calibration)")
     ap.add_argument("--bjac-only", action="store_true",
                     help="only the block-Jacobi setup and apply of the 3D grid (for profiling)")
+    ap.add_argument("--gmres-only", action="store_true",
+                    help="only capped GMRES runs: 512x512 FP64 (1 and 8 shifts), one FP32 cycle of "
+                         "8 shifts on the 3D grid (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -145,6 +148,9 @@ def main():
     v = synth.random_vector(prob, 2)
     ctx = Context()
     ctx.base_set(prob, torch.from_numpy(q0.ravel()).to(dev))
+    if args.gmres_only:
+        print(json.dumps(gmres_runs(torch, dev, ctx, prob)))
+        return
     if args.bjac_only:
         out = bjac(torch, dev, ctx, prob)
         if args.calib_copy:
@@ -230,6 +236,47 @@ def bjac(torch, dev, ctx3, prob3):
         "apply_factor_GBs": nblocks * 80 * 80 * 4 / t_apply / 1e9}}
 
 
+def gmres_runs(torch, dev, ctx3, prob3, max_mv_512=2000):
+    """GMRES step costs: one FP32 GMRES(30) cycle of the 8 shifts in lockstep on
+    the 3D grid (with the block-Jacobi factors if they are set up), GMRES(40)
+    at 512 x 512 FP64 for one shift and for 8 shifts in lockstep (capped)."""
+    import synth
+    from paper_1502_03701_amd import SA_F32, Context
+    res = {}
+    shifts = synth.config3_shifts()
+
+    def wall(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return r, time.perf_counter() - t0
+
+    B = torch.from_numpy(synth.random_vector(prob3, 4, nrhs=8).ravel()).to(dev).float()
+    for use_pc in ((False, True) if ctx3.has_precond() else (False,)):
+        X = torch.zeros_like(B)
+        (rc, info), el = wall(lambda: ctx3.gmres_solve(shifts, B, X, restart=30, tol=1e-6, max_matvec=31,
+                                                      use_precond=use_pc, prec=SA_F32))
+        res["gmres30_fp32_8shifts_" + ("bjac" if use_pc else "plain")] = {
+            "seconds_one_cycle": el, "relres": [i["relres"] for i in info], "iters": [i["iters"] for i in info]}
+    del B, X
+    p1 = synth.config1()
+    c1 = Context()
+    c1.base_set(p1, torch.from_numpy(synth.base_flow(p1).ravel()).to(dev))
+    b = torch.from_numpy(synth.random_vector(p1, 1).ravel()).to(dev)
+    x = torch.zeros_like(b)
+    (rc, info), el = wall(lambda: c1.gmres_solve([0.2], b, x, restart=40, tol=1e-10, max_matvec=max_mv_512))
+    res["gmres40_512x512"] = {"iters": info[0]["iters"], "relres": info[0]["relres"],
+                              "ms_per_iter": el / max(1, info[0]["iters"]) * 1e3}
+    B8 = torch.from_numpy(synth.random_vector(p1, 5, nrhs=8).ravel()).to(dev)
+    X8 = torch.zeros_like(B8)
+    (rc, info), el = wall(lambda: c1.gmres_solve(shifts, B8, X8, restart=40, tol=1e-10, max_matvec=401))
+    res["gmres40_512x512_8shifts"] = {"ms_per_iter_all_shifts": el / max(1, info[0]["iters"]) * 1e3,
+                                      "iters": info[0]["iters"]}
+    c1.close()
+    return res
+
+
 def extras(torch, dev, ctx3, prob3):
     """Secondary measurements (not the headline value)."""
     import synth
@@ -243,32 +290,8 @@ def extras(torch, dev, ctx3, prob3):
         torch.cuda.synchronize()
         return r, time.perf_counter() - t0
 
-    shifts = synth.config3_shifts()
     res.update(bjac(torch, dev, ctx3, prob3))
-    # 8 shifts advanced together: one GMRES(30) cycle, FP32, preconditioned vs not
-    B = torch.from_numpy(synth.random_vector(prob3, 4, nrhs=8).ravel()).to(dev).float()
-    for use_pc in (False, True):
-        X = torch.zeros_like(B)
-        (rc, info), el = wall(lambda: ctx3.gmres_solve(shifts, B, X, restart=30, tol=1e-6, max_matvec=31,
-                                                      use_precond=use_pc, prec=SA_F32))
-        res["gmres30_fp32_8shifts_" + ("bjac" if use_pc else "plain")] = {
-            "seconds_one_cycle": el, "relres": [i["relres"] for i in info], "iters": [i["iters"] for i in info]}
-    del B, X
-    # GMRES(40) iteration cost at 512 x 512 (2D, FP64), capped solve
-    p1 = synth.config1()
-    c1 = Context()
-    c1.base_set(p1, torch.from_numpy(synth.base_flow(p1).ravel()).to(dev))
-    b = torch.from_numpy(synth.random_vector(p1, 1).ravel()).to(dev)
-    x = torch.zeros_like(b)
-    (rc, info), el = wall(lambda: c1.gmres_solve([0.2], b, x, restart=40, tol=1e-10, max_matvec=2000))
-    res["gmres40_512x512"] = {"iters": info[0]["iters"], "relres": info[0]["relres"],
-                              "ms_per_iter": el / max(1, info[0]["iters"]) * 1e3}
-    # 8 shifts in lockstep at 512 x 512: one launch per kernel for all shifts
-    B8 = torch.from_numpy(synth.random_vector(p1, 5, nrhs=8).ravel()).to(dev)
-    X8 = torch.zeros_like(B8)
-    (rc, info), el = wall(lambda: c1.gmres_solve(shifts, B8, X8, restart=40, tol=1e-10, max_matvec=401))
-    res["gmres40_512x512_8shifts"] = {"ms_per_iter_all_shifts": el / max(1, info[0]["iters"]) * 1e3,
-                                      "iters": info[0]["iters"]}
+    res.update(gmres_runs(torch, dev, ctx3, prob3))
     # time to eigenpairs, FP64 vs mixed, small case (KH pair)
     pe = synth.mixing_layer_2d(32, 32, 0.5, 1000.0)
     ce = Context()

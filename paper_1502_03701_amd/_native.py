@@ -162,6 +162,7 @@ class Context:
             raise SAError(rc, "sa_create failed")
         self.h = h
         self.prob = None
+        self._pc = False
 
     def close(self):
         if getattr(self, "h", None):
@@ -184,7 +185,12 @@ class Context:
         _check_dev(q0, torch.float64, prob.ndof)
         self.prob = prob
         self._p = make_problem(prob)
+        self._pc = False
         return self._err(self.lib.sa_base_set(self.h, C.byref(self._p), _ptr(q0)))
+
+    def has_precond(self):
+        """Whether block-Jacobi factors are set up for the current base state."""
+        return self._pc
 
     def op_apply(self, x, y, shift=0.0, nrhs=1):
         import torch
@@ -207,7 +213,10 @@ class Context:
                       factor_prec=SA_F32):
         o = PrecondOpts(bx, by, bz, diag_add, noise_std, seed, factor_prec)
         arr = (C.c_double * len(shifts))(*shifts)
-        return self._err(self.lib.sa_precond_setup(self.h, C.byref(o), len(shifts), arr))
+        self._pc = False
+        rc = self._err(self.lib.sa_precond_setup(self.h, C.byref(o), len(shifts), arr))
+        self._pc = True
+        return rc
 
     def precond_apply(self, ishift, r, z, nrhs=1):
         import torch
