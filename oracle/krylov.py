@@ -122,3 +122,105 @@ def gmres(apply_A, b, x0=None, restart=40, tol=1e-12, max_matvec=10 ** 6,
         # the true residual is recomputed at the top of the loop (also after a
         # breakdown, where the Krylov space held the exact solution)
         x0 = x
+
+
+def lgmres(apply_A, b, x0=None, inner_m=30, outer_k=3, tol=1e-12, max_matvec=10 ** 6,
+           precond=None, breakdown_tol=1e-14, dtype=np.float64):
+    """LGMRES(m, k) (Section "Iterative solvers": GMRES whose restart cycles
+    are augmented with error approximations, after Baker, Jessup & Manteuffel).
+
+    Each cycle builds, from the current residual r, the space spanned by m
+    Krylov directions M^{-1} v_1 .. M^{-1} v_m followed by the stored
+    corrections of the previous cycles, newest first (at most k of them,
+    fewer in the first cycles).  The Arnoldi process runs over this sequence
+    of directions d_j in the flexible form: w = A d_j is orthogonalised by CGS2
+    against v_1 .. v_j, giving column j of the Hessenberg matrix and v_{j+1};
+    the iterate becomes x + D y with y the least-squares solution, and the
+    correction D y is stored as the newest augmentation vector.  Its image
+    A D y is not recomputed: it equals r_old - r_new, the difference of the
+    true residuals at the start of consecutive cycles, so an augmentation
+    step costs no operator product.  With k = 0 the method is GMRES(m).
+    Returns (x, info) as gmres does."""
+    b = np.asarray(b, dtype=dtype).ravel()
+    n = b.size
+    bnorm = float(np.linalg.norm(b))
+    x = np.zeros(n, dtype) if x0 is None else np.array(x0, dtype=dtype).ravel()
+    info = dict(iters=0, matvecs=0, cycles=0, relres=0.0, converged=False, breakdown=False)
+    if bnorm == 0.0:
+        info.update(converged=True)
+        return np.zeros(n, dtype), info
+    M = (lambda v: v) if precond is None else precond
+    aug = []                      # stored corrections, newest first
+    aug_A = []                    # their images under A
+    first = x0 is None
+    r_prev = None
+    while True:
+        if first:
+            r = b.copy()
+            first = False
+        else:
+            r = b - apply_A(x)
+            info["matvecs"] += 1
+        if r_prev is not None and outer_k > 0:
+            aug_A = [r_prev - r] + aug_A[:outer_k - 1]
+        beta = float(np.linalg.norm(r))
+        info["relres"] = beta / bnorm
+        if beta <= tol * bnorm:
+            info["converged"] = True
+            return x, info
+        if info["matvecs"] >= max_matvec:
+            return x, info
+        mt = inner_m + len(aug)
+        V = np.zeros((n, mt + 1), dtype)
+        D = np.zeros((n, mt), dtype)
+        H = np.zeros((mt + 1, mt))
+        cs = np.zeros(mt)
+        sn = np.zeros(mt)
+        g = np.zeros(mt + 1)
+        g[0] = beta
+        V[:, 0] = r / beta
+        jdone = 0
+        for j in range(mt):
+            if j < inner_m:
+                D[:, j] = M(V[:, j])
+                w = apply_A(D[:, j])
+                info["matvecs"] += 1
+            else:
+                D[:, j] = aug[j - inner_m]
+                w = aug_A[j - inner_m].copy()
+            info["iters"] += 1
+            wnorm0 = float(np.linalg.norm(w))
+            h = V[:, :j + 1].T @ w
+            w = w - V[:, :j + 1] @ h
+            h2 = V[:, :j + 1].T @ w
+            w = w - V[:, :j + 1] @ h2
+            h = h + h2
+            hnext = float(np.linalg.norm(w))
+            H[:j + 1, j] = h
+            H[j + 1, j] = hnext
+            for i in range(j):
+                t = cs[i] * H[i, j] + sn[i] * H[i + 1, j]
+                H[i + 1, j] = -sn[i] * H[i, j] + cs[i] * H[i + 1, j]
+                H[i, j] = t
+            cs[j], sn[j] = givens(H[j, j], H[j + 1, j])
+            H[j, j] = cs[j] * H[j, j] + sn[j] * H[j + 1, j]
+            H[j + 1, j] = 0.0
+            g[j + 1] = -sn[j] * g[j]
+            g[j] = cs[j] * g[j]
+            jdone = j + 1
+            if hnext <= breakdown_tol * wnorm0:
+                info["breakdown"] = True
+                break
+            V[:, j + 1] = w / hnext
+            if abs(g[j + 1]) <= tol * bnorm or info["matvecs"] >= max_matvec:
+                break
+        R = H[:jdone, :jdone]
+        y = np.zeros(jdone)
+        for i in range(jdone - 1, -1, -1):
+            y[i] = (g[i] - R[i, i + 1:jdone] @ y[i + 1:]) / R[i, i]
+        dx = D[:, :jdone] @ y.astype(dtype)
+        x = x + dx
+        info["cycles"] += 1
+        if outer_k > 0:
+            aug = [dx] + aug[:outer_k - 1]
+            r_prev = r

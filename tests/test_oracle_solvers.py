@@ -269,3 +269,67 @@ def test_block_noise_is_standard_normal():
     assert np.array_equal(z[20:], z2)                   # counter-based: any subset
     z3 = philox.block_noise(seed=4, nb=80, blocks=np.arange(20, 40))
     assert not np.array_equal(z2, z3)
+
+
+# ---------------------------------------------------------------------------
+# LGMRES (Section "Iterative solvers": restart cycles augmented with error
+# approximations)
+# ---------------------------------------------------------------------------
+def _convection_diffusion(N=40, eps=0.02):
+    import scipy.sparse as sp
+    h = 1.0 / (N + 1)
+    I = sp.eye(N)
+    e = np.ones(N)
+    D2 = sp.diags([e[:-1], -2 * e, e[:-1]], [-1, 0, 1]) / h ** 2
+    D1 = sp.diags([-e[:-1], e[:-1]], [-1, 1]) / (2 * h)
+    return (-eps * (sp.kron(I, D2) + sp.kron(D2, I)) + sp.kron(I, D1) + 0.5 * sp.kron(D1, I)).tocsr()
+
+
+def test_lgmres_without_augmentation_is_gmres(small):
+    prob, q0, J = small
+    idx = op.interior_index(prob)
+    A = J - 0.2 * np.eye(J.shape[0])
+    b = synth.random_vector(prob, 51).ravel()[idx]
+    xg, ig = kr.gmres(lambda v: A @ v, b, restart=9, tol=1e-11, max_matvec=50000)
+    xl, il = kr.lgmres(lambda v: A @ v, b, inner_m=9, outer_k=0, tol=1e-11, max_matvec=50000)
+    assert np.array_equal(xg, xl)
+    assert (ig["iters"], ig["matvecs"], ig["cycles"]) == (il["iters"], il["matvecs"], il["cycles"])
+
+
+def test_lgmres_solution_and_library_routine():
+    """LGMRES(17, 3) reaches the direct solution of a nonsymmetric
+    convection-diffusion system, as scipy's lgmres (the same method, which
+    also reuses the corrections' images) does, with about the same number of
+    operator products."""
+    import scipy.sparse.linalg as ssl
+    A = _convection_diffusion()
+    b = np.random.default_rng(5).standard_normal(A.shape[0])
+    xd = ssl.spsolve(A.tocsc(), b)
+    x, info = kr.lgmres(lambda v: A @ v, b, inner_m=17, outer_k=3, tol=1e-10, max_matvec=20000)
+    assert info["converged"]
+    assert np.linalg.norm(b - A @ x) <= 1e-10 * np.linalg.norm(b) * 1.0001
+    assert np.linalg.norm(x - xd) / np.linalg.norm(xd) < 1e-7
+    count = [0]
+
+    def mv(v):
+        count[0] += 1
+        return A @ v
+    xs, flag = ssl.lgmres(ssl.LinearOperator(A.shape, matvec=mv), b, rtol=1e-10, inner_m=17, outer_k=3,
+                          maxiter=2000)
+    assert flag == 0
+    assert np.linalg.norm(xs - x) / np.linalg.norm(xd) < 1e-7
+    assert abs(info["matvecs"] - count[0]) <= 0.05 * count[0]
+
+
+def test_lgmres_needs_fewer_products_on_a_cayley_system():
+    prob = synth.mixing_layer_2d(32, 32, 0.5, 1000.0)
+    S = op.sparse_jacobian(prob, synth.base_flow(prob)).tocsr()
+    idx = op.interior_index(prob)
+    import scipy.sparse as sp
+    A = (S[idx][:, idx] - 0.2 * sp.eye(len(idx))).tocsr()
+    b = synth.random_vector(prob, 1).ravel()[idx]
+    _, ig = kr.gmres(lambda v: A @ v, b, restart=40, tol=1e-10, max_matvec=60000)
+    xl, il = kr.lgmres(lambda v: A @ v, b, inner_m=37, outer_k=3, tol=1e-10, max_matvec=60000)
+    assert ig["converged"] and il["converged"]
+    assert np.linalg.norm(b - A @ xl) <= 1e-10 * np.linalg.norm(b) * 1.0001
+    assert il["matvecs"] < 0.8 * ig["matvecs"]
