@@ -83,6 +83,14 @@ typedef struct {
                           is captured once into a hipGraph and replayed; the
                           graph is cached in the context.  0: plain launches.
                           Results are identical either way.                 */
+  int augment;         /* k >= 0: LGMRES(restart, k) (Section "Iterative
+                          solvers": restart cycles augmented with error
+                          approximations).  Each cycle runs `restart` Krylov
+                          steps and then one step per stored correction of
+                          the previous k cycles (newest first); a correction's
+                          image under A is the difference of consecutive
+                          residuals, so those steps cost no operator product.
+                          0: plain GMRES(restart).  restart + k <= 128.     */
 } sa_gmres_opts;
 
 typedef struct {
@@ -198,8 +206,8 @@ int sa_precond_apply(sa_ctx *ctx, sa_prec prec, int ishift, int nrhs, const void
                      void *z_dev);
 
 /* Solve (J - sigma_s I) x_s = b_s for nshift systems (eq. cayley_arnoldi's
- * linear system; Section "Iterative solvers": restarted GMRES, here with
- * classical Gram-Schmidt applied twice).  b_dev / x_dev hold nshift vectors
+ * linear system; Section "Iterative solvers": restarted GMRES or LGMRES, here
+ * with classical Gram-Schmidt applied twice).  b_dev / x_dev hold nshift vectors
  * one after another; x is the initial guess on entry (zero it for x0 = 0)
  * and the solution on exit.  With use_precond, system s uses the factors of
  * shift s (nshift must equal the setup's).  info_host[nshift] is filled.

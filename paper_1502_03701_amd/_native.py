@@ -42,7 +42,7 @@ class Problem(C.Structure):
 class GmresOpts(C.Structure):
     _fields_ = [("restart", C.c_int), ("tol", C.c_double), ("max_matvec", C.c_long),
                 ("use_precond", C.c_int), ("prec", C.c_int), ("inner_tol", C.c_double),
-                ("max_outer", C.c_int), ("use_graph", C.c_int)]
+                ("max_outer", C.c_int), ("use_graph", C.c_int), ("augment", C.c_int)]
 
 
 class GmresInfo(C.Structure):
@@ -226,14 +226,15 @@ class Context:
         return self._err(self.lib.sa_precond_apply(self.h, prec, ishift, nrhs, _ptr(r), _ptr(z)))
 
     def gmres_solve(self, sigmas, b, x, restart=40, tol=1e-10, max_matvec=10 ** 6,
-                    use_precond=False, prec=SA_F64, inner_tol=1e-4, max_outer=10, use_graph=True):
+                    use_precond=False, prec=SA_F64, inner_tol=1e-4, max_outer=10, use_graph=True, augment=0):
+        """augment = k > 0: LGMRES(restart, k)."""
         import torch
         ns = len(sigmas)
         dt = torch.float32 if prec == SA_F32 else torch.float64
         _check_dev(b, dt, ns * self.ndof)
         _check_dev(x, dt, ns * self.ndof)
         o = GmresOpts(restart, tol, max_matvec, 1 if use_precond else 0, prec, inner_tol, max_outer,
-                      1 if use_graph else 0)
+                      1 if use_graph else 0, augment)
         infos = (GmresInfo * ns)()
         arr = (C.c_double * ns)(*sigmas)
         rc = self._err(self.lib.sa_gmres_solve(self.h, C.byref(o), ns, arr, _ptr(b), _ptr(x), infos))
@@ -244,7 +245,7 @@ class Context:
 
 def arnoldi_eigs(ctxs, v0s, nev=6, ncv=30, sigma=0.2, mu=-0.2, tol=1e-10, max_restarts=500,
                  restart=40, lin_tol=1e-12, max_matvec=10 ** 7, use_precond=False, prec=SA_F64,
-                 inner_tol=1e-4, max_outer=10, evecs=None, use_graph=True):
+                 inner_tol=1e-4, max_outer=10, evecs=None, use_graph=True, augment=0):
     """Leading eigenpairs for several problems (one context each).  evecs: optional
     list of (re, im) device float64 tensors of nev*n entries per problem.
     Contexts on one shared stream run in turn; contexts on pairwise distinct
@@ -254,7 +255,7 @@ def arnoldi_eigs(ctxs, v0s, nev=6, ncv=30, sigma=0.2, mu=-0.2, tol=1e-10, max_re
     npb = len(ctxs)
     o = EigOpts(nev, ncv, sigma, mu, tol, max_restarts,
                 GmresOpts(restart, lin_tol, max_matvec, 1 if use_precond else 0, prec, inner_tol,
-                          max_outer, 1 if use_graph else 0))
+                          max_outer, 1 if use_graph else 0, augment))
     hs = (C.c_void_p * npb)(*[c.h for c in ctxs])
     for c, v in zip(ctxs, v0s):
         _check_dev(v, torch.float64, c.ndof)

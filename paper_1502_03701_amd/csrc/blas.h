@@ -54,6 +54,10 @@ struct Blas {
   void scale(long long n, const R* x, R* out, const double* a, const int* active, hipStream_t s,
              const Batch& b = Batch()) const;
   void fill(long long n, R* x, R v, hipStream_t s) const;
+  // out = a x + c y for nsys systems (strides sx, sy, so; y may equal x),
+  // skipped for systems whose flag active[sys * sA] is 0
+  void lincomb(long long n, int nsys, const R* x, long long sx, double a, const R* y, long long sy, double c, R* out,
+               long long so, const int* active, long long sA, hipStream_t s) const;
 };
 
 // out = float(x * (*scale)) (scale may be null)

@@ -319,6 +319,18 @@ __global__ void cast_scale_kernel(long long n, const Ti* __restrict__ x, To* __r
 }
 
 template <typename R>
+__global__ void lincomb_kernel(long long n, const R* x, long long sx, double a, const R* y, long long sy, double c,
+                               R* out, long long so, const int* __restrict__ active, long long sA) {
+  if (inactive(active, sA)) return;
+  x += blockIdx.z * sx;
+  y += blockIdx.z * sy;
+  out += blockIdx.z * so;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    out[i] = (R)(a * (double)x[i] + c * (double)y[i]);
+}
+
+template <typename R>
 __global__ void fill_kernel(long long n, R* __restrict__ x, R v) {
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) x[i] = v;
@@ -438,6 +450,12 @@ template <typename R>
 void Blas<R>::scale(long long n, const R* x, R* out, const double* a, const int* active, hipStream_t s,
                     const Batch& b) const {
   scale_kernel<R><<<dim3(grid_for(n), 1, b.nsys), RED_THREADS, 0, s>>>(n, x, out, a, active, b.vec, b.res, b.act);
+}
+
+template <typename R>
+void Blas<R>::lincomb(long long n, int nsys, const R* x, long long sx, double a, const R* y, long long sy, double c,
+                      R* out, long long so, const int* active, long long sA, hipStream_t s) const {
+  lincomb_kernel<R><<<dim3(grid_for(n), 1, nsys), RED_THREADS, 0, s>>>(n, x, sx, a, y, sy, c, out, so, active, sA);
 }
 
 template <typename R>

@@ -11,7 +11,9 @@ struct GTail {
   double bnorm2, bnorm, rnorm2, beta, inv, tol, relres;
   int active, converged, breakdown, nonfinite, have_update, exhausted;
   int jdone, jlimit, restart;
+  int naug;                      // augmentation steps after the restart Krylov steps this cycle
   long long iters, matvecs, max_matvec;
+  long long krylov;              // Krylov steps (operator and preconditioner applications)
 };
 
 struct GState {
@@ -72,7 +74,10 @@ __device__ inline void gstate_step_block(GState* st, int j) {
   st->t.jdone = j + 1;
   st->t.have_update = 1;
   st->t.iters += 1;
-  st->t.matvecs += 1;
+  if (j < st->t.restart) {   // augmentation steps reuse stored products
+    st->t.matvecs += 1;
+    st->t.krylov += 1;
+  }
   const double est = fabs(s * gj);
   st->t.relres = est / st->t.bnorm;
   if (!isfinite(hn) || !isfinite(est)) {
@@ -92,8 +97,10 @@ __device__ inline void gstate_step_block(GState* st, int j) {
 // All launchers act on nsys consecutive states (one block each).
 void gstate_init(GState* st, int nsys, double tol, int restart, long long max_matvec, hipStream_t s);
 void gstate_set_bnorm(GState* st, int nsys, hipStream_t s);
-// beta = ||r||, convergence / budget tests, jlimit = min(restart, budget left)
-void gstate_cycle_start(GState* st, int nsys, hipStream_t s);
+// beta = ||r||, convergence / budget tests; the cycle runs `restart` Krylov
+// steps (fewer if the operator budget is short) and then naug augmentation
+// steps
+void gstate_cycle_start(GState* st, int nsys, hipStream_t s, int naug = 0);
 void gstate_step(GState* st, int nsys, int j, hipStream_t s);
 void gstate_finish(GState* st, int nsys, hipStream_t s);
 

@@ -16,6 +16,7 @@ __global__ void init_kernel(GState* base, double tol, int restart, long long max
   st->t.tol = tol;
   st->t.restart = restart;
   st->t.jlimit = restart;
+  st->t.naug = 0;
   st->t.max_matvec = max_matvec;
   st->t.active = 0;
   st->t.converged = 0;
@@ -24,6 +25,7 @@ __global__ void init_kernel(GState* base, double tol, int restart, long long max
   st->t.exhausted = 0;
   st->t.iters = 0;
   st->t.matvecs = 0;
+  st->t.krylov = 0;
   st->t.have_update = 0;
   st->t.jdone = 0;
 }
@@ -34,7 +36,7 @@ __global__ void set_bnorm_kernel(GState* base) {
   st->t.bnorm = sqrt(st->t.bnorm2);
 }
 
-__global__ void cycle_start_kernel(GState* base) {
+__global__ void cycle_start_kernel(GState* base, int naug) {
   if (threadIdx.x != 0) return;
   GState* st = base + blockIdx.x;
   st->t.jdone = 0;
@@ -61,7 +63,8 @@ __global__ void cycle_start_kernel(GState* base) {
     st->t.exhausted = 1;
     return;
   }
-  st->t.jlimit = left < st->t.restart ? (int)left : st->t.restart;
+  st->t.naug = naug;
+  st->t.jlimit = left < st->t.restart ? (int)left : st->t.restart + naug;
   st->g[0] = beta;
   st->t.inv = 1.0 / beta;
   st->t.active = 1;
@@ -128,7 +131,9 @@ void gstate_init(GState* st, int nsys, double tol, int restart, long long max_ma
   init_kernel<<<nsys, 64, 0, s>>>(st, tol, restart, max_matvec);
 }
 void gstate_set_bnorm(GState* st, int nsys, hipStream_t s) { set_bnorm_kernel<<<nsys, 64, 0, s>>>(st); }
-void gstate_cycle_start(GState* st, int nsys, hipStream_t s) { cycle_start_kernel<<<nsys, 64, 0, s>>>(st); }
+void gstate_cycle_start(GState* st, int nsys, hipStream_t s, int naug) {
+  cycle_start_kernel<<<nsys, 64, 0, s>>>(st, naug);
+}
 void gstate_step(GState* st, int nsys, int j, hipStream_t s) { step_kernel<<<nsys, 64, 0, s>>>(st, j); }
 void gstate_finish(GState* st, int nsys, hipStream_t s) { finish_kernel<<<nsys, 64, 0, s>>>(st); }
 

@@ -188,6 +188,11 @@ extern "C" int sa_arnoldi_eigs(sa_ctx* const* ctxs, int nprob, const sa_eig_opts
     return c0->fail(SA_EINVAL, "sa_arnoldi_eigs: need 1 <= nev <= 32 and nev+2 <= ncv <= %d", MMAX);
   if (!(o->tol > 0) || o->max_restarts < 0) return c0->fail(SA_EINVAL, "sa_arnoldi_eigs: bad tol/max_restarts");
   if (std::fabs(o->sigma - o->mu) == 0.0) return c0->fail(SA_EINVAL, "sa_arnoldi_eigs: sigma == mu");
+  const sa_gmres_opts& lin = o->lin;
+  if (lin.restart < 1 || lin.augment < 0 || lin.restart + lin.augment > GMAX || !(lin.tol > 0) ||
+      lin.max_matvec < 1 || (lin.prec == SA_MIXED && (!(lin.inner_tol > 0) || lin.max_outer < 1)))
+    return c0->fail(SA_EINVAL, "sa_arnoldi_eigs: bad inner solver options (restart 1..%d, restart + augment <= %d, "
+                               "tol > 0, max_matvec >= 1; MIXED: inner_tol > 0, max_outer >= 1)", GMAX, GMAX);
   bool same = true, distinct = true;
   for (int p = 0; p < nprob; ++p) {
     if (!ctxs[p] || !v0_dev[p]) return c0->fail(SA_EINVAL, "sa_arnoldi_eigs: null context or start vector");

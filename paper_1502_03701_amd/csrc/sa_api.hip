@@ -240,6 +240,8 @@ int sa_gmres_solve(sa_ctx* c, const sa_gmres_opts* o, int nshift, const double* 
   if (!o || !sigma_host || !b_dev || !x_dev || !info || nshift < 1)
     return c->fail(SA_EINVAL, "sa_gmres_solve: null argument or nshift < 1");
   if (o->restart < 1 || o->restart > GMAX) return c->fail(SA_EINVAL, "sa_gmres_solve: restart must be 1..%d", GMAX);
+  if (o->augment < 0 || o->restart + o->augment > GMAX)
+    return c->fail(SA_EINVAL, "sa_gmres_solve: need augment >= 0 and restart + augment <= %d", GMAX);
   if (!(o->tol > 0) || o->max_matvec < 1) return c->fail(SA_EINVAL, "sa_gmres_solve: bad tol or max_matvec");
   if (o->use_precond) {
     if (!c->has_precond) return c->fail(SA_ESTATE, "sa_gmres_solve: preconditioner not set up");

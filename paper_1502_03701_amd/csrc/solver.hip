@@ -76,11 +76,19 @@ int solve_gmres(Ctx* c, const sa_gmres_opts& o, int nsys, const double* sigma, c
   hipStream_t s = c->stream;
   const long long n = c->n;
   const int m = o.restart;
+  const int k = o.augment;            // LGMRES: error approximations kept (0: GMRES)
   const bool pc = pc_shift0 >= 0;
   const bool graph = o.use_graph != 0;
-  const long long sv = n * (m + 1);   // basis stride between systems
+  const long long sv = n * (m + k + 1);   // basis stride between systems
   R* V = (R*)c->buffer(tag + "V", sizeof(R) * sv * nsys);
   R* Z = pc ? (R*)c->buffer(tag + "Z", sizeof(R) * sv * nsys) : V;
+  // LGMRES state per system: k corrections (newest first), their images
+  // under A, the residual at the start of the cycle, x at its start
+  const long long sa = n * (k > 0 ? k : 1);
+  R* AUG = k ? (R*)c->buffer(tag + "aug", sizeof(R) * sa * nsys, false) : nullptr;
+  R* AUGA = k ? (R*)c->buffer(tag + "augA", sizeof(R) * sa * nsys, false) : nullptr;
+  R* RPREV = k ? (R*)c->buffer(tag + "rprev", sizeof(R) * n * nsys, false) : nullptr;
+  R* XOLD = k ? (R*)c->buffer(tag + "xold", sizeof(R) * n * nsys, false) : nullptr;
   R* T = (R*)c->buffer(tag + "T", sizeof(R) * n * nsys, false);
   GState* st = (GState*)c->buffer(tag + "state", sizeof(GState) * nsys);
   double* sig = (double*)c->buffer(tag + "sigma", sizeof(double) * nsys, false);
@@ -91,7 +99,8 @@ int solve_gmres(Ctx* c, const sa_gmres_opts& o, int nsys, const double* sigma, c
   // graph serves every caller buffer
   R* X = graph ? (R*)c->buffer(tag + "X", sizeof(R) * n * nsys, false) : x;
   R* B = graph ? (R*)c->buffer(tag + "B", sizeof(R) * n * nsys, false) : const_cast<R*>(b);
-  if (!V || !Z || !T || !st || !sig || !bl.partial || !bl.ticket || !X || !B)
+  if (!V || !Z || !T || !st || !sig || !bl.partial || !bl.ticket || !X || !B ||
+      (k && (!AUG || !AUGA || !RPREV || !XOLD)))
     return c->fail(SA_ENOMEM, "gmres: out of device memory");
   if (graph && !c->cap_stream) {
     hipError_t e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
@@ -114,21 +123,44 @@ int solve_gmres(Ctx* c, const sa_gmres_opts& o, int nsys, const double* sigma, c
   Batch bx = bb;                  // x += Z y: basis stride for Z, n for x
   bx.wvec = n;
 
-  // r = b - (J - sigma I) x -> V_s[:,0]; beta, convergence and budget tests
-  auto start_cycle = [&](hipStream_t q) -> hipError_t {
+  const int* upd = &st->t.have_update;
+  // r = b - (J - sigma I) x -> V_s[:,0]; with LGMRES the image of the last
+  // correction, A dx = r_prev - r; beta, convergence and budget tests
+  auto start_cycle = [&](hipStream_t q, int naug) -> hipError_t {
     hipError_t r =
         launch_jv_batch<R>(c->op, base, bdata, X, T, nsys, n, n, sigma, sig, nullptr, 0, q, c->variant_of<R>());
     if (r != hipSuccess) return r;
     bl.residual(n, B, T, V, &st->t.rnorm2, nullptr, q, bb, n, n);
-    gstate_cycle_start(st, nsys, q);
+    if (k) bl.lincomb(n, nsys, RPREV, n, 1.0, V, sv, -1.0, AUGA, sa, upd, GS_INTS, q);
+    gstate_cycle_start(st, nsys, q, naug);
     return hipGetLastError();
   };
-  // m Arnoldi steps, the least-squares solve and x += Z y
-  auto arnoldi_cycle = [&](hipStream_t q) -> hipError_t {
+  // one Arnoldi step on direction zj (null: the step's w is already in place)
+  auto arnoldi_step = [&](hipStream_t q, int j, const R* zj) -> hipError_t {
+    R* w = V + (long long)(j + 1) * n;
+    if (zj) {
+      hipError_t r = launch_jv_batch<R>(c->op, base, bdata, zj, w, nsys, sv, sv, sigma, sig, act, GS_INTS, q,
+                                        c->variant_of<R>());
+      if (r != hipSuccess) return r;
+    }
+    // CGS pass 1: d1 = V[0..j]^T w and ||w||^2
+    bl.multidot(n, V, n, j + 2, w, st->d1, false, act, q, bb);
+    // pass 2: w -= V d1, d2 = V^T w
+    bl.update(n, V, n, j + 1, st->d1, -1.0, w, w, 1, st->d2, false, act, q, bb);
+    // pass 3: w -= V d2, wn2 = ||w||^2, then the Givens step (fused when
+    // the reduction finishes inside the kernel)
+    if (!bl.update(n, V, n, j + 1, st->d2, -1.0, w, w, 2, &st->wn2, false, act, q, bb, st, j))
+      gstate_step(st, nsys, j, q);
+    bl.scale(n, w, w, &st->t.inv, act, q, bb);
+    return hipGetLastError();
+  };
+  // m Krylov steps, naug augmentation steps, the least-squares solve and
+  // x += Z y (+ AUG y_aug); LGMRES then stores the correction
+  auto arnoldi_cycle = [&](hipStream_t q, int naug) -> hipError_t {
+    if (k) bl.lincomb(n, nsys, V, sv, 1.0, V, sv, 0.0, RPREV, n, act, GS_INTS, q);
     bl.scale(n, V, V, &st->t.inv, act, q, bb);
     for (int j = 0; j < m; ++j) {
       R* vj = V + (long long)j * n;
-      R* w = V + (long long)(j + 1) * n;
       const R* zj = vj;
       if (pc) {
         R* zz = Z + (long long)j * n;
@@ -136,32 +168,48 @@ int solve_gmres(Ctx* c, const sa_gmres_opts& o, int nsys, const double* sigma, c
         if (r != hipSuccess) return r;
         zj = zz;
       }
-      hipError_t r = launch_jv_batch<R>(c->op, base, bdata, zj, w, nsys, sv, sv, sigma, sig, act, GS_INTS, q,
-                                        c->variant_of<R>());
+      hipError_t r = arnoldi_step(q, j, zj);
       if (r != hipSuccess) return r;
-      // CGS pass 1: d1 = V[0..j]^T w and ||w||^2
-      bl.multidot(n, V, n, j + 2, w, st->d1, false, act, q, bb);
-      // pass 2: w -= V d1, d2 = V^T w
-      bl.update(n, V, n, j + 1, st->d1, -1.0, w, w, 1, st->d2, false, act, q, bb);
-      // pass 3: w -= V d2, wn2 = ||w||^2, then the Givens step (fused when
-      // the reduction finishes inside the kernel)
-      if (!bl.update(n, V, n, j + 1, st->d2, -1.0, w, w, 2, &st->wn2, false, act, q, bb, st, j))
-        gstate_step(st, nsys, j, q);
-      bl.scale(n, w, w, &st->t.inv, act, q, bb);
+    }
+    for (int i = 0; i < naug; ++i) {
+      // direction: correction i; its image is stored, so w needs no product
+      bl.lincomb(n, nsys, AUGA + (long long)i * n, sa, 1.0, AUGA + (long long)i * n, sa, 0.0,
+                 V + (long long)(m + i + 1) * n, sv, act, GS_INTS, q);
+      hipError_t r = arnoldi_step(q, m + i, nullptr);
+      if (r != hipSuccess) return r;
     }
     gstate_finish(st, nsys, q);
+    if (k) bl.lincomb(n, nsys, X, n, 1.0, X, n, 0.0, XOLD, n, upd, GS_INTS, q);
     // x += Z y  (Z = V without preconditioning)
-    bl.update(n, Z, n, m, st->y, 1.0, X, X, 0, nullptr, false, &st->t.have_update, q, bx);
+    bl.update(n, Z, n, m, st->y, 1.0, X, X, 0, nullptr, false, upd, q, bx);
+    if (naug) {
+      Batch ba = bx;
+      ba.vec = sa;
+      bl.update(n, AUG, n, naug, st->y + m, 1.0, X, X, 0, nullptr, false, upd, q, ba);
+    }
+    if (k) {
+      // keep the newest k corrections: shift, then AUG_0 = x - x_old
+      for (int i = naug < k ? naug : k - 1; i >= 1; --i) {
+        bl.lincomb(n, nsys, AUG + (long long)(i - 1) * n, sa, 1.0, AUG + (long long)(i - 1) * n, sa, 0.0,
+                   AUG + (long long)i * n, sa, upd, GS_INTS, q);
+        bl.lincomb(n, nsys, AUGA + (long long)(i - 1) * n, sa, 1.0, AUGA + (long long)(i - 1) * n, sa, 0.0,
+                   AUGA + (long long)i * n, sa, upd, GS_INTS, q);
+      }
+      bl.lincomb(n, nsys, X, n, 1.0, XOLD, n, -1.0, AUG, sa, upd, GS_INTS, q);
+    }
     return hipGetLastError();
   };
 
-  // one graph = one cycle followed by the next cycle's start
-  hipGraphExec_t exec = nullptr;
-  if (graph) {
+  // one graph = one cycle followed by the next cycle's start; with LGMRES
+  // the cycle's shape depends on the corrections already stored (naug)
+  auto get_graph = [&](int naug, hipGraphExec_t& exec) -> int {
+    exec = nullptr;
     std::vector<unsigned char> key;
     put(key, (int)sizeof(R));
     put(key, nsys);
     put(key, m);
+    put(key, k);
+    put(key, naug);
     put(key, pc_shift0);
     put(key, n);
     put(key, c->variant_of<R>());
@@ -169,14 +217,15 @@ int solve_gmres(Ctx* c, const sa_gmres_opts& o, int nsys, const double* sigma, c
                             (const void*)bl.partial, (const void*)bl.ticket, (const void*)X, (const void*)B, (const void*)base,
                             (const void*)bdata, (const void*)c->pc_lu, (const void*)c->pc_perm})
       put(key, ptr);
+    for (const void* ptr : {(const void*)AUG, (const void*)AUGA, (const void*)RPREV, (const void*)XOLD}) put(key, ptr);
     for (int i = 0; i < nsys; ++i) put(key, sigma[i]);
     exec = find_graph(c, key);
     if (!exec) {
       hipGraph_t g = nullptr;
-      e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+      hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
       if (e != hipSuccess) return c->hip_fail(e, "gmres begin capture");
-      hipError_t ec = arnoldi_cycle(c->cap_stream);
-      if (ec == hipSuccess) ec = start_cycle(c->cap_stream);
+      hipError_t ec = arnoldi_cycle(c->cap_stream, naug);
+      if (ec == hipSuccess) ec = start_cycle(c->cap_stream, naug < k ? naug + 1 : k);
       e = hipStreamEndCapture(c->cap_stream, &g);
       if (ec != hipSuccess) {
         if (g) hipGraphDestroy(g);
@@ -193,13 +242,14 @@ int solve_gmres(Ctx* c, const sa_gmres_opts& o, int nsys, const double* sigma, c
       }
       c->graphs.push_back(CycleGraph{key, exec});
     }
-  }
+    return SA_OK;
+  };
 
   for (int i = 0; i < nsys; ++i) info[i] = sa_gmres_info{};
   gstate_init(st, nsys, o.tol, m, o.max_matvec, s);
   bl.nrm2sq(n, B, &st->t.bnorm2, nullptr, s, bn);
   gstate_set_bnorm(st, nsys, s);
-  e = start_cycle(s);
+  e = start_cycle(s, 0);
   if (e != hipSuccess) return c->hip_fail(e, "gmres residual");
   std::vector<GTail> h;
   int cycles = 0;
@@ -212,7 +262,7 @@ int solve_gmres(Ctx* c, const sa_gmres_opts& o, int nsys, const double* sigma, c
       info[i].matvecs = h[i].matvecs;
       info[i].cycles = cycles;
       info[i].relres = h[i].relres;
-      info[i].precond_applies = pc ? h[i].iters : 0;
+      info[i].precond_applies = pc ? h[i].krylov : 0;
       if (h[i].nonfinite) {
         info[i].status = SA_ENONFINITE;
         return c->fail(SA_ENONFINITE, "gmres: non-finite residual (system %d)", i);
@@ -221,12 +271,16 @@ int solve_gmres(Ctx* c, const sa_gmres_opts& o, int nsys, const double* sigma, c
       any_active = any_active || h[i].active;
     }
     if (!any_active) break;
+    const int naug = cycles < k ? cycles : k;   // corrections stored so far
     if (graph) {
+      hipGraphExec_t exec;
+      const int rc = get_graph(naug, exec);
+      if (rc != SA_OK) return rc;
       e = hipGraphLaunch(exec, s);
       if (e != hipSuccess) return c->hip_fail(e, "gmres graph launch");
     } else {
-      e = arnoldi_cycle(s);
-      if (e == hipSuccess) e = start_cycle(s);
+      e = arnoldi_cycle(s, naug);
+      if (e == hipSuccess) e = start_cycle(s, naug < k ? naug + 1 : k);
       if (e != hipSuccess) return c->hip_fail(e, "gmres cycle");
     }
     ++cycles;

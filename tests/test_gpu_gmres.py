@@ -100,3 +100,51 @@ def test_gmres_edge_cases(small):
     with pytest.raises(SAError) as e:
         ctx.gmres_solve([0.2], dev(b), torch.zeros_like(x), restart=5, tol=1e-10, use_precond=True)
     assert e.value.code == n.SA_ESTATE
+
+
+@pytest.mark.parametrize("restart,k", [(7, 3), (10, 2)])
+def test_lgmres_solution_and_oracle_counts(small, restart, k):
+    """LGMRES(restart, k): the solution of the dense solve, and the same number
+    of operator products as the oracle's LGMRES (up to the first cycle's
+    residual product, which the GPU always forms)."""
+    prob, q0, J, idx, ctx = small
+    b = synth.random_vector(prob, 61)
+    x = torch.zeros(prob.ndof, dtype=torch.float64, device="cuda:0")
+    rc, info = ctx.gmres_solve([0.2], dev(b), x, restart=restart, tol=1e-10, max_matvec=200000, augment=k)
+    assert rc == 0 and info[0]["relres"] <= 1e-10
+    xr, cond = _solve_ref(J, idx, prob, b, 0.2)
+    assert rel(host(x), xr) < 1e-10 * cond
+    A = J - 0.2 * np.eye(J.shape[0])
+    _, oi = kr.lgmres(lambda v: A @ v, b.ravel()[idx], inner_m=restart, outer_k=k, tol=1e-10, max_matvec=200000)
+    assert abs(info[0]["matvecs"] - (oi["matvecs"] + 1)) <= max(2, oi["matvecs"] // 50)
+    assert abs(info[0]["iters"] - oi["iters"]) <= max(2, oi["iters"] // 50)
+
+
+def test_lgmres_multishift_graph_and_precisions(small):
+    """Several shifts in lockstep equal the single solves bit for bit, graph
+    replays equal plain launches, and the FP32 (with block-Jacobi) and mixed
+    forms converge."""
+    prob, q0, J, idx, ctx = small
+    from paper_1502_03701_amd import SA_F32, SA_MIXED
+    sig = [0.1, 0.25]
+    B = synth.random_vector(prob, 62, nrhs=2)
+    X = torch.zeros(2 * prob.ndof, dtype=torch.float64, device="cuda:0")
+    rc, info = ctx.gmres_solve(sig, dev(B), X, restart=8, tol=1e-10, augment=3)
+    assert rc == 0
+    Xe = torch.zeros_like(X)
+    ctx.gmres_solve(sig, dev(B), Xe, restart=8, tol=1e-10, augment=3, use_graph=False)
+    assert np.array_equal(host(X), host(Xe))
+    for s in range(2):
+        x1 = torch.zeros(prob.ndof, dtype=torch.float64, device="cuda:0")
+        ctx.gmres_solve([sig[s]], dev(B[s]), x1, restart=8, tol=1e-10, augment=3)
+        assert np.array_equal(host(x1), host(X).reshape(2, -1)[s])
+    x32 = torch.zeros(prob.ndof, dtype=torch.float32, device="cuda:0")
+    rc, info = ctx.gmres_solve([0.2], dev(B[0], torch.float32), x32, restart=8, tol=1e-4, prec=SA_F32, augment=2)
+    assert rc == 0 and info[0]["relres"] <= 1e-4
+    xm = torch.zeros(prob.ndof, dtype=torch.float64, device="cuda:0")
+    rc, info = ctx.gmres_solve([0.2], dev(B[0]), xm, restart=8, tol=1e-10, prec=SA_MIXED, inner_tol=1e-4,
+                               max_outer=30, augment=2)
+    assert rc == 0 and info[0]["relres"] <= 1e-10
+    from paper_1502_03701_amd import SAError
+    with pytest.raises(SAError):
+        ctx.gmres_solve([0.2], dev(B[0]), xm, restart=100, augment=40)
