@@ -303,12 +303,15 @@ def extras(torch, dev, ctx3, prob3):
         res["eigs_kh_32x32_" + name] = {"seconds": el, "nconv": r[0]["nconv"],
                                         "lam": [[l.real, l.imag] for l in r[0]["lam"]],
                                         "n_matvec": r[0]["n_matvec"]}
-    res.update(sweep(torch, dev, log=lambda m: print(m, file=sys.stderr, flush=True)))
-    res.update(eigs_3d(torch, dev, log=lambda m: print(m, file=sys.stderr, flush=True)))
+    log = lambda m: print(m, file=sys.stderr, flush=True)   # noqa: E731
+    res.update(sweep(torch, dev, log=log))
+    res.update(sweep(torch, dev, augment=3, modes=("concurrent",), log=log))
+    res.update(eigs_3d(torch, dev, log=log))
+    res.update(eigs_3d(torch, dev, augment=3, log=log))
     return res
 
 
-def eigs_3d(torch, dev, side=32, nev=2, ncv=16, max_restarts=60, log=None):
+def eigs_3d(torch, dev, side=32, nev=2, ncv=16, max_restarts=60, augment=0, log=None):
     """Time to the leading eigenpairs of a 3D mixing layer (side^3, M = 0.5,
     Re = 1000, 1e-3 spanwise noise), FP64 against the mixed form, and the
     mixed eigenvalues' relative deviation from the FP64 ones."""
@@ -323,24 +326,26 @@ def eigs_3d(torch, dev, side=32, nev=2, ncv=16, max_restarts=60, log=None):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         rc, r = arnoldi_eigs([ctx], [v0], nev=nev, ncv=ncv, sigma=0.2, mu=-0.2, tol=1e-10, max_restarts=max_restarts,
-                             restart=40, lin_tol=1e-12, prec=prec, inner_tol=1e-4, max_outer=30)
+                             restart=40 - augment, augment=augment, lin_tol=1e-12, prec=prec, inner_tol=1e-4,
+                             max_outer=30)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         lam[name] = r[0]["lam"]
-        out["eigs_3d_%d_nev%d_%s" % (side, nev, name)] = {"seconds": el, "rc": rc, "nconv": r[0]["nconv"],
+        out["eigs_3d_%d_nev%d_%s%s" % (side, nev, "lgmres_" if augment else "", name)] = {"seconds": el, "rc": rc, "nconv": r[0]["nconv"],
                                                 "n_matvec": r[0]["n_matvec"], "n_cayley": r[0]["n_cayley"],
                                                 "lam": [[l.real, l.imag] for l in r[0]["lam"]]}
         if log:
-            log("eigs 3d %d %s: %.1f s, %d matvecs" % (side, name, el, r[0]["n_matvec"]))
+            log("eigs 3d %d %s%s: %.1f s, %d matvecs" % (side, "lgmres " if augment else "", name, el,
+                                                       r[0]["n_matvec"]))
     dev_rel = [abs(a - b) / abs(a) for a, b in zip(sorted(lam["fp64"], key=abs), sorted(lam["mixed"], key=abs))]
-    key = "eigs_3d_%d_nev%d_" % (side, nev)
+    key = "eigs_3d_%d_nev%d_%s" % (side, nev, "lgmres_" if augment else "")
     out[key + "mixed_vs_fp64"] = {"speedup": out[key + "fp64"]["seconds"] / out[key + "mixed"]["seconds"],
                                   "max_rel_dev": max(dev_rel)}
     ctx.close()
     return out
 
 
-def sweep(torch, dev, nev=2, log=None):
+def sweep(torch, dev, nev=2, augment=0, modes=("sequential", "concurrent"), log=None):
     """Reduced sweep of uneven base flows (the sweep's Mach/Re recipe on sides
     16-32), each its own mixed-precision Cayley-IRAM: the problems one after
     another on one stream, then all at once on one stream each (run
@@ -349,10 +354,10 @@ def sweep(torch, dev, nev=2, log=None):
     import synth
     from paper_1502_03701_amd import SA_MIXED, Context, arnoldi_eigs
     items = synth.config4_reduced(sides=(16, 24, 32))
-    kw = dict(nev=nev, ncv=16, sigma=0.2, mu=-0.2, tol=1e-8, max_restarts=100, restart=40, lin_tol=1e-10,
-              prec=SA_MIXED, inner_tol=1e-4, max_outer=20)
+    kw = dict(nev=nev, ncv=16, sigma=0.2, mu=-0.2, tol=1e-8, max_restarts=100, restart=40 - augment,
+              augment=augment, lin_tol=1e-10, prec=SA_MIXED, inner_tol=1e-4, max_outer=20)
     out = {}
-    for mode in ("sequential", "concurrent"):
+    for mode in modes:
         if mode == "sequential":
             streams = [torch.cuda.current_stream()] * len(items)
         else:
@@ -378,12 +383,12 @@ def sweep(torch, dev, nev=2, log=None):
         el = time.perf_counter() - t0
         secs = np.array([x["seconds"] for x in r])
         pairs = int(sum(min(x["nconv"], nev) for x in r))
-        out["sweep_reduced_" + mode] = {
+        out["sweep_reduced_" + ("lgmres_" if augment else "") + mode] = {
             "problems": len(items), "sides": [it.problem.n[0] for it in items], "eigenpairs": pairs,
             "seconds": el, "eigenpairs_per_s": pairs / el, "p50_s": float(np.percentile(secs, 50)),
             "p99_s": float(np.percentile(secs, 99)), "n_matvec": int(sum(x["n_matvec"] for x in r))}
         if log:
-            log("sweep %s: %.2f s" % (mode, el))
+            log("sweep %s%s: %.2f s" % ("lgmres " if augment else "", mode, el))
         for c in ctxs:
             c.close()
     return out
