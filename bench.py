@@ -128,6 +128,9 @@ def main():
                     help="also run a device copy of known size (counter calibration)")
     ap.add_argument("--bjac-only", action="store_true",
                     help="only the block-Jacobi setup and apply of the 3D grid (for profiling)")
+    ap.add_argument("--c0-eigs", action="store_true",
+                    help="only the time to the four separated eigenpairs of the 48x48 case: FP64 / mixed, "
+                         "GMRES / LGMRES inner solves")
     ap.add_argument("--gmres-only", action="store_true",
                     help="only capped GMRES runs: 512x512 FP64 (1 and 8 shifts), one FP32 cycle of "
                          "8 shifts on the 3D grid (for profiling)")
@@ -143,6 +146,9 @@ def main():
     from paper_1502_03701_amd import Context
 
     dev = torch.device("cuda:0")
+    if args.c0_eigs:
+        print(json.dumps(eigs_c0(torch, dev, log=lambda m: print(m, file=sys.stderr, flush=True))))
+        return
     prob = synth.config2()
     q0 = synth.base_flow(prob, seed=2, w_noise=1e-3)
     v = synth.random_vector(prob, 2)
@@ -309,6 +315,35 @@ def extras(torch, dev, ctx3, prob3):
     res.update(eigs_3d(torch, dev, log=log))
     res.update(eigs_3d(torch, dev, augment=3, log=log))
     return res
+
+
+def eigs_c0(torch, dev, log=None):
+    """Time to the four separated leading eigenpairs of the 48 x 48 mixing
+    layer (M = 0.3, Re = 500; the KH pair and its harmonic), FP64 and mixed
+    inner solves, GMRES(40) and LGMRES(37, 3)."""
+    import synth
+    from paper_1502_03701_amd import SA_F64, SA_MIXED, Context, arnoldi_eigs
+    p = synth.config0()
+    ctx = Context()
+    ctx.base_set(p, torch.from_numpy(synth.base_flow(p).ravel()).to(dev))
+    v0 = torch.from_numpy(synth.random_vector(p, 0).ravel()).to(dev)
+    out = {}
+    for solver, aug in (("gmres", 0), ("lgmres", 3)):
+        for name, prec in (("fp64", SA_F64), ("mixed", SA_MIXED)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rc, r = arnoldi_eigs([ctx], [v0], nev=4, ncv=20, sigma=0.2, mu=-0.2, tol=1e-10, max_restarts=50,
+                                 restart=40 - aug, augment=aug, lin_tol=1e-12, prec=prec, inner_tol=1e-4,
+                                 max_outer=30)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            out["eigs_c0_nev4_%s_%s" % (solver, name)] = {
+                "seconds": el, "rc": rc, "nconv": r[0]["nconv"], "n_matvec": r[0]["n_matvec"],
+                "n_cayley": r[0]["n_cayley"], "lam": [[l.real, l.imag] for l in r[0]["lam"]]}
+            if log:
+                log("eigs c0 %s %s: %.1f s, %d matvecs" % (solver, name, el, r[0]["n_matvec"]))
+    ctx.close()
+    return out
 
 
 def eigs_3d(torch, dev, side=32, nev=2, ncv=16, max_restarts=60, augment=0, log=None):
