@@ -183,7 +183,8 @@ __global__ void __launch_bounds__(NT) jv_prefetch_kernel(OpParams op, const R* _
   };
   auto load_bdata = [&](int k) {
 #pragma unroll
-    for (int q = 0; q < NB; ++q) bq[q] = bdata[q * npts + k * plane + col_own];
+    // streamed once: nontemporal, so they do not push the reused x halos out of L2
+    for (int q = 0; q < NB; ++q) bq[q] = __builtin_nontemporal_load(bdata + (q * npts + k * plane + col_own));
   };
   load_plane(kbeg);
 
@@ -327,7 +328,8 @@ __global__ void __launch_bounds__(NT) jv_prefetch_kernel(OpParams op, const R* _
         tangent_point<R, ND>(b, P, op, out);
       }
 #pragma unroll
-      for (int f = 0; f < ND + 2; ++f) y[f * npts + pown] = wallrow ? R(0) : out[f] - shift * P.q[f];
+      for (int f = 0; f < ND + 2; ++f)   // written once, read by another kernel: nontemporal
+        __builtin_nontemporal_store(wallrow ? R(0) : out[f] - shift * P.q[f], y + (f * npts + pown));
     }
   }
 }

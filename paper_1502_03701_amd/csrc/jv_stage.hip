@@ -257,7 +257,7 @@ __global__ void __launch_bounds__(NT) jv_stage_kernel(OpParams op, const R* __re
         const R* bd = bdata + id;
         int q = 0;
         auto get = [&]() -> R {
-          const R v = bd[(long long)q * npts];
+          const R v = __builtin_nontemporal_load(bd + (long long)q * npts);   // streamed once
           ++q;
           return v;
         };
@@ -285,7 +285,8 @@ __global__ void __launch_bounds__(NT) jv_stage_kernel(OpParams op, const R* __re
         tangent_point<R, ND>(b, P, op, out);
       }
 #pragma unroll
-      for (int f = 0; f < ND + 2; ++f) y[(long long)f * npts + id] = wallrow ? R(0) : out[f] - shift * P.q[f];
+      for (int f = 0; f < ND + 2; ++f)   // written once, read by another kernel: nontemporal
+        __builtin_nontemporal_store(wallrow ? R(0) : out[f] - shift * P.q[f], y + ((long long)f * npts + id));
     }
     if (ND == 3) {
 #pragma unroll
