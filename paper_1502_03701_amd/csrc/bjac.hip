@@ -432,19 +432,62 @@ __global__ void __launch_bounds__(64) apply_kernel(BLayout L, const F* __restric
     const long long d = block_dof(L, bb, pg[(long long)i * 64], wall);
     ys[i * 64 + lane] = wall ? F(0) : (F)rr[d];
   }
+  // Both substitutions go in chunks of RB rows: the updates from the rows
+  // already solved are RB independent, contiguous loads per column (memory-
+  // level parallelism for the one-pass stream of factors), then the RB x RB
+  // diagonal block is solved in registers.  Rows past the end of a short last
+  // chunk read clamped (valid) entries and are never stored, so every load is
+  // unconditional and the compiler can issue them together.
+  constexpr int RB = 16;
+  auto entry = [&](int row, int col) -> F {   // factor entry, indices clamped into the block
+    row = row < nb ? row : nb - 1;
+    col = col < nb ? col : nb - 1;
+    return __builtin_nontemporal_load(A + ((long long)col * nb + row) * 64);
+  };
   // forward, in place: y_i = (P r)_i - sum_{j<i} L_ij y_j
-  for (int i = 0; i < nb; ++i) {
-    F acc = ys[i * 64 + lane];
-#pragma unroll 8
-    for (int j = 0; j < i; ++j) acc -= A[((long long)j * nb + i) * 64] * ys[j * 64 + lane];
-    ys[i * 64 + lane] = acc;
+  for (int i0 = 0; i0 < nb; i0 += RB) {
+    const int nr = nb - i0 < RB ? nb - i0 : RB;
+    F acc[RB];
+#pragma unroll
+    for (int q = 0; q < RB; ++q) acc[q] = ys[(i0 + (q < nr ? q : nr - 1)) * 64 + lane];
+#pragma unroll 2
+    for (int j = 0; j < i0; ++j) {
+      const F yj = ys[j * 64 + lane];
+#pragma unroll
+      for (int q = 0; q < RB; ++q) acc[q] -= entry(i0 + q, j) * yj;
+    }
+#pragma unroll
+    for (int q = 1; q < RB; ++q)
+#pragma unroll
+      for (int c = 0; c < q; ++c) acc[q] -= entry(i0 + q, i0 + c) * acc[c];
+#pragma unroll
+    for (int q = 0; q < RB; ++q)
+      if (q < nr) ys[(i0 + q) * 64 + lane] = acc[q];
   }
   // backward: z_i = (y_i - sum_{j>i} U_ij z_j) / U_ii, in place over y
-  for (int i = nb - 1; i >= 0; --i) {
-    F acc = ys[i * 64 + lane];
-#pragma unroll 8
-    for (int j = i + 1; j < nb; ++j) acc -= A[((long long)j * nb + i) * 64] * ys[j * 64 + lane];
-    ys[i * 64 + lane] = acc / A[((long long)i * nb + i) * 64];
+  for (int i1 = nb; i1 > 0; i1 -= RB) {
+    const int i0 = i1 - RB > 0 ? i1 - RB : 0;
+    const int nr = i1 - i0;
+    F acc[RB];
+#pragma unroll
+    for (int q = 0; q < RB; ++q) acc[q] = ys[(i0 + (q < nr ? q : nr - 1)) * 64 + lane];
+#pragma unroll 2
+    for (int j = i1; j < nb; ++j) {
+      const F zj = ys[j * 64 + lane];
+#pragma unroll
+      for (int q = 0; q < RB; ++q) acc[q] -= entry(i0 + q, j) * zj;
+    }
+#pragma unroll
+    for (int q = 0; q < RB; ++q) acc[q] = q < nr ? acc[q] : F(0);   // rows past the chunk: 0
+#pragma unroll
+    for (int q = RB - 1; q >= 0; --q) {
+#pragma unroll
+      for (int c = q + 1; c < RB; ++c) acc[q] -= entry(i0 + q, i0 + c) * acc[c];
+      acc[q] = q < nr ? acc[q] / entry(i0 + q, i0 + q) : F(0);
+    }
+#pragma unroll
+    for (int q = 0; q < RB; ++q)
+      if (q < nr) ys[(i0 + q) * 64 + lane] = acc[q];
   }
   if (!valid) return;
   for (int l = 0; l < nb; ++l) {
