@@ -26,6 +26,34 @@ __device__ __forceinline__ bool inactive(const int* active, long long sA) {
   return active && !active[blockIdx.z * sA];
 }
 
+// E consecutive elements moved by one load / store (E = 16 / sizeof(R) on
+// the 16-byte path, 1 on the scalar path); NT: nontemporal (data streamed
+// once, kept from displacing what is re-read).
+template <typename R, int E, bool NT = false>
+__device__ __forceinline__ void vload(const R* p, R (&v)[E]) {
+  if constexpr (E == 1) {
+    v[0] = NT ? __builtin_nontemporal_load(p) : *p;
+  } else {
+    typedef R vt __attribute__((ext_vector_type(E)));
+    const vt* q = reinterpret_cast<const vt*>(p);
+    const vt x = NT ? __builtin_nontemporal_load(q) : *q;
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = x[e];
+  }
+}
+template <typename R, int E>
+__device__ __forceinline__ void vstore(R* p, const R (&v)[E]) {
+  if constexpr (E == 1) {
+    *p = v[0];
+  } else {
+    typedef R vt __attribute__((ext_vector_type(E)));
+    vt x;
+#pragma unroll
+    for (int e = 0; e < E; ++e) x[e] = v[e];
+    *reinterpret_cast<vt*>(p) = x;
+  }
+}
+
 // Sum acc[c] over the block for c < ncol; writes out[c].
 template <int MAXC>
 __device__ __forceinline__ void block_sum_cols(double (&acc)[MAXC], int ncol, double* __restrict__ out) {
@@ -94,8 +122,9 @@ __device__ __forceinline__ void finish_reduction(const double* __restrict__ part
 }
 
 // partial[b*ldp + c0 + c] = sum over this block's elements of V[c0+c][i] w[i]
-// (blockIdx.y: column chunk, blockIdx.z: system)
-template <typename R, int MAXC>
+// (blockIdx.y: column chunk, blockIdx.z: system); threads take E elements at
+// a time (n, ldv and the strides are multiples of E)
+template <typename R, int MAXC, int E, bool NT>
 __global__ void __launch_bounds__(RED_THREADS) multidot_kernel(long long n, const R* __restrict__ V, long long ldv,
                                                                int ncol, const R* __restrict__ w,
                                                                double* __restrict__ partial, int ldp,
@@ -111,13 +140,22 @@ __global__ void __launch_bounds__(RED_THREADS) multidot_kernel(long long n, cons
   double acc[MAXC];
 #pragma unroll
   for (int c = 0; c < MAXC; ++c) acc[c] = 0.0;
+  const long long nch = n / E;
   const long long stride = (long long)gridDim.x * blockDim.x;
 #pragma unroll 1
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    const double wi = (double)w[i];
+  for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < nch; k += stride) {
+    R wv[E];
+    vload<R, E>(w + k * E, wv);
 #pragma unroll
     for (int c = 0; c < MAXC; ++c)
-      if (c < nc) acc[c] += (double)V[(long long)(c0 + c) * ldv + i] * wi;
+      if (c < nc) {
+        R v[E];
+        vload<R, E, NT>(V + (long long)(c0 + c) * ldv + k * E, v);
+        double t = (double)v[0] * (double)wv[0];
+#pragma unroll
+        for (int q = 1; q < E; ++q) t += (double)v[q] * (double)wv[q];
+        acc[c] += t;
+      }
   }
   block_sum_cols<MAXC>(acc, nc, partial + (long long)blockIdx.x * ldp + c0);
   finish_reduction(partial, gridDim.x, gridDim.x * gridDim.y, ldp, ncol, e);
@@ -125,7 +163,7 @@ __global__ void __launch_bounds__(RED_THREADS) multidot_kernel(long long n, cons
 
 // w_new = w + hsign * sum_c V[c] h[c]; writes w_new to wout (may alias w).
 // norm: partial ||w_new||^2 in column 0.  The coefficients sit in LDS.
-template <typename R, int MAXC>
+template <typename R, int MAXC, int E, bool NT>
 __global__ void __launch_bounds__(RED_THREADS) update_kernel(
     long long n, const R* __restrict__ V, long long ldv, int ncol, const double* __restrict__ h, double hsign,
     const R* w, R* wout, int norm, double* __restrict__ partial, int ldp, const int* __restrict__ active,
@@ -141,15 +179,29 @@ __global__ void __launch_bounds__(RED_THREADS) update_kernel(
   for (int c = threadIdx.x; c < MAXC; c += blockDim.x) hc[c] = c < ncol ? hsign * h[c] : 0.0;
   __syncthreads();
   double acc[1] = {0.0};
+  const long long nch = n / E;
   const long long stride = (long long)gridDim.x * blockDim.x;
 #pragma unroll 1
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    double s = (double)w[i];
+  for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < nch; k += stride) {
+    R wv[E];
+    vload<R, E>(w + k * E, wv);
+    double sum[E];
+#pragma unroll
+    for (int q = 0; q < E; ++q) sum[q] = (double)wv[q];
 #pragma unroll 8
-    for (int c = 0; c < ncol; ++c) s += (double)V[(long long)c * ldv + i] * hc[c];
-    const R wn = (R)s;
-    wout[i] = wn;
-    acc[0] += (double)wn * (double)wn;
+    for (int c = 0; c < ncol; ++c) {
+      R v[E];
+      vload<R, E, NT>(V + (long long)c * ldv + k * E, v);
+#pragma unroll
+      for (int q = 0; q < E; ++q) sum[q] += (double)v[q] * hc[c];
+    }
+    R wn[E];
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+      wn[q] = (R)sum[q];
+      acc[0] += (double)wn[q] * (double)wn[q];
+    }
+    vstore<R, E>(wout + k * E, wn);
   }
   if (!norm) return;
   block_sum_cols<1>(acc, 1, partial + (long long)blockIdx.x * ldp);
@@ -157,17 +209,21 @@ __global__ void __launch_bounds__(RED_THREADS) update_kernel(
 }
 
 // The same update followed by the dots V^T w_new (partial per block and
-// column).  Blocks walk tiles of RED_THREADS elements: each thread forms one
-// element of w_new, the tile of w_new goes to LDS, and then wave q owns
-// columns q, q + 4, ...: its lanes re-read their V entries (from cache) and
-// accumulate.  Per thread only ceil(MAXC/4) accumulators are live.
-template <typename R, int MAXC>
+// column).  Blocks walk tiles of RED_THREADS chunks of E elements: each
+// thread forms one chunk of w_new, the tile of w_new goes to LDS, and then
+// wave q owns columns q, q + 4, ...: its lanes re-read their V chunks (from
+// cache) and accumulate.  Per thread only ceil(MAXC/4) accumulators are live.
+// In the first phase lane l of a wave forms chunk l ^ 1 of the wave's range,
+// so no thread re-reads an address it loaded itself: the compiler cannot
+// keep first-phase V values alive across the barrier to reuse them.
+template <typename R, int MAXC, int E>
 __global__ void __launch_bounds__(RED_THREADS) update_dot_kernel(
     long long n, const R* __restrict__ V, long long ldv, int ncol, const double* __restrict__ h, double hsign,
     const R* w, R* wout, double* __restrict__ partial, int ldp, const int* __restrict__ active, long long sV,
     long long sR, long long sP, long long sA, long long sW, RedEnd e) {
   constexpr int NW = RED_THREADS / 64;
   constexpr int KC = (MAXC + NW - 1) / NW;
+  constexpr int TILE = RED_THREADS * E;   // elements per tile
   if (inactive(active, sA)) return;
   const long long sys = blockIdx.z;
   V += sys * sV;
@@ -176,27 +232,44 @@ __global__ void __launch_bounds__(RED_THREADS) update_dot_kernel(
   h += sys * sR;
   partial += sys * sP;
   __shared__ double hc[MAXC];
-  __shared__ double tile[RED_THREADS];
+  __shared__ double tile[TILE];
   for (int c = threadIdx.x; c < MAXC; c += blockDim.x) hc[c] = c < ncol ? hsign * h[c] : 0.0;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int own = (threadIdx.x & ~63) | (lane ^ 1);   // chunk of the tile this thread forms
   double acc[KC];
 #pragma unroll
   for (int k = 0; k < KC; ++k) acc[k] = 0.0;
-  const long long tstride = (long long)gridDim.x * RED_THREADS;
+  const long long tstride = (long long)gridDim.x * TILE;
 #pragma unroll 1
-  for (long long base = (long long)blockIdx.x * RED_THREADS; base < n; base += tstride) {
+  for (long long base = (long long)blockIdx.x * TILE; base < n; base += tstride) {
     __syncthreads();   // hc ready / previous tile consumed
-    const long long i = base + threadIdx.x;
-    double wd = 0.0;
+    const long long i = base + (long long)own * E;
+    double wd[E];
+#pragma unroll
+    for (int q = 0; q < E; ++q) wd[q] = 0.0;
     if (i < n) {
-      double s = (double)w[i];
+      R wv[E];
+      vload<R, E>(w + i, wv);
+      double sum[E];
+#pragma unroll
+      for (int q = 0; q < E; ++q) sum[q] = (double)wv[q];
 #pragma unroll 8
-      for (int c = 0; c < ncol; ++c) s += (double)V[(long long)c * ldv + i] * hc[c];
-      const R wn = (R)s;
-      wout[i] = wn;
-      wd = (double)wn;
+      for (int c = 0; c < ncol; ++c) {
+        R v[E];
+        vload<R, E>(V + (long long)c * ldv + i, v);
+#pragma unroll
+        for (int q = 0; q < E; ++q) sum[q] += (double)v[q] * hc[c];
+      }
+      R wn[E];
+#pragma unroll
+      for (int q = 0; q < E; ++q) {
+        wn[q] = (R)sum[q];
+        wd[q] = (double)wn[q];
+      }
+      vstore<R, E>(wout + i, wn);
     }
-    tile[threadIdx.x] = wd;
+#pragma unroll
+    for (int q = 0; q < E; ++q) tile[own * E + q] = wd[q];
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < KC; ++k) {
@@ -205,10 +278,14 @@ __global__ void __launch_bounds__(RED_THREADS) update_dot_kernel(
         const R* Vc = V + (long long)c * ldv + base;
         double a = acc[k];
 #pragma unroll
-        for (int q = 0; q < RED_THREADS / 64; ++q) {
-          const int t = lane + 64 * q;
-          if (base + t < n) a += (double)__hip_atomic_load(Vc + t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT) *
-                                 tile[t];
+        for (int r = 0; r < NW; ++r) {
+          const int t = lane + 64 * r;
+          if (base + (long long)t * E < n) {
+            R v[E];
+            vload<R, E>(Vc + (long long)t * E, v);
+#pragma unroll
+            for (int q = 0; q < E; ++q) a += (double)v[q] * tile[t * E + q];
+          }
         }
         acc[k] = a;
       }
@@ -294,16 +371,22 @@ __global__ void __launch_bounds__(RED_THREADS) residual_kernel(long long n, cons
 }
 
 // out = x * (*scale)   (scale read from device memory)
-template <typename R>
+template <typename R, int E>
 __global__ void scale_kernel(long long n, const R* x, R* out, const double* __restrict__ scale,
                              const int* __restrict__ active, long long sV, long long sR, long long sA) {
   if (inactive(active, sA)) return;
   x += blockIdx.z * sV;
   out += blockIdx.z * sV;
   const double a = scale[blockIdx.z * sR];
+  const long long nch = n / E;
   const long long stride = (long long)gridDim.x * blockDim.x;
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
-    out[i] = (R)((double)x[i] * a);
+  for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < nch; k += stride) {
+    R v[E];
+    vload<R, E>(x + k * E, v);
+#pragma unroll
+    for (int q = 0; q < E; ++q) v[q] = (R)((double)v[q] * a);
+    vstore<R, E>(out + k * E, v);
+  }
 }
 
 // out = (To)(x * (*scale)) with a precision change
@@ -345,6 +428,23 @@ inline unsigned grid_for(long long n) {
 
 inline long long part_stride(int ldp) { return (long long)RED_BLOCKS * ldp; }
 
+// Chunk width of the vector kernels: 16-byte loads when every column, vector
+// and system stride allows it, else one element.
+template <typename R>
+int chunk_width(long long n, long long ldv, const Batch& b, const void* p0, const void* p1 = nullptr,
+                const void* p2 = nullptr) {
+  constexpr int E = 16 / sizeof(R);
+  if (n % E || ldv % E || b.vec % E || b.w() % E) return 1;
+  for (const void* p : {p0, p1, p2})
+    if (reinterpret_cast<uintptr_t>(p) % 16) return 1;
+  return E;
+}
+
+// Basis columns of at least this many bytes are streamed with nontemporal
+// loads in the single-pass kernels (they are not re-read from cache before
+// the next pass anyway).
+constexpr long long NT_MIN_BYTES = 4ll << 20;
+
 }  // namespace
 
 template <typename R>
@@ -357,12 +457,23 @@ RedEnd reduction_end(const Blas<R>& bl, unsigned nb, double* out, bool accumulat
 template <typename R>
 void Blas<R>::multidot(long long n, const R* V, long long ldv, int ncol, const R* w, double* out, bool accumulate,
                        const int* active, hipStream_t s, const Batch& b) const {
+  constexpr int VE = 16 / sizeof(R);
+  const int E = chunk_width<R>(n, ldv, b, V, w);
+  const bool nt = n * (long long)sizeof(R) >= NT_MIN_BYTES;
   const int chunks = (ncol + 15) / 16;
-  const unsigned nb = grid_for(n);
+  const unsigned nb = grid_for(n / E);
   const long long sP = part_stride(ldp);
   const RedEnd e = reduction_end(*this, nb, out, accumulate, b);
-  multidot_kernel<R, 16><<<dim3(nb, chunks, b.nsys), RED_THREADS, 0, s>>>(n, V, ldv, ncol, w, partial, ldp, active,
-                                                                          b.vec, sP, b.act, e);
+  const dim3 grid(nb, chunks, b.nsys);
+#define SA_MULTIDOT(EE, NT)                                                                                        \
+  multidot_kernel<R, 16, EE, NT><<<grid, RED_THREADS, 0, s>>>(n, V, ldv, ncol, w, partial, ldp, active, b.vec, sP, \
+                                                             b.act, e)
+  if (E == VE) {
+    if (nt) SA_MULTIDOT(VE, true); else SA_MULTIDOT(VE, false);
+  } else {
+    if (nt) SA_MULTIDOT(1, true); else SA_MULTIDOT(1, false);
+  }
+#undef SA_MULTIDOT
   if (!e.ticket)
     reduce_cols_kernel<<<dim3(ncol, b.nsys), RED_THREADS, 0, s>>>(partial, (int)nb, ldp, ncol, out,
                                                                   accumulate ? 1 : 0, active, b.res, sP, b.act);
@@ -374,8 +485,11 @@ bool Blas<R>::update(long long n, const R* V, long long ldv, int ncol, const dou
                      const Batch& b, GState* step, int step_j) const {
   // mode: 0 = no reduction, 1 = dots V^T w_new, 2 = ||w_new||^2
   constexpr int CH = 48;   // columns per launch
+  constexpr int VE = 16 / sizeof(R);
   const bool dot = mode == 1;
-  const unsigned nb = grid_for(n);
+  const int E = chunk_width<R>(n, ldv, b, V, w, wout);
+  const bool nt = n * (long long)sizeof(R) >= NT_MIN_BYTES;
+  const unsigned nb = grid_for(n / E);
   const long long sP = part_stride(ldp);
   const dim3 grid(nb, 1, b.nsys);
   const RedEnd none{nullptr, 0, 0, nullptr, nullptr, 0};
@@ -388,22 +502,30 @@ bool Blas<R>::update(long long n, const R* V, long long ldv, int ncol, const dou
     const bool last = done + c >= ncol;
     const R* Vc = V + (long long)done * ldv;
     if (last && dot && ncol <= CH) {
-      if (c <= 16)
-        update_dot_kernel<R, 16><<<grid, RED_THREADS, 0, s>>>(n, Vc, ldv, c, h + done, hsign, src, wout, partial, ldp,
-                                                              active, b.vec, b.res, sP, b.act, b.w(), e);
-      else
-        update_dot_kernel<R, CH><<<grid, RED_THREADS, 0, s>>>(n, Vc, ldv, c, h + done, hsign, src, wout, partial, ldp,
-                                                              active, b.vec, b.res, sP, b.act, b.w(), e);
+#define SA_UPDOT(MC, EE)                                                                                        \
+  update_dot_kernel<R, MC, EE><<<grid, RED_THREADS, 0, s>>>(n, Vc, ldv, c, h + done, hsign, src, wout, partial, ldp, \
+                                                            active, b.vec, b.res, sP, b.act, b.w(), e)
+      if (c <= 16) {
+        if (E == VE) SA_UPDOT(16, VE); else SA_UPDOT(16, 1);
+      } else {
+        if (E == VE) SA_UPDOT(CH, VE); else SA_UPDOT(CH, 1);
+      }
+#undef SA_UPDOT
       reduced = e.ticket != nullptr;
     } else {
       const int norm = last && mode == 2 ? 1 : 0;
       const RedEnd& ee = norm ? e : none;
-      if (c <= 16)
-        update_kernel<R, 16><<<grid, RED_THREADS, 0, s>>>(n, Vc, ldv, c, h + done, hsign, src, wout, norm, partial,
-                                                          ldp, active, b.vec, b.res, sP, b.act, b.w(), ee);
-      else
-        update_kernel<R, CH><<<grid, RED_THREADS, 0, s>>>(n, Vc, ldv, c, h + done, hsign, src, wout, norm, partial,
-                                                          ldp, active, b.vec, b.res, sP, b.act, b.w(), ee);
+#define SA_UPD(MC, EE, NT)                                                                                        \
+  update_kernel<R, MC, EE, NT><<<grid, RED_THREADS, 0, s>>>(n, Vc, ldv, c, h + done, hsign, src, wout, norm, partial, \
+                                                            ldp, active, b.vec, b.res, sP, b.act, b.w(), ee)
+      if (c <= 16) {
+        if (E == VE) { if (nt) SA_UPD(16, VE, true); else SA_UPD(16, VE, false); }
+        else { if (nt) SA_UPD(16, 1, true); else SA_UPD(16, 1, false); }
+      } else {
+        if (E == VE) { if (nt) SA_UPD(CH, VE, true); else SA_UPD(CH, VE, false); }
+        else { if (nt) SA_UPD(CH, 1, true); else SA_UPD(CH, 1, false); }
+      }
+#undef SA_UPD
       reduced = norm && e.ticket != nullptr;
     }
     src = wout;
@@ -449,7 +571,13 @@ void Blas<R>::residual(long long n, const R* bvec, const R* y, R* r, double* out
 template <typename R>
 void Blas<R>::scale(long long n, const R* x, R* out, const double* a, const int* active, hipStream_t s,
                     const Batch& b) const {
-  scale_kernel<R><<<dim3(grid_for(n), 1, b.nsys), RED_THREADS, 0, s>>>(n, x, out, a, active, b.vec, b.res, b.act);
+  constexpr int VE = 16 / sizeof(R);
+  if (chunk_width<R>(n, n, b, x, out) == VE)
+    scale_kernel<R, VE><<<dim3(grid_for(n / VE), 1, b.nsys), RED_THREADS, 0, s>>>(n, x, out, a, active, b.vec, b.res,
+                                                                                  b.act);
+  else
+    scale_kernel<R, 1><<<dim3(grid_for(n), 1, b.nsys), RED_THREADS, 0, s>>>(n, x, out, a, active, b.vec, b.res,
+                                                                           b.act);
 }
 
 template <typename R>
