@@ -209,21 +209,22 @@ __global__ void __launch_bounds__(RED_THREADS) update_kernel(
 }
 
 // The same update followed by the dots V^T w_new (partial per block and
-// column).  Blocks walk tiles of RED_THREADS chunks of E elements: each
-// thread forms one chunk of w_new, the tile of w_new goes to LDS, and then
-// wave q owns columns q, q + 4, ...: its lanes re-read their V chunks (from
-// cache) and accumulate.  Per thread only ceil(MAXC/4) accumulators are live.
-// In the first phase lane l of a wave forms chunk l ^ 1 of the wave's range,
-// so no thread re-reads an address it loaded itself: the compiler cannot
-// keep first-phase V values alive across the barrier to reuse them.
-template <typename R, int MAXC, int E>
+// column), reading V once.  The four 16-lane groups of a wave share 16
+// chunks of E elements: group g holds columns g, g + 4, ... (KC of them) of
+// its chunk in registers, the groups' partial sums of V h are combined with
+// two xor shuffles (the same fixed order on all four lanes, so they agree
+// bit for bit), group 0 stores w_new, and each group accumulates the dots of
+// its own columns.  Lanes whose last column lies past ncol read column
+// ncol - 1 again (a cached duplicate) with coefficient 0, so every load is
+// unconditional.
+template <typename R, int KC, int E>
 __global__ void __launch_bounds__(RED_THREADS) update_dot_kernel(
     long long n, const R* __restrict__ V, long long ldv, int ncol, const double* __restrict__ h, double hsign,
     const R* w, R* wout, double* __restrict__ partial, int ldp, const int* __restrict__ active, long long sV,
     long long sR, long long sP, long long sA, long long sW, RedEnd e) {
+  constexpr int NG = 4;
   constexpr int NW = RED_THREADS / 64;
-  constexpr int KC = (MAXC + NW - 1) / NW;
-  constexpr int TILE = RED_THREADS * E;   // elements per tile
+  constexpr int MAXC = NG * KC;
   if (inactive(active, sA)) return;
   const long long sys = blockIdx.z;
   V += sys * sV;
@@ -232,74 +233,69 @@ __global__ void __launch_bounds__(RED_THREADS) update_dot_kernel(
   h += sys * sR;
   partial += sys * sP;
   __shared__ double hc[MAXC];
-  __shared__ double tile[TILE];
+  __shared__ double red[NW][MAXC];
   for (int c = threadIdx.x; c < MAXC; c += blockDim.x) hc[c] = c < ncol ? hsign * h[c] : 0.0;
+  __syncthreads();
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const int own = (threadIdx.x & ~63) | (lane ^ 1);   // chunk of the tile this thread forms
+  const int g = lane >> 4, sl = lane & 15;
+  const R* Vk[KC];
+  double hk[KC];
+#pragma unroll
+  for (int k = 0; k < KC; ++k) {
+    const int c = g + NG * k;
+    Vk[k] = V + (long long)(c < ncol ? c : ncol - 1) * ldv;
+    hk[k] = hc[c];
+  }
   double acc[KC];
 #pragma unroll
   for (int k = 0; k < KC; ++k) acc[k] = 0.0;
-  const long long tstride = (long long)gridDim.x * TILE;
+  const long long nch = n / E;
+  const long long cstride = (long long)gridDim.x * NW * 16;
 #pragma unroll 1
-  for (long long base = (long long)blockIdx.x * TILE; base < n; base += tstride) {
-    __syncthreads();   // hc ready / previous tile consumed
-    const long long i = base + (long long)own * E;
-    double wd[E];
+  for (long long q0 = ((long long)blockIdx.x * NW + wid) * 16 + sl; q0 < nch; q0 += cstride) {
+    const long long i = q0 * E;
+    R v[KC][E];
 #pragma unroll
-    for (int q = 0; q < E; ++q) wd[q] = 0.0;
-    if (i < n) {
-      R wv[E];
-      vload<R, E>(w + i, wv);
-      double sum[E];
+    for (int k = 0; k < KC; ++k) vload<R, E>(Vk[k] + i, v[k]);
+    R wv[E];
+    vload<R, E>(w + i, wv);
+    double p[E];
 #pragma unroll
-      for (int q = 0; q < E; ++q) sum[q] = (double)wv[q];
-#pragma unroll 8
-      for (int c = 0; c < ncol; ++c) {
-        R v[E];
-        vload<R, E>(V + (long long)c * ldv + i, v);
+    for (int q = 0; q < E; ++q) {
+      double t = 0.0;
 #pragma unroll
-        for (int q = 0; q < E; ++q) sum[q] += (double)v[q] * hc[c];
-      }
-      R wn[E];
-#pragma unroll
-      for (int q = 0; q < E; ++q) {
-        wn[q] = (R)sum[q];
-        wd[q] = (double)wn[q];
-      }
-      vstore<R, E>(wout + i, wn);
+      for (int k = 0; k < KC; ++k) t += (double)v[k][q] * hk[k];
+      t += __shfl_xor(t, 16, 64);
+      t += __shfl_xor(t, 32, 64);
+      p[q] = t;
     }
+    R wn[E];
 #pragma unroll
-    for (int q = 0; q < E; ++q) tile[own * E + q] = wd[q];
-    __syncthreads();
+    for (int q = 0; q < E; ++q) wn[q] = (R)((double)wv[q] + p[q]);
+    if (g == 0) vstore<R, E>(wout + i, wn);
 #pragma unroll
     for (int k = 0; k < KC; ++k) {
-      const int c = wid + NW * k;
-      if (c < ncol) {
-        const R* Vc = V + (long long)c * ldv + base;
-        double a = acc[k];
+      double t = (double)v[k][0] * (double)wn[0];
 #pragma unroll
-        for (int r = 0; r < NW; ++r) {
-          const int t = lane + 64 * r;
-          if (base + (long long)t * E < n) {
-            R v[E];
-            vload<R, E>(Vc + (long long)t * E, v);
-#pragma unroll
-            for (int q = 0; q < E; ++q) a += (double)v[q] * tile[t * E + q];
-          }
-        }
-        acc[k] = a;
-      }
+      for (int q = 1; q < E; ++q) t += (double)v[k][q] * (double)wn[q];
+      acc[k] += t;
     }
   }
-  // each column belongs to one wave: reduce over its lanes and store
-  double* prow = partial + (long long)blockIdx.x * ldp;
+  // per column: sum over the 16 lanes of its group, then over the waves
 #pragma unroll
   for (int k = 0; k < KC; ++k) {
-    const int c = wid + NW * k;
-    if (c < ncol) {
-      const double sum = wave_sum(acc[k]);
-      if (lane == 0) prow[c] = sum;
-    }
+    double t = acc[k];
+#pragma unroll
+    for (int off = 8; off > 0; off >>= 1) t += __shfl_down(t, off, 16);
+    if (sl == 0) red[wid][g + NG * k] = t;
+  }
+  __syncthreads();
+  double* prow = partial + (long long)blockIdx.x * ldp;
+  for (int c = threadIdx.x; c < ncol; c += blockDim.x) {
+    double t = red[0][c];
+#pragma unroll
+    for (int q = 1; q < NW; ++q) t += red[q][c];
+    prow[c] = t;
   }
   finish_reduction(partial, gridDim.x, gridDim.x, ldp, ncol, e);
 }
@@ -497,21 +493,39 @@ bool Blas<R>::update(long long n, const R* V, long long ldv, int ncol, const dou
   int done = 0;
   const R* src = w;
   bool reduced = false;   // the reduction ran inside the last launch
+  unsigned nb_dot = nb;   // partial rows of the dot reduction
   for (;;) {
     const int c = ncol - done < CH ? ncol - done : CH;
     const bool last = done + c >= ncol;
     const R* Vc = V + (long long)done * ldv;
     if (last && dot && ncol <= CH) {
-#define SA_UPDOT(MC, EE)                                                                                        \
-  update_dot_kernel<R, MC, EE><<<grid, RED_THREADS, 0, s>>>(n, Vc, ldv, c, h + done, hsign, src, wout, partial, ldp, \
-                                                            active, b.vec, b.res, sP, b.act, b.w(), e)
-      if (c <= 16) {
-        if (E == VE) SA_UPDOT(16, VE); else SA_UPDOT(16, 1);
-      } else {
-        if (E == VE) SA_UPDOT(CH, VE); else SA_UPDOT(CH, 1);
+      // 16 chunks per wave and grid step: its own block count and reduction
+      const unsigned nbd = grid_for(4 * (n / E));
+      const RedEnd ed = reduction_end(*this, nbd, out, accumulate, b);
+      const dim3 gridd(nbd, 1, b.nsys);
+      nb_dot = nbd;
+#define SA_UPDOT(KC, EE)                                                                                         \
+  update_dot_kernel<R, KC, EE><<<gridd, RED_THREADS, 0, s>>>(n, Vc, ldv, c, h + done, hsign, src, wout, partial, ldp, \
+                                                             active, b.vec, b.res, sP, b.act, b.w(), ed)
+#define SA_UPDOT_E(KC) \
+  if (E == VE) SA_UPDOT(KC, VE); else SA_UPDOT(KC, 1)
+      switch ((c + 3) / 4) {
+        case 1: SA_UPDOT_E(1); break;
+        case 2: SA_UPDOT_E(2); break;
+        case 3: SA_UPDOT_E(3); break;
+        case 4: SA_UPDOT_E(4); break;
+        case 5: SA_UPDOT_E(5); break;
+        case 6: SA_UPDOT_E(6); break;
+        case 7: SA_UPDOT_E(7); break;
+        case 8: SA_UPDOT_E(8); break;
+        case 9: SA_UPDOT_E(9); break;
+        case 10: SA_UPDOT_E(10); break;
+        case 11: SA_UPDOT_E(11); break;
+        default: SA_UPDOT_E(12); break;
       }
+#undef SA_UPDOT_E
 #undef SA_UPDOT
-      reduced = e.ticket != nullptr;
+      reduced = ed.ticket != nullptr;
     } else {
       const int norm = last && mode == 2 ? 1 : 0;
       const RedEnd& ee = norm ? e : none;
@@ -535,7 +549,7 @@ bool Blas<R>::update(long long n, const R* V, long long ldv, int ncol, const dou
   if (dot && ncol > CH) {
     multidot(n, V, ldv, ncol, wout, out, accumulate, active, s, b);
   } else if (mode == 1 && !reduced) {
-    reduce_cols_kernel<<<dim3(ncol, b.nsys), RED_THREADS, 0, s>>>(partial, (int)nb, ldp, ncol, out,
+    reduce_cols_kernel<<<dim3(ncol, b.nsys), RED_THREADS, 0, s>>>(partial, (int)nb_dot, ldp, ncol, out,
                                                                   accumulate ? 1 : 0, active, b.res, sP, b.act);
   } else if (mode == 2 && !reduced) {
     reduce_cols_kernel<<<dim3(1, b.nsys), RED_THREADS, 0, s>>>(partial, (int)nb, ldp, 1, out, accumulate ? 1 : 0,
