@@ -94,3 +94,58 @@ def test_singular_block_and_errors():
     with pytest.raises(SAError) as e:
         ctx.precond_setup([0.2], 5, 4, 1)
     assert e.value.code == n.SA_EINVAL
+
+
+def test_full_size_3d_sampled_blocks():
+    """256x128x128 with 4x4x1-cell blocks (262 144 blocks of order 80), the 8
+    benchmark shifts and FP32 factors, as timed: the GPU preconditioner's
+    output on sampled blocks (walls, periodic seams, interior) against the
+    oracle's solve with that block.  Each block comes from the oracle's
+    complex-step operator on a periodic window around it (rows >= 6 cells
+    from the window's cut faces, so the window's operator equals the full
+    grid's there) plus the Philox noise of its global block index."""
+    need_gpu()
+    from oracle import philox
+    from paper_1502_03701_amd import Context
+    prob = synth.config2()
+    q0 = synth.base_flow(prob, seed=2, w_noise=1e-3)
+    shifts = synth.config3_shifts()
+    nx, ny, nz = prob.n
+    lay = bj.block_layout(prob, 4, 4, 1)
+    ctx = Context()
+    ctx.base_set(prob, dev(q0))
+    ctx.precond_setup(shifts, 4, 4, 1, diag_add=0.1, noise_std=0.01, seed=3)
+    r = synth.random_vector(prob, 43)
+    Z = {}
+    for s in (0, 7):
+        z = torch.empty(prob.ndof, dtype=torch.float64, device="cuda:0")
+        ctx.precond_apply(s, dev(r), z)
+        Z[s] = host(z).reshape(prob.shape)
+    ctx.close()
+    dx, dz = prob.length[0] / nx, prob.length[2] / nz
+    M, WX, WZ = 6, 16, 13          # margin, window width in x and z
+    for ib, jb, kb in [(0, 0, 0), (63, 31, 127), (17, 13, 64), (40, 1, 5)]:
+        ii = (4 * ib - M + np.arange(WX)) % nx
+        kk = (kb - M + np.arange(WZ)) % nz
+        sub = synth.mixing_layer_3d(WX, ny, WZ, prob.mach, prob.re, lx=WX * dx, ly=prob.length[1], lz=WZ * dz)
+        qs = q0[:, kk][:, :, :, ii]
+        # local DOF l = var*16 + 4*cy + cx of the block, in window coordinates
+        l = np.arange(80)
+        var, cy, cx = l // 16, (l % 16) // 4, l % 4
+        wflat = ((var * WZ + M) * ny + (4 * jb + cy)) * WX + (M + cx)
+        B = np.zeros((80, 80))
+        for c in range(80):
+            e = np.zeros(sub.ndof)
+            e[wflat[c]] = 1.0
+            B[:, c] = op.jv_cstep(sub, qs, e.reshape(sub.shape)).ravel()[wflat]
+        b = (kb * lay["nby"] + jb) * lay["nbx"] + ib
+        E = philox.block_noise(3, 80, [b])[0]
+        gflat = ((var * nz + kb) * ny + (4 * jb + cy)) * nx + (4 * ib + cx)
+        wall = (4 * jb + cy == 0) | (4 * jb + cy == ny - 1)
+        for s in (0, 7):
+            Bs = B + 0.01 * E + (0.1 - shifts[s]) * np.eye(80)
+            ref = np.linalg.solve(Bs, r.ravel()[gflat])
+            ref[wall] = 0.0
+            got = Z[s].ravel()[gflat]
+            tol = 8 * 80 * 2.0 ** -24 * np.linalg.cond(Bs)
+            assert rel(got, ref) < tol, (ib, jb, kb, s)
