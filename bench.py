@@ -131,6 +131,9 @@ def main():
     ap.add_argument("--c0-eigs", action="store_true",
                     help="only the time to the four separated eigenpairs of the 48x48 case: FP64 / mixed, "
                          "GMRES / LGMRES inner solves")
+    ap.add_argument("--iram-only", action="store_true",
+                    help="only the 3D 32^3 eigen solve (2 eigenpairs, LGMRES(37, 3) inner solves, FP64 and "
+                         "mixed; for profiling the Arnoldi, Cayley and Ritz kernels)")
     ap.add_argument("--gmres-only", action="store_true",
                     help="only capped GMRES runs: 512x512 FP64 (1 and 8 shifts), one FP32 cycle of "
                          "8 shifts on the 3D grid (for profiling)")
@@ -148,6 +151,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.c0_eigs:
         print(json.dumps(eigs_c0(torch, dev, log=lambda m: print(m, file=sys.stderr, flush=True))))
+        return
+    if args.iram_only:
+        print(json.dumps(eigs_3d(torch, dev, augment=3, log=lambda m: print(m, file=sys.stderr, flush=True))))
         return
     prob = synth.config2()
     q0 = synth.base_flow(prob, seed=2, w_noise=1e-3)

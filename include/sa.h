@@ -145,13 +145,19 @@ const char *sa_version(void);
 /* Kernels of the operator product: a prefetching one (16 x 16 column tiles,
  * the next plane's loads in flight during the pointwise algebra) and a
  * plane-staging one (32 x 8 tiles, two waves per SIMD in FP32), each
- * marching over 32 or 16 z planes per workgroup.  All give the same product
- * to rounding. */
+ * marching over 32, 16, 4 or 1 z planes per workgroup (the shallow ones give
+ * small 3D grids enough workgroups; in 2D the depth is irrelevant).  All give
+ * the same product to rounding. */
 typedef enum {
   SA_JV_PREFETCH_Z32 = 0,
   SA_JV_PREFETCH_Z16 = 1,
   SA_JV_STAGE_Z16 = 2,
-  SA_JV_STAGE_Z32 = 3
+  SA_JV_STAGE_Z32 = 3,
+  SA_JV_PREFETCH_Z4 = 4,
+  SA_JV_PREFETCH_Z1 = 5,
+  SA_JV_STAGE_Z4 = 6,
+  SA_JV_STAGE_Z1 = 7,
+  SA_JV_NVARIANTS = 8
 } sa_jv_variant;
 
 /* Set the base state q0 (eq. model_stabiity: J is linearised about q0).
@@ -167,8 +173,9 @@ int sa_base_set(sa_ctx *ctx, const sa_problem *prob, const double *q0_dev);
  * pinned with sa_set_jv_variant (variant -1 unpins and selects the
  * precision's default until the next sa_base_set; SA_JV_AUTOTUNE=0 in the
  * environment skips the timing).  sa_get_jv_variant returns the variant in
- * use (-1: default) and, if times_us is not NULL, fills times_us[4] with the
- * measured microseconds per launch (0 where not measured).  Errors:
+ * use (-1: default) and, if times_us is not NULL, fills
+ * times_us[SA_JV_NVARIANTS] with the measured microseconds per launch (0
+ * where not measured).  Errors:
  * SA_EINVAL (bad precision or variant). */
 int sa_set_jv_variant(sa_ctx *ctx, sa_prec prec, int variant);
 int sa_get_jv_variant(const sa_ctx *ctx, sa_prec prec, float *times_us);

@@ -30,7 +30,8 @@ EXPORTED = ["sa_create", "sa_destroy", "sa_last_error", "sa_version", "sa_base_s
             "sa_arnoldi_eigs", "sa_set_jv_variant", "sa_get_jv_variant"]
 
 # operator kernel variants (sa_jv_variant)
-JV_VARIANTS = ["prefetch_z32", "prefetch_z16", "stage_z16", "stage_z32"]
+JV_VARIANTS = ["prefetch_z32", "prefetch_z16", "stage_z16", "stage_z32", "prefetch_z4", "prefetch_z1", "stage_z4",
+               "stage_z1"]
 
 
 class Problem(C.Structure):

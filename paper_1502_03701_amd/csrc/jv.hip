@@ -272,8 +272,11 @@ hipError_t launch_jv_pert(const OpParams& p, const R* base, const R* bdata, cons
   if (k == 4) variant = 0;
   if (k == 5) variant = 2;
   if (variant < 0 || variant >= JV_NVARIANTS) variant = sizeof(R) == 8 ? 0 : 2;
-  const int nzc = (variant == 0 || variant == 3) ? 32 : 16;
-  if (variant <= 1)
+  // kernel (0 prefetch, 1 stage) and z planes per workgroup of each variant
+  static constexpr int kind[JV_NVARIANTS] = {0, 0, 1, 1, 0, 0, 1, 1};
+  static constexpr int depth[JV_NVARIANTS] = {32, 16, 16, 32, 4, 1, 4, 1};
+  const int nzc = depth[variant];
+  if (kind[variant] == 0)
     return launch_jv_prefetch<R>(p, base, bdata, x, y, nrhs, shift, active, s, sX, sY, shifts, sA, nzc);
   return launch_jv_stage<R>(p, base, bdata, x, y, nrhs, shift, active, s, sX, sY, shifts, sA, nzc);
 }

@@ -306,7 +306,7 @@ hipError_t launch_jv_stage(const OpParams& p, const R* base, const R* bdata, con
   const long long ndof = (long long)(p.ndim + 2) * p.npts;
   // 32-bit indices within the base data (the widest per-point array)
   if ((long long)base_data_fields(p.ndim) * p.npts >= (1LL << 31)) return hipErrorInvalidValue;
-  if (nzc != 16 && nzc != 32) return hipErrorInvalidValue;
+  if (nzc != 1 && nzc != 4 && nzc != 16 && nzc != 32) return hipErrorInvalidValue;
   const int zchunks = p.ndim == 3 ? (p.nz + nzc - 1) / nzc : 1;
   if (sX == 0) sX = ndof;   // right-hand sides one after another
   if (sY == 0) sY = ndof;
@@ -319,6 +319,10 @@ hipError_t launch_jv_stage(const OpParams& p, const R* base, const R* bdata, con
                                        (int)ntot)
   if (p.ndim == 2)
     SA_LAUNCH(2, 16);   // one plane: the chunk depth is irrelevant
+  else if (nzc == 1)
+    SA_LAUNCH(3, 1);
+  else if (nzc == 4)
+    SA_LAUNCH(3, 4);
   else if (nzc == 16)
     SA_LAUNCH(3, 16);
   else

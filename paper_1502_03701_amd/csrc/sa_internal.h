@@ -39,7 +39,7 @@ int base_data_fields(int ndim);
 // shifts[r] (device array; null: the scalar shift) and active[r*sA].
 // launch_jv_prefetch (jv_prefetch.hip) prefetches the next plane (16 x 16
 // tiles); launch_jv_stage (jv_stage.hip) stages whole planes (32 x 8 tiles);
-// nzc (16 or 32) is the number of z planes a workgroup marches over.
+// nzc (1, 4, 16 or 32) is the number of z planes a workgroup marches over.
 template <typename R>
 hipError_t launch_jv_prefetch(const OpParams& p, const R* base, const R* bdata, const R* x, R* y, int nrhs, R shift,
                               const int* active, hipStream_t s, long long sX, long long sY, const double* shifts,
@@ -51,7 +51,10 @@ hipError_t launch_jv_stage(const OpParams& p, const R* base, const R* bdata, con
 // The variants of the perturbation-only kernel (values of sa.h's
 // sa_jv_variant); -1 is the precision's default (prefetch z32 in FP64,
 // stage z16 in FP32).
-constexpr int JV_NVARIANTS = 4;   // prefetch z32, prefetch z16, stage z16, stage z32
+// prefetch z32, prefetch z16, stage z16, stage z32, prefetch z4, prefetch z1,
+// stage z4, stage z1 (zN: N planes per workgroup; shallow ones give small 3D
+// grids enough workgroups)
+constexpr int JV_NVARIANTS = 8;
 template <typename R>
 hipError_t launch_jv_pert(const OpParams& p, const R* base, const R* bdata, const R* x, R* y, int nrhs, R shift,
                           const int* active, hipStream_t s, long long sX = 0, long long sY = 0,
