@@ -424,6 +424,17 @@ inline unsigned grid_for(long long n) {
 
 inline long long part_stride(int ldp) { return (long long)RED_BLOCKS * ldp; }
 
+// Blocks for nch chunks (one per thread and grid step).  Mid-size vectors
+// that would leave compute units idle get two blocks per unit (at least 64
+// chunks each), which measured faster than one block per unit with the
+// reduction finished in the kernel; short vectors keep few blocks (latency).
+constexpr int NUM_CU = 256;
+inline unsigned grid_for_chunks(long long nch) {
+  const unsigned b = grid_for(nch);
+  if (b < (unsigned)NUM_CU && nch >= 128ll * NUM_CU) return 2 * NUM_CU;
+  return b;
+}
+
 // Chunk width of the vector kernels: 16-byte loads when every column, vector
 // and system stride allows it, else one element.
 template <typename R>
@@ -457,7 +468,7 @@ void Blas<R>::multidot(long long n, const R* V, long long ldv, int ncol, const R
   const int E = chunk_width<R>(n, ldv, b, V, w);
   const bool nt = n * (long long)sizeof(R) >= NT_MIN_BYTES;
   const int chunks = (ncol + 15) / 16;
-  const unsigned nb = grid_for(n / E);
+  const unsigned nb = grid_for_chunks(n / E);
   const long long sP = part_stride(ldp);
   const RedEnd e = reduction_end(*this, nb, out, accumulate, b);
   const dim3 grid(nb, chunks, b.nsys);
@@ -485,7 +496,7 @@ bool Blas<R>::update(long long n, const R* V, long long ldv, int ncol, const dou
   const bool dot = mode == 1;
   const int E = chunk_width<R>(n, ldv, b, V, w, wout);
   const bool nt = n * (long long)sizeof(R) >= NT_MIN_BYTES;
-  const unsigned nb = grid_for(n / E);
+  const unsigned nb = grid_for_chunks(n / E);
   const long long sP = part_stride(ldp);
   const dim3 grid(nb, 1, b.nsys);
   const RedEnd none{nullptr, 0, 0, nullptr, nullptr, 0};
@@ -587,7 +598,7 @@ void Blas<R>::scale(long long n, const R* x, R* out, const double* a, const int*
                     const Batch& b) const {
   constexpr int VE = 16 / sizeof(R);
   if (chunk_width<R>(n, n, b, x, out) == VE)
-    scale_kernel<R, VE><<<dim3(grid_for(n / VE), 1, b.nsys), RED_THREADS, 0, s>>>(n, x, out, a, active, b.vec, b.res,
+    scale_kernel<R, VE><<<dim3(grid_for_chunks(n / VE), 1, b.nsys), RED_THREADS, 0, s>>>(n, x, out, a, active, b.vec, b.res,
                                                                                   b.act);
   else
     scale_kernel<R, 1><<<dim3(grid_for(n), 1, b.nsys), RED_THREADS, 0, s>>>(n, x, out, a, active, b.vec, b.res,
