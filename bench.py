@@ -32,13 +32,15 @@ HBM_PEAK_GBS = 8000.0
 
 
 COUNTERS = os.path.join(ROOT, "profiles", "jv_prefetch_fp64_256x128x128_hbm_counters.md")
-KERNEL_SOURCES = ["paper_1502_03701_amd/csrc/jv_prefetch.hip", "paper_1502_03701_amd/csrc/jv_common.h"]
+KERNEL_SOURCES = ["paper_1502_03701_amd/csrc/jv_prefetch.hip", "paper_1502_03701_amd/csrc/jv_stage.hip",
+                  "paper_1502_03701_amd/csrc/jv_common.h", "paper_1502_03701_amd/csrc/jv.hip"]
 
 
-def measured_traffic():
-    """HBM bytes per launch of the FP64 operator kernel from the committed
-    rocprofv3 FETCH_SIZE / WRITE_SIZE summary (calibrated against a copy of
-    known size), or None if the kernel source changed since it was taken."""
+def measured_traffic(variant):
+    """HBM bytes per launch of the FP64 operator kernel variant the autotuner
+    kept, from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary
+    (calibrated against a copy of known size), or None if that variant was
+    not measured or the kernel source changed since."""
     import hashlib
     try:
         text = open(COUNTERS).read()
@@ -53,10 +55,11 @@ def measured_traffic():
     for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
-    key = "kernel_source_sha256 (jv_prefetch.hip + jv_common.h at measurement)"
-    if fields.get(key) != h.hexdigest() or "traffic_bytes_per_launch" not in fields:
+    key = "kernel_source_sha256 (jv_prefetch.hip, jv_stage.hip, jv_common.h, jv.hip at measurement)"
+    name = "traffic_bytes_per_launch[%s]" % variant
+    if fields.get(key) != h.hexdigest() or name not in fields:
         return None
-    return int(fields["traffic_bytes_per_launch"])
+    return int(fields[name])
 
 
 def calib_copy(torch, dev):
@@ -214,7 +217,7 @@ def main():
                    "grid": [256, 128, 128], "nv": nv, "shift": 0.2},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic() if tuned["f64"]["variant"] == "prefetch_z32" else None,
+                     "traffic": measured_traffic(tuned["f64"]["variant"]),
                      "kernel": "jv_prefetch_kernel<double,3>" if tuned["f64"]["variant"].startswith("prefetch")
                      else "jv_stage_kernel<double,3>", "alg_bytes_per_point": 3 * nv * 8},
         "fp32_jv": {"gpts": npts / per32 / 1e9, "ms": per32 * 1e3,
@@ -362,19 +365,23 @@ def eigs_3d(torch, dev, side=32, nev=2, ncv=16, max_restarts=60, augment=0, log=
     ctx = Context()
     ctx.base_set(p, torch.from_numpy(synth.base_flow(p, seed=1, w_noise=1e-3).ravel()).to(dev))
     v0 = torch.from_numpy(synth.random_vector(p, 0).ravel()).to(dev)
+    # Ritz vectors and their true residuals are part of the timed solve
+    evr = torch.empty(nev * p.ndof, dtype=torch.float64, device=dev)
+    evi = torch.empty_like(evr)
     out, lam = {}, {}
     for name, prec in (("fp64", SA_F64), ("mixed", SA_MIXED)):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         rc, r = arnoldi_eigs([ctx], [v0], nev=nev, ncv=ncv, sigma=0.2, mu=-0.2, tol=1e-10, max_restarts=max_restarts,
                              restart=40 - augment, augment=augment, lin_tol=1e-12, prec=prec, inner_tol=1e-4,
-                             max_outer=30)
+                             max_outer=30, evecs=[(evr, evi)])
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         lam[name] = r[0]["lam"]
         out["eigs_3d_%d_nev%d_%s%s" % (side, nev, "lgmres_" if augment else "", name)] = {"seconds": el, "rc": rc, "nconv": r[0]["nconv"],
                                                 "n_matvec": r[0]["n_matvec"], "n_cayley": r[0]["n_cayley"],
-                                                "lam": [[l.real, l.imag] for l in r[0]["lam"]]}
+                                                "lam": [[l.real, l.imag] for l in r[0]["lam"]],
+                                                "resid": r[0]["resid"]}
         if log:
             log("eigs 3d %d %s%s: %.1f s, %d matvecs" % (side, "lgmres " if augment else "", name, el,
                                                        r[0]["n_matvec"]))
