@@ -217,7 +217,7 @@ __global__ void __launch_bounds__(RED_THREADS) update_kernel(
 // its own columns.  Lanes whose last column lies past ncol read column
 // ncol - 1 again (a cached duplicate) with coefficient 0, so every load is
 // unconditional.
-template <typename R, int KC, int E>
+template <typename R, int KC, int E, bool NT>
 __global__ void __launch_bounds__(RED_THREADS) update_dot_kernel(
     long long n, const R* __restrict__ V, long long ldv, int ncol, const double* __restrict__ h, double hsign,
     const R* w, R* wout, double* __restrict__ partial, int ldp, const int* __restrict__ active, long long sV,
@@ -256,7 +256,7 @@ __global__ void __launch_bounds__(RED_THREADS) update_dot_kernel(
     const long long i = q0 * E;
     R v[KC][E];
 #pragma unroll
-    for (int k = 0; k < KC; ++k) vload<R, E>(Vk[k] + i, v[k]);
+    for (int k = 0; k < KC; ++k) vload<R, E, NT>(Vk[k] + i, v[k]);
     R wv[E];
     vload<R, E>(w + i, wv);
     double p[E];
@@ -515,11 +515,11 @@ bool Blas<R>::update(long long n, const R* V, long long ldv, int ncol, const dou
       const RedEnd ed = reduction_end(*this, nbd, out, accumulate, b);
       const dim3 gridd(nbd, 1, b.nsys);
       nb_dot = nbd;
-#define SA_UPDOT(KC, EE)                                                                                         \
-  update_dot_kernel<R, KC, EE><<<gridd, RED_THREADS, 0, s>>>(n, Vc, ldv, c, h + done, hsign, src, wout, partial, ldp, \
-                                                             active, b.vec, b.res, sP, b.act, b.w(), ed)
+#define SA_UPDOT(KC, EE, NT)                                                                                    \
+  update_dot_kernel<R, KC, EE, NT><<<gridd, RED_THREADS, 0, s>>>(n, Vc, ldv, c, h + done, hsign, src, wout, partial, \
+                                                                 ldp, active, b.vec, b.res, sP, b.act, b.w(), ed)
 #define SA_UPDOT_E(KC) \
-  if (E == VE) SA_UPDOT(KC, VE); else SA_UPDOT(KC, 1)
+  if (E != VE) SA_UPDOT(KC, 1, false); else if (nt) SA_UPDOT(KC, VE, true); else SA_UPDOT(KC, VE, false)
       switch ((c + 3) / 4) {
         case 1: SA_UPDOT_E(1); break;
         case 2: SA_UPDOT_E(2); break;
