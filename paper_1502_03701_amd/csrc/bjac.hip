@@ -293,15 +293,28 @@ __global__ void __launch_bounds__(64) lu_mfma_kernel(BLayout L, const double* __
   bool sing = false;
   const int li = lane % 16, lk = lane / 16;
   for (int c0 = 0; c0 < nb; c0 += 16) {
-    // panel elimination, columns c0 .. c0+15
-    for (int k = c0; k < c0 + 16; ++k) {
-      float best = -1.0f;
-      int bi = nb;
-      for (int i = k + lane; i < nb; i += 64) {
-        const float v = fabsf(A[k * nb + i]);
-        if (v > best) {
-          best = v;
-          bi = i;
+    // Panel elimination, columns c0 .. c0+15, in registers: lane l holds rows
+    // c0 + l and c0 + 64 + l of the panel.  Pivot search by a wave butterfly,
+    // row exchanges and the pivot row by uniform-lane reads; the exchanges
+    // are applied to the other columns after the panel.
+    float P[2][16];
+    const int r0 = c0 + lane, r1 = c0 + 64 + lane;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      P[0][c] = r0 < nb ? A[(c0 + c) * nb + r0] : 0.0f;
+      P[1][c] = r1 < nb ? A[(c0 + c) * nb + r1] : 0.0f;
+    }
+    int piv[16];
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      const int k = c0 + kk;
+      float best = r0 >= k && r0 < nb ? fabsf(P[0][kk]) : -1.0f;
+      int bi = r0 >= k && r0 < nb ? r0 : nb;
+      if (r1 < nb) {
+        const float v1 = fabsf(P[1][kk]);
+        if (v1 > best) {
+          best = v1;
+          bi = r1;
         }
       }
 #pragma unroll
@@ -314,42 +327,63 @@ __global__ void __launch_bounds__(64) lu_mfma_kernel(BLayout L, const double* __
         }
       }
       if (!(best > 0.0f)) sing = true;
-      const int p = bi < nb ? bi : k;
-      if (p != k) {
-        for (int c = lane; c < nb; c += 64) {
-          const float t1 = A[c * nb + k];
-          A[c * nb + k] = A[c * nb + p];
-          A[c * nb + p] = t1;
-        }
-        if (lane == 0) {
-          const int t2 = s_perm[k];
-          s_perm[k] = s_perm[p];
-          s_perm[p] = t2;
-        }
-      }
-      __syncthreads();
-      const float piv = A[k * nb + k];
-      const float ipiv = piv != 0.0f ? 1.0f / piv : 0.0f;
-      // row k of the panel (broadcast) and this lane's rows, read in one go,
-      // updated in registers, written back: no load waits on a prior store
+      const int p = __builtin_amdgcn_readfirstlane(bi < nb ? bi : k);
+      piv[kk] = p;
+      const int lk = k - c0;                                // lane of row k (slot 0)
+      const int lp = (p - c0) & 63, sp = (p - c0) >> 6;    // lane and slot of row p
       float urow[16];
 #pragma unroll
-      for (int c = 0; c < 16; ++c) urow[c] = c0 + c > k ? A[(c0 + c) * nb + k] : 0.0f;
-      for (int i = k + 1 + lane; i < nb; i += 64) {
-        float mine[16];
-#pragma unroll
-        for (int c = 0; c < 16; ++c) mine[c] = A[(c0 + c) * nb + i];
-        const float lik = A[k * nb + i] * ipiv;
-#pragma unroll
-        for (int c = 0; c < 16; ++c)
-          if (c0 + c > k) mine[c] -= lik * urow[c];
-#pragma unroll
-        for (int c = 0; c < 16; ++c)
-          if (c0 + c > k) A[(c0 + c) * nb + i] = mine[c];
-        A[k * nb + i] = lik;
+      for (int c = 0; c < 16; ++c) {
+        const float vk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(P[0][c]), lk));
+        const float vp = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sp ? P[1][c] : P[0][c]), lp));
+        urow[c] = vp;   // row k after the exchange
+        if (p != k) {
+          if (lane == lk) P[0][c] = vp;
+          if (lane == lp) {
+            if (sp) P[1][c] = vk;
+            else P[0][c] = vk;
+          }
+        }
       }
-      __syncthreads();
+      if (p != k && lane == 0) {
+        const int t2 = s_perm[k];
+        s_perm[k] = s_perm[p];
+        s_perm[p] = t2;
+      }
+      const float ipiv = urow[kk] != 0.0f ? 1.0f / urow[kk] : 0.0f;
+      if (r0 > k && r0 < nb) {
+        const float l = P[0][kk] * ipiv;
+        P[0][kk] = l;
+#pragma unroll
+        for (int c = kk + 1; c < 16; ++c) P[0][c] -= l * urow[c];
+      }
+      if (r1 < nb) {
+        const float l = P[1][kk] * ipiv;
+        P[1][kk] = l;
+#pragma unroll
+        for (int c = kk + 1; c < 16; ++c) P[1][c] -= l * urow[c];
+      }
     }
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      if (r0 < nb) A[(c0 + c) * nb + r0] = P[0][c];
+      if (r1 < nb) A[(c0 + c) * nb + r1] = P[1][c];
+    }
+    // the panel's row exchanges on the other columns (a lane per column)
+    for (int c = lane; c < nb - 16; c += 64) {
+      const int col = c < c0 ? c : c + 16;
+      float* Ac = A + col * nb;
+#pragma unroll
+      for (int kk = 0; kk < 16; ++kk) {
+        const int k = c0 + kk, p = piv[kk];
+        if (p != k) {
+          const float t1 = Ac[k];
+          Ac[k] = Ac[p];
+          Ac[p] = t1;
+        }
+      }
+    }
+    __syncthreads();
     const int c1 = c0 + 16;
     if (c1 >= nb) break;
     // U12 = L11^-1 A12 (unit lower L11), a lane per column
