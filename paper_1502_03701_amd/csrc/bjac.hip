@@ -265,9 +265,10 @@ __global__ void __launch_bounds__(64) lu_mfma_kernel(BLayout L, const double* __
                                                      float* __restrict__ LU, int* __restrict__ perm,
                                                      int* __restrict__ singular) {
   extern __shared__ unsigned char smem[];
-  float* A = reinterpret_cast<float*>(smem);   // nb x nb column-major
-  __shared__ int s_perm[128];
   const int nb = L.nb;
+  const int ld = nb + 1;   // odd column stride: lane-per-column accesses hit distinct banks
+  float* A = reinterpret_cast<float*>(smem);   // nb x nb column-major, leading dimension ld
+  __shared__ int s_perm[128];
   const int lane = threadIdx.x;
   long long b;
   int s;
@@ -285,7 +286,7 @@ __global__ void __launch_bounds__(64) lu_mfma_kernel(BLayout L, const double* __
 #pragma unroll
     for (int q = 0; q < 20; ++q) {
       const int t = t0 + lane + 64 * q;
-      if (t < nb * nb) A[t] = (float)(t / nb == t % nb ? v[q] + dshift : v[q]);
+      if (t < nb * nb) A[(t / nb) * ld + t % nb] = (float)(t / nb == t % nb ? v[q] + dshift : v[q]);
     }
   }
   for (int t = lane; t < nb; t += 64) s_perm[t] = t;
@@ -298,23 +299,23 @@ __global__ void __launch_bounds__(64) lu_mfma_kernel(BLayout L, const double* __
     // row exchanges and the pivot row by uniform-lane reads; the exchanges
     // are applied to the other columns after the panel.
     float P[2][16];
-    const int r0 = c0 + lane, r1 = c0 + 64 + lane;
+    const int ra = c0 + lane, rb = c0 + 64 + lane;
 #pragma unroll
     for (int c = 0; c < 16; ++c) {
-      P[0][c] = r0 < nb ? A[(c0 + c) * nb + r0] : 0.0f;
-      P[1][c] = r1 < nb ? A[(c0 + c) * nb + r1] : 0.0f;
+      P[0][c] = ra < nb ? A[(c0 + c) * ld + ra] : 0.0f;
+      P[1][c] = rb < nb ? A[(c0 + c) * ld + rb] : 0.0f;
     }
     int piv[16];
 #pragma unroll
     for (int kk = 0; kk < 16; ++kk) {
       const int k = c0 + kk;
-      float best = r0 >= k && r0 < nb ? fabsf(P[0][kk]) : -1.0f;
-      int bi = r0 >= k && r0 < nb ? r0 : nb;
-      if (r1 < nb) {
+      float best = ra >= k && ra < nb ? fabsf(P[0][kk]) : -1.0f;
+      int bi = ra >= k && ra < nb ? ra : nb;
+      if (rb < nb) {
         const float v1 = fabsf(P[1][kk]);
         if (v1 > best) {
           best = v1;
-          bi = r1;
+          bi = rb;
         }
       }
 #pragma unroll
@@ -351,13 +352,13 @@ __global__ void __launch_bounds__(64) lu_mfma_kernel(BLayout L, const double* __
         s_perm[p] = t2;
       }
       const float ipiv = urow[kk] != 0.0f ? 1.0f / urow[kk] : 0.0f;
-      if (r0 > k && r0 < nb) {
+      if (ra > k && ra < nb) {
         const float l = P[0][kk] * ipiv;
         P[0][kk] = l;
 #pragma unroll
         for (int c = kk + 1; c < 16; ++c) P[0][c] -= l * urow[c];
       }
-      if (r1 < nb) {
+      if (rb < nb) {
         const float l = P[1][kk] * ipiv;
         P[1][kk] = l;
 #pragma unroll
@@ -366,13 +367,13 @@ __global__ void __launch_bounds__(64) lu_mfma_kernel(BLayout L, const double* __
     }
 #pragma unroll
     for (int c = 0; c < 16; ++c) {
-      if (r0 < nb) A[(c0 + c) * nb + r0] = P[0][c];
-      if (r1 < nb) A[(c0 + c) * nb + r1] = P[1][c];
+      if (ra < nb) A[(c0 + c) * ld + ra] = P[0][c];
+      if (rb < nb) A[(c0 + c) * ld + rb] = P[1][c];
     }
     // the panel's row exchanges on the other columns (a lane per column)
     for (int c = lane; c < nb - 16; c += 64) {
       const int col = c < c0 ? c : c + 16;
-      float* Ac = A + col * nb;
+      float* Ac = A + col * ld;
 #pragma unroll
       for (int kk = 0; kk < 16; ++kk) {
         const int k = c0 + kk, p = piv[kk];
@@ -390,14 +391,14 @@ __global__ void __launch_bounds__(64) lu_mfma_kernel(BLayout L, const double* __
     for (int c = c1 + lane; c < nb; c += 64) {
       float x[16];
 #pragma unroll
-      for (int i = 0; i < 16; ++i) x[i] = A[c * nb + c0 + i];
+      for (int i = 0; i < 16; ++i) x[i] = A[c * ld + c0 + i];
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
 #pragma unroll
-        for (int i = j + 1; i < 16; ++i) x[i] -= A[(c0 + j) * nb + c0 + i] * x[j];
+        for (int i = j + 1; i < 16; ++i) x[i] -= A[(c0 + j) * ld + c0 + i] * x[j];
       }
 #pragma unroll
-      for (int i = 1; i < 16; ++i) A[c * nb + c0 + i] = x[i];
+      for (int i = 1; i < 16; ++i) A[c * ld + c0 + i] = x[i];
     }
     __syncthreads();
     // A22 -= L21 U12, 16 x 16 tiles on the matrix cores
@@ -406,15 +407,15 @@ __global__ void __launch_bounds__(64) lu_mfma_kernel(BLayout L, const double* __
       const int r0 = c1 + 16 * (t % nt), q0 = c1 + 16 * (t / nt);
       floatx4 acc;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) acc[v] = A[(q0 + li) * nb + r0 + 4 * lk + v];
+      for (int v = 0; v < 4; ++v) acc[v] = A[(q0 + li) * ld + r0 + 4 * lk + v];
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) {
-        const float a = -A[(c0 + 4 * kk + lk) * nb + r0 + li];    // -L21[r0+li][c0+4kk+lk]
-        const float bv = A[(q0 + li) * nb + c0 + 4 * kk + lk];    // U12[c0+4kk+lk][q0+li]
+        const float a = -A[(c0 + 4 * kk + lk) * ld + r0 + li];    // -L21[r0+li][c0+4kk+lk]
+        const float bv = A[(q0 + li) * ld + c0 + 4 * kk + lk];    // U12[c0+4kk+lk][q0+li]
         acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv, acc, 0, 0, 0);
       }
 #pragma unroll
-      for (int v = 0; v < 4; ++v) A[(q0 + li) * nb + r0 + 4 * lk + v] = acc[v];
+      for (int v = 0; v < 4; ++v) A[(q0 + li) * ld + r0 + 4 * lk + v] = acc[v];
     }
     __syncthreads();
   }
@@ -423,7 +424,7 @@ __global__ void __launch_bounds__(64) lu_mfma_kernel(BLayout L, const double* __
   const int gl = (int)(b % 64);
   const long long ngroups = (L.nblocks + 63) / 64;
   float* out = LU + ((long long)s * ngroups + g) * nb * nb * 64 + gl;
-  for (int t = lane; t < nb * nb; t += 64) out[(long long)t * 64] = A[t];
+  for (int t = lane; t < nb * nb; t += 64) out[(long long)t * 64] = A[(t / nb) * ld + t % nb];
   int* pout = perm + ((long long)s * ngroups + g) * nb * 64 + gl;
   for (int t = lane; t < nb; t += 64) pout[t * 64] = s_perm[t];
 }
@@ -646,8 +647,9 @@ extern "C" int sa_precond_setup(sa_ctx* c, const sa_precond_opts* o, int nshift,
   const unsigned grid = (unsigned)(L.nblocks * nshift);
   if (o->factor_prec == SA_F64)
     lu_kernel<double><<<grid, 256, lds, s>>>(L, B, sh, o->diag_add, (double*)LU, perm, flag);
-  else if (L.nb % 16 == 0)
-    lu_mfma_kernel<<<grid, 64, lds, s>>>(L, B, sh, o->diag_add, (float*)LU, perm, flag);
+  else if (L.nb % 16 == 0)   // LDS block with leading dimension nb + 1
+    lu_mfma_kernel<<<grid, 64, sizeof(float) * L.nb * (L.nb + 1), s>>>(L, B, sh, o->diag_add, (float*)LU, perm,
+                                                                         flag);
   else
     lu_kernel<float><<<grid, 256, lds, s>>>(L, B, sh, o->diag_add, (float*)LU, perm, flag);
   hipError_t e = hipGetLastError();
