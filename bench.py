@@ -137,6 +137,8 @@ def main():
     ap.add_argument("--iram-only", action="store_true",
                     help="only the 3D 32^3 eigen solve (2 eigenpairs, LGMRES(37, 3) inner solves, FP64 and "
                          "mixed; for profiling the Arnoldi, Cayley and Ritz kernels)")
+    ap.add_argument("--sweep-mid", action="store_true",
+                    help="only the sweep of 8 uneven flows on sides 64-128 (LGMRES(37, 3), concurrent)")
     ap.add_argument("--gmres-only", action="store_true",
                     help="only capped GMRES runs: 512x512 FP64 (1 and 8 shifts), one FP32 cycle of "
                          "8 shifts on the 3D grid (for profiling)")
@@ -154,6 +156,10 @@ def main():
     dev = torch.device("cuda:0")
     if args.c0_eigs:
         print(json.dumps(eigs_c0(torch, dev, log=lambda m: print(m, file=sys.stderr, flush=True))))
+        return
+    if args.sweep_mid:
+        print(json.dumps(sweep(torch, dev, augment=3, modes=("concurrent",), sides=(64, 96, 128), tag="mid",
+                               max_matvec=30000, log=lambda m: print(m, file=sys.stderr, flush=True))))
         return
     if args.iram_only:
         print(json.dumps(eigs_3d(torch, dev, augment=3, log=lambda m: print(m, file=sys.stderr, flush=True))))
@@ -321,6 +327,8 @@ def extras(torch, dev, ctx3, prob3):
     log = lambda m: print(m, file=sys.stderr, flush=True)   # noqa: E731
     res.update(sweep(torch, dev, log=log))
     res.update(sweep(torch, dev, augment=3, modes=("concurrent",), log=log))
+    res.update(sweep(torch, dev, augment=3, modes=("concurrent",), sides=(64, 96, 128), tag="mid",
+                     max_matvec=30000, log=log))
     res.update(eigs_3d(torch, dev, log=log))
     res.update(eigs_3d(torch, dev, augment=3, log=log))
     return res
@@ -393,17 +401,19 @@ def eigs_3d(torch, dev, side=32, nev=2, ncv=16, max_restarts=60, augment=0, log=
     return out
 
 
-def sweep(torch, dev, nev=2, augment=0, modes=("sequential", "concurrent"), log=None):
-    """Reduced sweep of uneven base flows (the sweep's Mach/Re recipe on sides
-    16-32), each its own mixed-precision Cayley-IRAM: the problems one after
-    another on one stream, then all at once on one stream each (run
-    concurrently by the library)."""
+def sweep(torch, dev, nev=2, augment=0, modes=("sequential", "concurrent"), log=None, sides=(16, 24, 32),
+          tag="reduced", max_matvec=10 ** 7):
+    """Sweep of uneven base flows (the sweep's Mach/Re recipe on the given
+    sides, 8 problems), each its own mixed-precision Cayley-IRAM: the
+    problems one after another on one stream, then all at once on one stream
+    each (run concurrently by the library).  max_matvec caps each inner
+    solve."""
     import numpy as np
     import synth
     from paper_1502_03701_amd import SA_MIXED, Context, arnoldi_eigs
-    items = synth.config4_reduced(sides=(16, 24, 32))
+    items = synth.config4_reduced(sides=sides)
     kw = dict(nev=nev, ncv=16, sigma=0.2, mu=-0.2, tol=1e-8, max_restarts=100, restart=40 - augment,
-              augment=augment, lin_tol=1e-10, prec=SA_MIXED, inner_tol=1e-4, max_outer=20)
+              augment=augment, lin_tol=1e-10, prec=SA_MIXED, inner_tol=1e-4, max_outer=20, max_matvec=max_matvec)
     out = {}
     for mode in modes:
         if mode == "sequential":
@@ -431,12 +441,12 @@ def sweep(torch, dev, nev=2, augment=0, modes=("sequential", "concurrent"), log=
         el = time.perf_counter() - t0
         secs = np.array([x["seconds"] for x in r])
         pairs = int(sum(min(x["nconv"], nev) for x in r))
-        out["sweep_reduced_" + ("lgmres_" if augment else "") + mode] = {
+        out["sweep_" + tag + "_" + ("lgmres_" if augment else "") + mode] = {
             "problems": len(items), "sides": [it.problem.n[0] for it in items], "eigenpairs": pairs,
             "seconds": el, "eigenpairs_per_s": pairs / el, "p50_s": float(np.percentile(secs, 50)),
             "p99_s": float(np.percentile(secs, 99)), "n_matvec": int(sum(x["n_matvec"] for x in r))}
         if log:
-            log("sweep %s%s: %.2f s" % ("lgmres " if augment else "", mode, el))
+            log("sweep %s %s%s: %.2f s" % (tag, "lgmres " if augment else "", mode, el))
         for c in ctxs:
             c.close()
     return out
