@@ -53,8 +53,9 @@ __device__ __forceinline__ long long block_dof(const BLayout& L, long long b, in
 }
 
 // e[r][dof(b, l0 + r)] = 1 for blocks b of colour `col`, r < nprobe
-__global__ void probe_fill_kernel(BLayout L, double* __restrict__ e, long long n, int col, int cx, int cy,
-                                  int cz, int l0, int nprobe) {
+template <typename F>
+__global__ void probe_fill_kernel(BLayout L, F* __restrict__ e, long long n, int col, int cx, int cy,
+                                  int cz, int l0, int nprobe, F value) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= L.nblocks * nprobe) return;
   const long long b = t % L.nblocks;
@@ -66,11 +67,12 @@ __global__ void probe_fill_kernel(BLayout L, double* __restrict__ e, long long n
   if (c != col) return;
   bool wall;
   const long long d = block_dof(L, b, l0 + r, wall);
-  e[(long long)r * n + d] = 1.0;
+  e[(long long)r * n + d] = value;
 }
 
 // B[b][l0 + r][row] = y[r][dof(b, row)] for blocks of colour col (column-major blocks)
-__global__ void probe_extract_kernel(BLayout L, const double* __restrict__ y, long long n, double* __restrict__ B,
+template <typename F>
+__global__ void probe_extract_kernel(BLayout L, const F* __restrict__ y, long long n, double* __restrict__ B,
                                      int col, int cx, int cy, int cz, int l0, int nprobe) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long per = (long long)L.nb * nprobe;
@@ -86,7 +88,7 @@ __global__ void probe_extract_kernel(BLayout L, const double* __restrict__ y, lo
   if (c != col) return;
   bool wall;
   const long long d = block_dof(L, b, row, wall);
-  B[(b * L.nb + (l0 + r)) * L.nb + row] = y[(long long)r * n + d];
+  B[(b * L.nb + (l0 + r)) * L.nb + row] = (double)y[(long long)r * n + d];
 }
 
 // --- Philox4x32-10 (Salmon et al. 2011) ---
@@ -621,23 +623,37 @@ extern "C" int sa_precond_setup(sa_ctx* c, const sa_precond_opts* o, int nshift,
   const size_t padded = (size_t)((L.nblocks + 63) / 64) * 64;   // blocks, interleaved in groups of 64
   void* LU = c->buffer("pc_LU", fsz * (size_t)nshift * padded * L.nb * L.nb, false);
   int* perm = (int*)c->buffer("pc_perm", sizeof(int) * (size_t)nshift * padded * L.nb, false);
+  // probes in the factor precision: FP32 factors take blocks probed with the
+  // FP32 operator (half the bytes of the FP64 one)
   const int batch = L.nb < 16 ? L.nb : 16;
-  double* E = (double*)c->buffer("pc_probe", sizeof(double) * n * batch, false);
-  double* Y = (double*)c->buffer("pc_resp", sizeof(double) * n * batch, false);
+  void* E = c->buffer("pc_probe", fsz * n * batch, false);
+  void* Y = c->buffer("pc_resp", fsz * n * batch, false);
   if (!B || !sh || !flag || !LU || !perm || !E || !Y) return c->fail(SA_ENOMEM, "sa_precond_setup: out of device memory");
+  hipMemsetAsync(E, 0, fsz * n * batch, s);   // once: each probe batch resets its own entries
   hipMemsetAsync(B, 0, bbytes, s);
   hipMemcpyAsync(sh, shifts_host, sizeof(double) * nshift, hipMemcpyHostToDevice, s);
-  const int ncol = cx * cy * cz;
-  for (int col = 0; col < ncol; ++col) {
-    for (int l0 = 0; l0 < L.nb; l0 += batch) {
-      const int np = std::min(batch, L.nb - l0);
-      hipMemsetAsync(E, 0, sizeof(double) * n * np, s);
-      probe_fill_kernel<<<blocks_for(L.nblocks * np, 256), 256, 0, s>>>(L, E, n, col, cx, cy, cz, l0, np);
-      hipError_t e = c->jv<double>(E, Y, np, 0.0, nullptr);
-      if (e != hipSuccess) return c->hip_fail(e, "sa_precond_setup probe");
-      probe_extract_kernel<<<blocks_for(L.nblocks * L.nb * np, 256), 256, 0, s>>>(L, Y, n, B, col, cx, cy, cz, l0,
-                                                                                 np);
+  auto probe = [&](auto one) -> hipError_t {
+    using F = decltype(one);
+    F* Ef = static_cast<F*>(E);
+    F* Yf = static_cast<F*>(Y);
+    const int ncol = cx * cy * cz;
+    for (int col = 0; col < ncol; ++col) {
+      for (int l0 = 0; l0 < L.nb; l0 += batch) {
+        const int np = std::min(batch, L.nb - l0);
+        const unsigned gf = blocks_for(L.nblocks * np, 256);
+        probe_fill_kernel<F><<<gf, 256, 0, s>>>(L, Ef, n, col, cx, cy, cz, l0, np, one);
+        hipError_t e = c->jv<F>(Ef, Yf, np, 0.0, nullptr);
+        if (e != hipSuccess) return e;
+        probe_extract_kernel<F><<<blocks_for(L.nblocks * L.nb * np, 256), 256, 0, s>>>(L, Yf, n, B, col, cx, cy, cz,
+                                                                                      l0, np);
+        probe_fill_kernel<F><<<gf, 256, 0, s>>>(L, Ef, n, col, cx, cy, cz, l0, np, F(0));
+      }
     }
+    return hipGetLastError();
+  };
+  {
+    const hipError_t e = o->factor_prec == SA_F64 ? probe(1.0) : probe(1.0f);
+    if (e != hipSuccess) return c->hip_fail(e, "sa_precond_setup probe");
   }
   if (o->noise_std != 0.0)
     add_noise_kernel<<<blocks_for(L.nblocks * L.nb * L.nb, 256), 256, 0, s>>>(L, B, o->noise_std, o->seed);
