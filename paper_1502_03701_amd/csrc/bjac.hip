@@ -52,40 +52,61 @@ __device__ __forceinline__ long long block_dof(const BLayout& L, long long b, in
   return (((long long)var * L.nz + k) * L.ny + j) * L.nx + i;
 }
 
-// e[r][dof(b, l0 + r)] = 1 for blocks b of colour `col`, r < nprobe
+// The blocks of one probe colour: block (ib, jb, kb) has colour
+// ((kb % cz) cy + (jb % cy)) cx + (ib % cx), so colour col holds the blocks
+// with residues (rx, ry, rz) along the axes: mx x my x mz of them.
+struct ColourSet {
+  int rx, ry, rz, mx, my, mz;
+  long long count;
+};
+
+ColourSet colour_set(const BLayout& L, int col, int cx, int cy, int cz) {
+  ColourSet q;
+  q.rx = col % cx;
+  q.ry = (col / cx) % cy;
+  q.rz = col / (cx * cy);
+  q.mx = (L.nbx - q.rx + cx - 1) / cx;
+  q.my = (L.nby - q.ry + cy - 1) / cy;
+  q.mz = (L.nbz - q.rz + cz - 1) / cz;
+  q.count = (long long)q.mx * q.my * q.mz;
+  return q;
+}
+
+// block index of the idx-th block of the colour
+__device__ __forceinline__ long long colour_block(const BLayout& L, const ColourSet& q, int cx, int cy, int cz,
+                                                  long long idx) {
+  const int ic = (int)(idx % q.mx);
+  const int jc = (int)((idx / q.mx) % q.my);
+  const int kc = (int)(idx / ((long long)q.mx * q.my));
+  const int ib = q.rx + ic * cx, jb = q.ry + jc * cy, kb = q.rz + kc * cz;
+  return ((long long)kb * L.nby + jb) * L.nbx + ib;
+}
+
+// e[r][dof(b, l0 + r)] = value for the blocks b of one colour, r < nprobe
 template <typename F>
-__global__ void probe_fill_kernel(BLayout L, F* __restrict__ e, long long n, int col, int cx, int cy,
-                                  int cz, int l0, int nprobe, F value) {
+__global__ void probe_fill_kernel(BLayout L, ColourSet q, F* __restrict__ e, long long n, int cx, int cy, int cz,
+                                  int l0, int nprobe, F value) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= L.nblocks * nprobe) return;
-  const long long b = t % L.nblocks;
-  const int r = (int)(t / L.nblocks);
-  const int ib = (int)(b % L.nbx);
-  const int jb = (int)((b / L.nbx) % L.nby);
-  const int kb = (int)(b / ((long long)L.nbx * L.nby));
-  const int c = ((kb % cz) * cy + (jb % cy)) * cx + (ib % cx);
-  if (c != col) return;
+  if (t >= q.count * nprobe) return;
+  const long long b = colour_block(L, q, cx, cy, cz, t % q.count);
+  const int r = (int)(t / q.count);
   bool wall;
   const long long d = block_dof(L, b, l0 + r, wall);
   e[(long long)r * n + d] = value;
 }
 
-// B[b][l0 + r][row] = y[r][dof(b, row)] for blocks of colour col (column-major blocks)
+// B[b][l0 + r][row] = y[r][dof(b, row)] for the blocks of one colour
+// (column-major blocks)
 template <typename F>
-__global__ void probe_extract_kernel(BLayout L, const F* __restrict__ y, long long n, double* __restrict__ B,
-                                     int col, int cx, int cy, int cz, int l0, int nprobe) {
+__global__ void probe_extract_kernel(BLayout L, ColourSet q, const F* __restrict__ y, long long n,
+                                     double* __restrict__ B, int cx, int cy, int cz, int l0, int nprobe) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long per = (long long)L.nb * nprobe;
-  if (t >= L.nblocks * per) return;
-  const long long b = t / per;
+  if (t >= q.count * per) return;
+  const long long b = colour_block(L, q, cx, cy, cz, t / per);
   const int rem = (int)(t % per);
   const int r = rem / L.nb;
   const int row = rem % L.nb;
-  const int ib = (int)(b % L.nbx);
-  const int jb = (int)((b / L.nbx) % L.nby);
-  const int kb = (int)(b / ((long long)L.nbx * L.nby));
-  const int c = ((kb % cz) * cy + (jb % cy)) * cx + (ib % cx);
-  if (c != col) return;
   bool wall;
   const long long d = block_dof(L, b, row, wall);
   B[(b * L.nb + (l0 + r)) * L.nb + row] = (double)y[(long long)r * n + d];
@@ -638,15 +659,17 @@ extern "C" int sa_precond_setup(sa_ctx* c, const sa_precond_opts* o, int nshift,
     F* Yf = static_cast<F*>(Y);
     const int ncol = cx * cy * cz;
     for (int col = 0; col < ncol; ++col) {
+      const ColourSet q = colour_set(L, col, cx, cy, cz);
+      if (q.count == 0) continue;
       for (int l0 = 0; l0 < L.nb; l0 += batch) {
         const int np = std::min(batch, L.nb - l0);
-        const unsigned gf = blocks_for(L.nblocks * np, 256);
-        probe_fill_kernel<F><<<gf, 256, 0, s>>>(L, Ef, n, col, cx, cy, cz, l0, np, one);
+        const unsigned gf = blocks_for(q.count * np, 256);
+        probe_fill_kernel<F><<<gf, 256, 0, s>>>(L, q, Ef, n, cx, cy, cz, l0, np, one);
         hipError_t e = c->jv<F>(Ef, Yf, np, 0.0, nullptr);
         if (e != hipSuccess) return e;
-        probe_extract_kernel<F><<<blocks_for(L.nblocks * L.nb * np, 256), 256, 0, s>>>(L, Yf, n, B, col, cx, cy, cz,
-                                                                                      l0, np);
-        probe_fill_kernel<F><<<gf, 256, 0, s>>>(L, Ef, n, col, cx, cy, cz, l0, np, F(0));
+        probe_extract_kernel<F><<<blocks_for(q.count * L.nb * np, 256), 256, 0, s>>>(L, q, Yf, n, B, cx, cy, cz, l0,
+                                                                                    np);
+        probe_fill_kernel<F><<<gf, 256, 0, s>>>(L, q, Ef, n, cx, cy, cz, l0, np, F(0));
       }
     }
     return hipGetLastError();
