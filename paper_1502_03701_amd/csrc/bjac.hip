@@ -5,16 +5,18 @@
 //  * Extraction by coloured probing: blocks of one colour are more than the
 //    stencil reach (3 cells) apart along some axis, so one product J e with
 //    e = sum over those blocks of unit vector l gives column l of all of
-//    them.  The products run through the FP64 operator kernel, many probes
-//    per launch.
+//    them.  The products run through the operator kernel in the factor
+//    precision, 16 probes per launch; each batch of probes resets its own
+//    entries afterwards.
 //  * Block b of shift s is B_b + diag_add I + noise_std E_b - s I with E_b
 //    seeded standard normals (Philox4x32-10 + Box-Muller, one per entry),
 //    kept in FP64; the factor kernel rounds once to the factor precision.
 //  * One workgroup per (shift, block) factors a block in LDS by LU with
 //    partial pivoting and stores L\U plus the row permutation: FP32 blocks
-//    of order 16k by a blocked LU whose trailing updates run on the matrix
-//    cores (one wavefront per block), other blocks unblocked (wave-butterfly
-//    pivot search, three barriers per elimination step).
+//    of order 16k by a blocked LU (one wavefront per block: 16-column panels
+//    eliminated in registers, trailing updates on the matrix cores), other
+//    blocks unblocked (wave-butterfly pivot search, three barriers per
+//    elimination step).
 //  * Factors are stored block-interleaved: 64 consecutive blocks form a
 //    group whose entry t is contiguous over the blocks.  The apply solves
 //    one block per lane, so each factor load is a coalesced row across the
@@ -273,9 +275,10 @@ __global__ void __launch_bounds__(256) lu_kernel(BLayout L, const double* __rest
 
 // FP32 factors of orders that are multiples of 16 (the C3 blocks are 80):
 // blocked right-looking LU, one wavefront per (block, shift), the block in
-// LDS.  Per 16-column panel: unblocked elimination of the panel with partial
-// pivoting (wave butterfly for the pivot, rows swapped across the whole
-// block), the triangular solve U12 = L11^-1 A12 (a lane per column), and the
+// LDS (column stride nb + 1).  Per 16-column panel: unblocked elimination of
+// the panel in registers with partial pivoting (wave butterfly for the
+// pivot, the row exchanges then applied to the other columns), the
+// triangular solve U12 = L11^-1 A12 (a lane per column), and the
 // trailing update A22 -= L21 U12 on the matrix cores: 16 x 16 output tiles,
 // four v_mfma_f32_16x16x4f32 each (K = 16).  Operand layout of that
 // instruction for lane l: A[i][k] with i = l % 16, k = l / 16; B[k][j] with
