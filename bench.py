@@ -331,6 +331,7 @@ def extras(torch, dev, ctx3, prob3):
                      max_matvec=30000, log=log))
     res.update(eigs_3d(torch, dev, log=log))
     res.update(eigs_3d(torch, dev, augment=3, log=log))
+    res.update(eigs_3d(torch, dev, nev=4, ncv=20, max_restarts=40, augment=3, log=log))
     return res
 
 
