@@ -332,6 +332,7 @@ def extras(torch, dev, ctx3, prob3):
     res.update(eigs_3d(torch, dev, log=log))
     res.update(eigs_3d(torch, dev, augment=3, log=log))
     res.update(eigs_3d(torch, dev, nev=4, ncv=20, max_restarts=40, augment=3, log=log))
+    res.update(eigs_3d(torch, dev, side=64, max_restarts=20, augment=3, log=log))
     return res
 
 
