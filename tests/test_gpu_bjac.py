@@ -28,6 +28,9 @@ CASES = [
     ("3d", synth.mixing_layer_3d(8, 8, 8, 0.5, 1000.0), (4, 4, 1)),
     # order 40: not a multiple of 16, so FP32 factors take the unblocked kernel
     ("2d-nb40", synth.mixing_layer_2d(20, 12, 0.5, 1000.0), (5, 2, 1)),
+    # 5 block rows between the walls, 2 probe colours in y: colours of
+    # unequal size (3 and 2 block rows)
+    ("2d-ragged-colours", synth.mixing_layer_2d(16, 20, 0.3, 500.0), (4, 4, 1)),
 ]
 
 
