@@ -184,3 +184,23 @@ def test_errors(ctxs):
     with pytest.raises(SAError) as e:
         ctx.base_set(bad, dev(synth.base_flow(bad)))
     assert e.value.code == n.SA_EINVAL
+
+
+def test_jv_full_size_2d_every_output(ctxs):
+    """512 x 512 (the 2D benchmark grid, n = 1 048 576), the autotuned
+    kernels: every output of the FP64 product against the oracle to 1e-12,
+    the FP32 product to 1e-5."""
+    from paper_1502_03701_amd import SA_F32, SA_F64
+    prob = synth.config1()
+    q0 = synth.base_flow(prob)
+    v = synth.random_vector(prob, 8)
+    ctx = ctxs()
+    ctx.base_set(prob, dev(q0))
+    assert ctx.jv_variant(SA_F64)[0] >= 0 and ctx.jv_variant(SA_F32)[0] >= 0   # tuned, not defaulted
+    ref = op.jv_cstep(prob, q0, v) - 0.2 * op.project(prob, v)
+    y = torch.empty(prob.ndof, dtype=torch.float64, device="cuda:0")
+    ctx.op_apply(dev(v), y, shift=0.2)
+    assert rel(host(y), ref) < 1e-12
+    y32 = torch.empty(prob.ndof, dtype=torch.float32, device="cuda:0")
+    ctx.op_apply(dev(v, torch.float32), y32, shift=0.2)
+    assert rel(host(y32), ref) < 1e-5
