@@ -176,6 +176,13 @@ def test_gmres_3d_odd_length_scalar_path():
     x32 = torch.zeros(prob.ndof, dtype=torch.float32, device="cuda:0")
     rc, info = ctx.gmres_solve([0.2], dev(b, torch.float32), x32, restart=20, tol=1e-4, prec=SA_F32)
     assert rc == 0 and info[0]["relres"] <= 1e-4
+    # the mixed form (FP32 inner GMRES, FP64 refinement), with LGMRES inner solves
+    from paper_1502_03701_amd import SA_MIXED
+    xm = torch.zeros(prob.ndof, dtype=torch.float64, device="cuda:0")
+    rc, info = ctx.gmres_solve([0.2], dev(b), xm, restart=17, augment=3, tol=1e-10, prec=SA_MIXED,
+                               inner_tol=1e-4, max_outer=30, max_matvec=100000)
+    assert rc == 0 and info[0]["relres"] <= 1e-10 and info[0]["outer"] >= 2
+    assert rel(host(xm), xr) < 1e-10 * cond
     ctx.close()
 
 
