@@ -139,6 +139,11 @@ def main():
                          "mixed; for profiling the Arnoldi, Cayley and Ritz kernels)")
     ap.add_argument("--sweep-mid", action="store_true",
                     help="only the sweep of 8 uneven flows on sides 64-128 (LGMRES(37, 3), concurrent)")
+    ap.add_argument("--c2-solve", action="store_true",
+                    help="only one Cayley system of the 3D grid to 1e-10: FP64 against the mixed form, "
+                         "GMRES(30) and LGMRES(30, 3)")
+    ap.add_argument("--c2-cap", type=int, default=30000,
+                    help="product budget of each --c2-solve solve (a small cap for profiling)")
     ap.add_argument("--gmres-only", action="store_true",
                     help="only capped GMRES runs: 512x512 FP64 (1 and 8 shifts), one FP32 cycle of "
                          "8 shifts on the 3D grid (for profiling)")
@@ -171,6 +176,12 @@ def main():
     ctx.base_set(prob, torch.from_numpy(q0.ravel()).to(dev))
     if args.gmres_only:
         print(json.dumps(gmres_runs(torch, dev, ctx, prob)))
+        return
+    if args.c2_solve:
+        log = lambda m: print(m, file=sys.stderr, flush=True)   # noqa: E731
+        out = c2_solve(torch, dev, ctx, prob, max_matvec=args.c2_cap, log=log)
+        out.update(c2_solve(torch, dev, ctx, prob, augment=3, max_matvec=args.c2_cap, log=log))
+        print(json.dumps(out))
         return
     if args.bjac_only:
         out = bjac(torch, dev, ctx, prob)
@@ -298,6 +309,42 @@ def gmres_runs(torch, dev, ctx3, prob3, max_mv_512=2000):
     return res
 
 
+def c2_solve(torch, dev, ctx3, prob3, sigma=0.2, restart=30, augment=0, max_matvec=30000, log=None):
+    """One Cayley system (J - sigma I) x = b of the full 3D grid, b seeded
+    N(0,1), to 1e-10 relative residual: all-FP64 GMRES(restart) against
+    FP32 GMRES(restart) inner solves (relative tolerance 1e-4) inside FP64
+    refinement, both capped at max_matvec products; augment = k > 0 makes
+    both LGMRES(restart, k).  The true FP64 residual of each
+    solution is recomputed with one FP64 operator product."""
+    import synth
+    from paper_1502_03701_amd import SA_F64, SA_MIXED
+    res = {}
+    key = "c2_solve_%s%d%s_" % ("lgmres" if augment else "gmres", restart, "_%d" % augment if augment else "")
+    b = torch.from_numpy(synth.random_vector(prob3, 6, stream=1).ravel()).to(dev)
+    bn = float(torch.linalg.vector_norm(b))
+    y = torch.empty_like(b)
+    for name, prec in (("fp64", SA_F64), ("mixed", SA_MIXED)):
+        x = torch.zeros_like(b)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, info = ctx3.gmres_solve([sigma], b, x, restart=restart, tol=1e-10, max_matvec=max_matvec, prec=prec,
+                                    inner_tol=1e-4, max_outer=20, augment=augment)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        ctx3.op_apply(x, y, shift=sigma)
+        true_rel = float(torch.linalg.vector_norm(b - y)) / bn
+        i = info[0]
+        res[key + name] = {"seconds": el, "matvecs": i["matvecs"], "iters": i["iters"], "outer": i["outer"], "relres": i["relres"], "true_relres": true_rel,
+                           "status": i["status"], "ms_per_matvec": el / max(1, i["matvecs"]) * 1e3}
+        if log:
+            log(key + "%s: %.2f s, %d products, relres %.2e (true %.2e)"
+                % (name, el, i["matvecs"], i["relres"], true_rel))
+    f, m = res[key + "fp64"], res[key + "mixed"]
+    res[key + "mixed_vs_fp64"] = {"speedup": f["seconds"] / m["seconds"],
+                                  "per_matvec_speedup": f["ms_per_matvec"] / m["ms_per_matvec"]}
+    return res
+
+
 def extras(torch, dev, ctx3, prob3):
     """Secondary measurements (not the headline value)."""
     import synth
@@ -313,6 +360,7 @@ def extras(torch, dev, ctx3, prob3):
 
     res.update(bjac(torch, dev, ctx3, prob3))
     res.update(gmres_runs(torch, dev, ctx3, prob3))
+    res.update(c2_solve(torch, dev, ctx3, prob3, log=lambda m: print(m, file=sys.stderr, flush=True)))
     # time to eigenpairs, FP64 vs mixed, small case (KH pair)
     pe = synth.mixing_layer_2d(32, 32, 0.5, 1000.0)
     ce = Context()
