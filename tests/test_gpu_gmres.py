@@ -222,3 +222,35 @@ def test_gmres_full_size_2d_one_cycle_matches_oracle():
     _, oi = kr.gmres(apply_A, b.ravel(), restart=30, tol=1e-14, max_matvec=30)
     assert abs(info[0]["relres"] - oi["relres"]) <= 1e-3 * oi["relres"]
     ctx.close()
+
+
+def test_mixed_solve_full_size_3d_true_residual():
+    """256 x 128 x 128 (the 3D benchmark grid, n = 20 971 520), the Cayley
+    system at sigma = 0.2 with a seeded N(0,1) right-hand side.  FP32
+    GMRES(30) inside FP64 refinement and all-FP64 GMRES(30), both stopped by
+    a budget of 200 products: the mixed solve reports the FP64 residual that
+    the oracle's complex-step operator gives for the returned x, and its
+    residual tracks the FP64 solve's (the FP32 basis rounds at 1e-7, far
+    below the residuals reached)."""
+    need_gpu()
+    from paper_1502_03701_amd import SA_F64, SA_MIXED, Context
+    prob = synth.config2()
+    q0 = synth.base_flow(prob, seed=2, w_noise=1e-3)
+    b = synth.random_vector(prob, 6, stream=1)
+    ctx = Context()
+    ctx.base_set(prob, dev(q0))
+    out = {}
+    for name, prec in (("fp64", SA_F64), ("mixed", SA_MIXED)):
+        x = torch.zeros(prob.ndof, dtype=torch.float64, device="cuda:0")
+        rc, info = ctx.gmres_solve([0.2], dev(b), x, restart=30, tol=1e-10, max_matvec=200, prec=prec,
+                                   inner_tol=1e-4, max_outer=20)
+        assert rc > 0 and info[0]["status"] == 1, info   # stopped by the budget
+        out[name] = (host(x), info[0]["relres"])
+    ctx.close()
+    xm, rm = out["mixed"]
+    r64 = out["fp64"][1]
+    assert 1e-4 < rm < 0.5 and 1e-4 < r64 < 0.5
+    assert abs(rm - r64) <= 0.05 * r64   # the refinement step costs a product or two of the budget
+    ax = op.jv_cstep(prob, q0, xm.reshape(b.shape)) - 0.2 * op.project(prob, xm.reshape(b.shape))
+    true = np.linalg.norm((b - ax).ravel()) / np.linalg.norm(b.ravel())
+    assert abs(true - rm) <= 1e-8 * true
