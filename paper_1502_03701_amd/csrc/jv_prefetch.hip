@@ -13,10 +13,12 @@
 //     G_z = D2_z w + D_x(D_z u) + D_y(D_z v)); the z-derivatives on the halo
 //     strips come from direct loads, one halo position per thread;
 //   * the global loads of plane k+1 (halo, halo z-taps, plane k+4) are
-//     issued before the pointwise algebra of plane k, and the base data of a
-//     point before the plane's first barrier, so about one memory latency is
-//     exposed per plane; in FP64 the kernel runs at one wave per SIMD and this
-//     memory-level parallelism is what keeps HBM busy;
+//     issued before the pointwise algebra of plane k, unconditionally and
+//     with no arithmetic on them (T' and the wall rows are formed when plane
+//     k+1 is staged), so the wave does not wait for them before the algebra;
+//     the base data of a point are loaded before the plane's first barrier;
+//     in FP64 the kernel runs at one wave per SIMD and this memory-level
+//     parallelism is what keeps HBM busy;
 //   * workgroups are numbered so that tiles adjacent in x run on the same
 //     XCD (and share its L2), which serves the halo re-reads from cache;
 //   * loads are branch-free (wall rows are clamped and masked), indices are
@@ -111,6 +113,23 @@ __global__ void __launch_bounds__(NT) jv_prefetch_kernel(OpParams op, const R* _
       for (int f = 0; f < NF; ++f) v[f] = R(0);
     }
   };
+  // The same in two halves for the loads of the next plane: the raw values
+  // (x fields, then T_p, T_s) are loaded before the algebra of this plane
+  // and combined only when the next plane is staged, so that no arithmetic
+  // on them (which would make the wave wait for them) precedes the algebra.
+  auto load_raw = [&](int p, R v[NF + 1]) {
+#pragma unroll
+    for (int f = 0; f < ND + 2; ++f) v[f] = x[f * npts + p];
+    v[ND + 2] = Tp[p];
+    v[ND + 3] = Ts[p];
+  };
+  auto finish_raw = [&](bool wall, R v[NF + 1]) {
+    v[ND + 2] = v[ND + 2] * v[0] + v[ND + 3] * v[ND + 1];
+    if (wall) {
+#pragma unroll
+      for (int f = 0; f < NF; ++f) v[f] = R(0);
+    }
+  };
 
   // own column
   const int col_own = grow(tj + 3) * nx + wrapc(i, nx);
@@ -168,10 +187,13 @@ __global__ void __launch_bounds__(NT) jv_prefetch_kernel(OpParams op, const R* _
   }
 
   // global loads of one plane: halo, halo z-taps, plane k+3 at the own column
-  R hv[NF], dzw[6], dzb[6], qn[NF], bq[NB];
+  R hv[NF + 1], dzw[6], dzb[6], qn[NF + 1], bq[NB];   // hv, qn: raw until finish_raw
   auto load_plane = [&](int k) {
-    if (has_h) load_point(k * plane + col_h, wall_h, hv);
-    if (ND == 3 && has_d) {
+    // unconditional: threads without a halo position load a valid one and
+    // drop it (a load under a divergent branch is merged by a register copy,
+    // which waits for it)
+    load_raw(k * plane + col_h, hv);
+    if (ND == 3) {
 #pragma unroll
       for (int m = 0; m < 6; ++m) {
         const int p = wrapc(k - 3 + m + (m >= 3 ? 1 : 0), nz) * plane + col_d;
@@ -179,7 +201,7 @@ __global__ void __launch_bounds__(NT) jv_prefetch_kernel(OpParams op, const R* _
         dzb[m] = x[fb * npts + p];
       }
     }
-    load_point((ND == 3 ? wrapc(k + 3, nz) * plane : 0) + col_own, wall_own, qn);
+    load_raw((ND == 3 ? wrapc(k + 3, nz) * plane : 0) + col_own, qn);
   };
   auto load_bdata = [&](int k) {
 #pragma unroll
@@ -191,6 +213,8 @@ __global__ void __launch_bounds__(NT) jv_prefetch_kernel(OpParams op, const R* _
   for (int k = kbeg; k < kend; ++k) {
     const int pown = k * plane + col_own;   // the output index for inside points
     load_bdata(k);
+    finish_raw(wall_h, hv);
+    finish_raw(wall_own, qn);
     __syncthreads();
     // ---- stage plane k: interior from the queue, halo from the loads ----
 #pragma unroll
