@@ -62,6 +62,24 @@ def measured_traffic(variant):
     return int(fields[name])
 
 
+def hbm_probe(torch, dev):
+    """Achievable HBM bandwidth of plain torch kernels on 4 GiB FP64 tensors
+    (context for the Krylov kernels' GB/s): a read-only sum, a two-read
+    one-write add, a copy."""
+    n = 512 * 1024 * 1024
+    a = torch.randn(n, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    c = torch.empty(n // 4, dtype=torch.float64, device=dev)
+    out = {}
+    for name, fn, nbytes in (("sum_read", lambda: torch.sum(a), 8 * n),
+                             ("add_2r1w", lambda: torch.add(a[: n // 4], a[n // 4: n // 2], out=c), 3 * 8 * (n // 4)),
+                             ("copy_1r1w", lambda: b.copy_(a), 2 * 8 * n)):
+        sec = timed(fn, 10, 2, torch) / 10
+        out[name] = {"ms": sec * 1e3, "TBs": nbytes / sec / 1e12}
+    del a, b, c
+    return out
+
+
 def calib_copy(torch, dev):
     """A device copy of known size, 16x the 256 MB last-level cache: reads and
     writes 4 GiB each (the reference for the rocprofv3 byte counters)."""
@@ -142,6 +160,8 @@ def main():
     ap.add_argument("--c2-solve", action="store_true",
                     help="only one Cayley system of the 3D grid to 1e-10: FP64 against the mixed form, "
                          "GMRES(30) and LGMRES(30, 3)")
+    ap.add_argument("--hbm-probe", action="store_true",
+                    help="only the achievable HBM bandwidth of plain torch sum / add / copy on 4 GiB")
     ap.add_argument("--c2-cap", type=int, default=30000,
                     help="product budget of each --c2-solve solve (a small cap for profiling)")
     ap.add_argument("--gmres-only", action="store_true",
@@ -159,6 +179,9 @@ def main():
     from paper_1502_03701_amd import Context
 
     dev = torch.device("cuda:0")
+    if args.hbm_probe:
+        print(json.dumps(hbm_probe(torch, dev)))
+        return
     if args.c0_eigs:
         print(json.dumps(eigs_c0(torch, dev, log=lambda m: print(m, file=sys.stderr, flush=True))))
         return
