@@ -49,7 +49,9 @@ constexpr int nbdata() { return 1 + ND + 1 + ND + ND * ND + ND + ND + ND + 1; }
 // A batch of systems shares one launch: system sys (from the logical z block
 // index sys * zchunks + chunk) reads x + sys*strideX, writes y + sys*strideY,
 // uses shifts[sys] (or the scalar shift) and the flag active[sys*sA].
-template <typename R, int ND, int NZC>
+// FULL: the tiles cover the grid exactly (nx, ny multiples of 16): every
+// thread owns a grid point and no branch surrounds the algebra and stores.
+template <typename R, int ND, int NZC, bool FULL>
 __global__ void __launch_bounds__(NT) jv_prefetch_kernel(OpParams op, const R* __restrict__ base,
                                                      const R* __restrict__ bdata, const R* __restrict__ x,
                                                      R* __restrict__ y, R shift, const int* __restrict__ active,
@@ -87,7 +89,7 @@ __global__ void __launch_bounds__(NT) jv_prefetch_kernel(OpParams op, const R* _
   const int i = i0 + ti, j = j0 + tj;
   const int plane = nx * ny;
   const int npts = (int)op.npts;
-  const bool inside = i < nx && j < ny;
+  const bool inside = FULL || (i < nx && j < ny);
   const bool wallbc = op.bcy == 1;
   const R ihx = R(op.ihx), ihy = R(op.ihy), ihz = R(op.ihz);
   const Axis<R> ax = axis_coefs<R>(6);
@@ -375,19 +377,21 @@ hipError_t launch_jv_prefetch(const OpParams& p, const R* base, const R* bdata, 
   const long long ntot = (long long)gx * gy * zchunks * nrhs;
   if (ntot >= (1LL << 31)) return hipErrorInvalidValue;
   dim3 grid((unsigned)ntot);
-#define SA_LAUNCH(ND_, NZ_)                                                                                      \
-  jv_prefetch_kernel<R, ND_, NZ_><<<grid, NT, 0, s>>>(p, base, bdata, x, y, shift, active, sX, sY, shifts, sA, zchunks, gx, gy, \
-                                       (int)ntot)
-  if (p.ndim == 2)
-    SA_LAUNCH(2, 16);   // one plane: the chunk depth is irrelevant
-  else if (nzc == 1)
-    SA_LAUNCH(3, 1);
-  else if (nzc == 4)
-    SA_LAUNCH(3, 4);
-  else if (nzc == 16)
-    SA_LAUNCH(3, 16);
-  else
-    SA_LAUNCH(3, 32);
+#define SA_LAUNCH(ND_, NZ_, F_)                                                                                   \
+  jv_prefetch_kernel<R, ND_, NZ_, F_><<<grid, NT, 0, s>>>(p, base, bdata, x, y, shift, active, sX, sY, shifts, sA, \
+                                                        zchunks, gx, gy, (int)ntot)
+  const bool full = p.nx % TX == 0 && p.ny % TY == 0;
+  if (p.ndim == 2) {
+    SA_LAUNCH(2, 16, false);   // one plane: the chunk depth is irrelevant
+  } else if (nzc == 1) {
+    if (full) SA_LAUNCH(3, 1, true); else SA_LAUNCH(3, 1, false);
+  } else if (nzc == 4) {
+    if (full) SA_LAUNCH(3, 4, true); else SA_LAUNCH(3, 4, false);
+  } else if (nzc == 16) {
+    if (full) SA_LAUNCH(3, 16, true); else SA_LAUNCH(3, 16, false);
+  } else {
+    if (full) SA_LAUNCH(3, 32, true); else SA_LAUNCH(3, 32, false);
+  }
 #undef SA_LAUNCH
   return hipGetLastError();
 }

@@ -67,6 +67,9 @@ VARIANT_CASES = [
     ("3d-periodic", synth.mixing_layer_3d(9, 8, 7, 0.4, 500.0, bc_y=synth.BC_PERIODIC), "random"),
     # 40 planes: a ragged last z chunk for the chunk depths 16 and 32
     ("3d-zragged", synth.mixing_layer_3d(20, 13, 40, 0.5, 800.0), "noise"),
+    # nx, ny multiples of 16: the 16 x 16 tiles cover the plane exactly (the
+    # FP64 prefetch kernels' branch-free instantiation), z ragged as above
+    ("3d-exact-tiles", synth.mixing_layer_3d(32, 16, 40, 0.5, 1000.0), "noise"),
 ]
 
 
