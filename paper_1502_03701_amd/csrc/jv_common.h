@@ -47,6 +47,18 @@ __device__ __forceinline__ Axis<R> axis_coefs(int order) {
   return a;
 }
 
+// v, or +0 where z (the wall rows' output): a bitwise mask instead of a
+// select, so that the compiler does not put the computation of v under a
+// branch on z (whose register copies would wait for pending loads)
+__device__ __forceinline__ double zero_on(bool z, double v) {
+  const long long m = (long long)z - 1;   // z: 0, else all ones
+  return __longlong_as_double(__double_as_longlong(v) & m);
+}
+__device__ __forceinline__ float zero_on(bool z, float v) {
+  const int m = (int)z - 1;
+  return __int_as_float(__float_as_int(v) & m);
+}
+
 __device__ __forceinline__ int wall_row_order(int j, int ny, int bcy) {
   if (bcy == 0) return 6;
   if (j <= 0 || j >= ny - 1) return 0;

@@ -39,17 +39,6 @@ constexpr int NYH = 6 * TX;           // y-strip positions needing D_z
 static_assert(NHALO <= NT && NXH + NYH <= NT, "one halo position per thread");
 constexpr int NXCD = 8;
 
-// v, or +0 where z: a bitwise mask instead of a select, so that the compiler
-// does not put the computation of v under a branch on z
-__device__ __forceinline__ double zero_on(bool z, double v) {
-  const long long m = (long long)z - 1;   // z: 0, else all ones
-  return __longlong_as_double(__double_as_longlong(v) & m);
-}
-__device__ __forceinline__ float zero_on(bool z, float v) {
-  const int m = (int)z - 1;
-  return __int_as_float(__float_as_int(v) & m);
-}
-
 // Periodic index of a in [-n, 2n).  Indices beyond n + 3 only feed points
 // outside the grid (tiles are padded), so they are clamped into range.
 __device__ __forceinline__ int wrapc(int a, int n) { return a < 0 ? a + n : (a >= n ? min(a - n, n - 1) : a); }

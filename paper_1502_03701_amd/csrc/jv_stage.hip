@@ -286,7 +286,7 @@ __global__ void __launch_bounds__(NT) jv_stage_kernel(OpParams op, const R* __re
       }
 #pragma unroll
       for (int f = 0; f < ND + 2; ++f)   // written once, read by another kernel: nontemporal
-        __builtin_nontemporal_store(wallrow ? R(0) : out[f] - shift * P.q[f], y + ((long long)f * npts + id));
+        __builtin_nontemporal_store(zero_on(wallrow, out[f] - shift * P.q[f]), y + ((long long)f * npts + id));
     }
     if (ND == 3) {
 #pragma unroll
