@@ -155,6 +155,8 @@ def main():
     ap.add_argument("--iram-only", action="store_true",
                     help="only the 3D 32^3 eigen solve (2 eigenpairs, LGMRES(37, 3) inner solves, FP64 and "
                          "mixed; for profiling the Arnoldi, Cayley and Ritz kernels)")
+    ap.add_argument("--eigs-64", action="store_true",
+                    help="only the 3D 64^3 eigen solve (2 eigenpairs, LGMRES(37, 3) inner solves, FP64 and mixed)")
     ap.add_argument("--sweep-mid", action="store_true",
                     help="only the sweep of 8 uneven flows on sides 64-128 (LGMRES(37, 3), concurrent)")
     ap.add_argument("--c2-solve", action="store_true",
@@ -188,6 +190,10 @@ def main():
     if args.sweep_mid:
         print(json.dumps(sweep(torch, dev, augment=3, modes=("concurrent",), sides=(64, 96, 128), tag="mid",
                                max_matvec=30000, log=lambda m: print(m, file=sys.stderr, flush=True))))
+        return
+    if args.eigs_64:
+        print(json.dumps(eigs_3d(torch, dev, side=64, max_restarts=20, augment=3,
+                                 log=lambda m: print(m, file=sys.stderr, flush=True))))
         return
     if args.iram_only:
         print(json.dumps(eigs_3d(torch, dev, augment=3, log=lambda m: print(m, file=sys.stderr, flush=True))))
