@@ -93,6 +93,10 @@ def test_jv_every_kernel_variant(ctxs, name, prob, kind, variant):
     y32 = torch.empty(2 * prob.ndof, dtype=torch.float32, device="cuda:0")
     ctx.op_apply(dev(v, torch.float32), y32, shift=0.1, nrhs=2)
     assert rel(host(y32), ref.ravel()) < 1e-5, (name, variant)
+    if prob.bc[1] == synth.BC_WALL:   # wall rows: exactly zero (+0 or -0), in both precisions
+        for out in (host(y), host(y32)):
+            w = out.reshape((2,) + prob.shape)
+            assert np.all(w[..., 0, :] == 0) and np.all(w[..., -1, :] == 0), (name, variant)
 
 
 def test_autotuner_picks_a_measured_variant(ctxs):
