@@ -192,11 +192,14 @@ int sa_op_apply(sa_ctx *ctx, sa_prec prec, int nrhs, const void *x_dev, void *y_
 /* Assemble and factor the block-Jacobi preconditioner for nshift shifts
  * (Section "Preconditioning": blocks of the operator assembled from
  * operator calls).  Block b of shift s is
- *     B_b(s) = P_b J P_b^T + diag_add I + noise_std E_b - s I,
- * E_b seeded standard-normal (Philox4x32-10), P_b the restriction to the
- * block's DOFs.  Blocks are extracted by coloured probing with the FP64
- * operator, formed in FP64 (unshifted blocks plus noise are kept in FP64 on
- * the device), rounded once to the factor precision and factored (LU with
+ *     B_b(s) = P_b J P_b^T + diag_add I + noise_std E_b - s I
+ * on the block's interior DOFs, E_b seeded standard-normal (Philox4x32-10),
+ * P_b the restriction to the block's DOFs; on its wall DOFs (which are not
+ * unknowns of P J P) the block is the identity, with no noise or shift.
+ * Blocks are extracted by coloured probing with the operator in the factor
+ * precision (FP32 operator products for SA_F32 factors, FP64 for SA_F64),
+ * formed in FP64 (unshifted blocks plus noise are kept in FP64 on the
+ * device), rounded once to the factor precision and factored (LU with
  * partial pivoting), all blocks of all shifts in one launch.  Every axis
  * must be divisible by its block size, and along a periodic axis the block
  * count must be divisible by the probe colour count 1 + ceil(3/b);

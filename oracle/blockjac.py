@@ -11,9 +11,13 @@ an nb x nb matrix, nb = nv*bx*by*bz, with local index
 and blocks are numbered b = (kb*nby + jb)*nbx + ib.
 
 For a shift s the block is
-    B_b(s) = P_b J P_b^T + diag_add I + noise_std E_b - s I,
-E_b a standard-normal matrix from the counter-based generator (seeded,
-shared by all shifts), and the preconditioner applies z = P blockdiag(B_b)^{-1} r.
+    B_b(s) = P_b J P_b^T + diag_add I + noise_std E_b - s I
+on the block's interior DOFs, E_b a standard-normal matrix from the
+counter-based generator (seeded, shared by all shifts), and the identity on
+its wall DOFs (the operator is P J P: wall values are not unknowns, so no
+noise, shift or diagonal term enters there and B_b(s)^{-1} restricted to the
+interior is the inverse of the interior part).  The preconditioner applies
+z = P blockdiag(B_b)^{-1} r.
 """
 from __future__ import annotations
 
@@ -105,11 +109,29 @@ def blocks_by_probing(prob, jv, lay):
     return B
 
 
-def shifted_blocks(B, shift, diag_add, noise_std, seed, stream=0):
-    """B_b(s) = B_b + diag_add I + noise_std E_b - s I."""
+def block_wall_mask(prob, lay):
+    """wall[b, l]: local DOF l of block b sits on a wall row.  Such DOFs are
+    not unknowns of the operator P J P (their rows and columns of B_b are
+    zero), so the shifted block keeps the identity there."""
+    idx = block_dof_index(prob, lay)
+    interior = np.tile(opr.interior_mask(prob).ravel(), prob.nv)
+    return interior[idx] == 0.0
+
+
+def shifted_blocks(B, shift, diag_add, noise_std, seed, stream=0, wall=None):
+    """B_b(s) = B_b + diag_add I + noise_std E_b - s I on the block's interior
+    DOFs, and the identity on its wall DOFs (wall = block_wall_mask(...); no
+    noise, shift or diagonal term there), so that the block's inverse
+    restricted to the interior is the inverse of its interior part."""
     nblocks, nb, _ = B.shape
     E = philox.block_noise(seed, nb, np.arange(nblocks), stream)
-    return B + noise_std * E + (diag_add - shift) * np.eye(nb)[None]
+    out = B + noise_std * E + (diag_add - shift) * np.eye(nb)[None]
+    if wall is not None:
+        w = np.asarray(wall, dtype=bool)
+        out = np.where(w[:, :, None] | w[:, None, :], 0.0, out)
+        bi, li = np.nonzero(w)
+        out[bi, li, li] = 1.0
+    return out
 
 
 def apply(prob, Bs, lay, r):

@@ -10,7 +10,10 @@
 //    entries afterwards.
 //  * Block b of shift s is B_b + diag_add I + noise_std E_b - s I with E_b
 //    seeded standard normals (Philox4x32-10 + Box-Muller, one per entry),
-//    kept in FP64; the factor kernel rounds once to the factor precision.
+//    kept in FP64, on the block's interior DOFs; its wall DOFs (not unknowns
+//    of P J P: zero rows and columns in B_b) keep the identity, with no
+//    noise or shift, so the inverse on the interior is that of the interior
+//    part.  The factor kernel rounds once to the factor precision.
 //  * One workgroup per (shift, block) factors a block in LDS by LU with
 //    partial pivoting and stores L\U plus the row permutation: FP32 blocks
 //    of order 16k by a blocked LU (one wavefront per block: 16-column panels
@@ -52,6 +55,16 @@ __device__ __forceinline__ long long block_dof(const BLayout& L, long long b, in
   const int i = ib * L.bx + cx, j = jb * L.by + cy, k = kb * L.bz + cz;
   wall = L.bcy == 1 && (j == 0 || j == L.ny - 1);
   return (((long long)var * L.nz + k) * L.ny + j) * L.nx + i;
+}
+
+// whether local DOF l of block b lies on a wall row (not an unknown of the
+// operator P J P: its row and column of the block are zero, and the shifted
+// block keeps the identity there)
+__device__ __forceinline__ bool local_wall(const BLayout& L, long long b, int l) {
+  const int jb = (int)((b / L.nbx) % L.nby);
+  const int cy = ((l % L.cells) / L.bx) % L.by;
+  const int j = jb * L.by + cy;
+  return L.bcy == 1 && (j == 0 || j == L.ny - 1);
 }
 
 // The blocks of one probe colour: block (ib, jb, kb) has colour
@@ -147,6 +160,7 @@ __device__ __forceinline__ double noise_entry(unsigned long long seed, long long
 }
 
 // B[b] += noise_std * E_b   (E_b[r][c] at column-major position c*nb + r)
+// on the rows and columns of interior DOFs
 __global__ void add_noise_kernel(BLayout L, double* __restrict__ B, double noise_std, unsigned long long seed) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long per = (long long)L.nb * L.nb;
@@ -154,6 +168,7 @@ __global__ void add_noise_kernel(BLayout L, double* __restrict__ B, double noise
   const long long b = t / per;
   const int e = (int)(t % per);
   const int col = e / L.nb, row = e % L.nb;
+  if (local_wall(L, b, row) || local_wall(L, b, col)) return;
   B[t] += noise_std * noise_entry(seed, b, row * L.nb + col);
 }
 
@@ -203,7 +218,10 @@ __global__ void __launch_bounds__(256) lu_kernel(BLayout L, const double* __rest
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
       const int t = t0 + tid + 256 * q;
-      if (t < nb * nb) A[t] = (F)(t / nb == t % nb ? v[q] + dshift : v[q]);
+      if (t < nb * nb) {
+        const bool diag = t / nb == t % nb;
+        A[t] = (F)(diag ? (local_wall(L, b, t % nb) ? 1.0 : v[q] + dshift) : v[q]);
+      }
     }
   }
   for (int t = tid; t < nb; t += blockDim.x) s_perm[t] = t;
@@ -312,7 +330,10 @@ __global__ void __launch_bounds__(64) lu_mfma_kernel(BLayout L, const double* __
 #pragma unroll
     for (int q = 0; q < 20; ++q) {
       const int t = t0 + lane + 64 * q;
-      if (t < nb * nb) A[(t / nb) * ld + t % nb] = (float)(t / nb == t % nb ? v[q] + dshift : v[q]);
+      if (t < nb * nb) {
+        const bool diag = t / nb == t % nb;
+        A[(t / nb) * ld + t % nb] = (float)(diag ? (local_wall(L, b, t % nb) ? 1.0 : v[q] + dshift) : v[q]);
+      }
     }
   }
   for (int t = lane; t < nb; t += 64) s_perm[t] = t;

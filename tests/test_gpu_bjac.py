@@ -19,7 +19,8 @@ def oracle_blocks(prob, q0, bx, by, bz, shifts, diag_add, noise_std, seed):
     lay = bj.block_layout(prob, bx, by, bz)
     Jfull = op.dense_jacobian(prob, q0, interior_only=False)
     B = bj.blocks_from_dense(prob, Jfull, lay)
-    return lay, [bj.shifted_blocks(B, s, diag_add, noise_std, seed) for s in shifts]
+    wall = bj.block_wall_mask(prob, lay)
+    return lay, [bj.shifted_blocks(B, s, diag_add, noise_std, seed, wall=wall) for s in shifts]
 
 
 CASES = [
@@ -39,7 +40,8 @@ CASES = [
 def test_block_apply_parity(name, prob, blk, fprec):
     need_gpu()
     from paper_1502_03701_amd import SA_F32, SA_F64, Context
-    shifts = [0.05, 0.2, 0.35]
+    # 0.1 == diag_add: the interior part of a wall block is then unshifted
+    shifts = [0.05, 0.1, 0.35]
     q0 = synth.random_base(prob, 41)
     lay, Bs = oracle_blocks(prob, q0, *blk, shifts, 0.1, 0.01, 3)
     ctx = Context()
@@ -57,6 +59,43 @@ def test_block_apply_parity(name, prob, blk, fprec):
         z32 = torch.empty(prob.ndof, dtype=torch.float32, device="cuda:0")
         ctx.precond_apply(s, dev(r, torch.float32), z32)
         assert rel(host(z32), ref) < max(tol, 8 * lay["nb"] * 2.0 ** -24 * cond)
+
+
+@pytest.mark.parametrize("fprec", ["f64", "f32"])
+def test_wall_blocks_invert_their_interior_part(fprec):
+    """At shift == diag_add and without noise, each block's interior part is
+    the interior submatrix of the dense Jacobian: the preconditioner must
+    apply exactly its inverse on the interior DOFs of wall blocks (the wall
+    DOFs, not unknowns of P J P, stay an identity and add no Schur term)."""
+    need_gpu()
+    from paper_1502_03701_amd import SA_F32, SA_F64, Context
+    prob = synth.mixing_layer_2d(16, 16, 0.3, 500.0)
+    q0 = synth.random_base(prob, 45)
+    lay = bj.block_layout(prob, 4, 4, 1)
+    Jfull = op.dense_jacobian(prob, q0, interior_only=False)
+    idx = bj.block_dof_index(prob, lay)
+    wall = bj.block_wall_mask(prob, lay)
+    ctx = Context()
+    ctx.base_set(prob, dev(q0))
+    ctx.precond_setup([0.1], 4, 4, 1, diag_add=0.1, noise_std=0.0,
+                      factor_prec=SA_F64 if fprec == "f64" else SA_F32)
+    r = synth.random_vector(prob, 46)
+    z = torch.empty(prob.ndof, dtype=torch.float64, device="cuda:0")
+    ctx.precond_apply(0, dev(r), z)
+    zh = host(z)
+    nwall = 0
+    for b in range(lay["nblocks"]):
+        if not wall[b].any():
+            continue
+        nwall += 1
+        inn = ~wall[b]
+        Bi = Jfull[np.ix_(idx[b][inn], idx[b][inn])]
+        ref = np.linalg.solve(Bi, r.ravel()[idx[b][inn]])
+        cond = np.linalg.cond(Bi)
+        tol = 1e-12 * cond if fprec == "f64" else 8 * lay["nb"] * 2.0 ** -24 * cond
+        assert rel(zh[idx[b][inn]], ref) < tol, (b, cond)
+        assert np.all(zh[idx[b][wall[b]]] == 0)
+    assert nwall == 2 * lay["nbx"]
 
 
 def test_preconditioned_gmres_converges():
@@ -90,7 +129,12 @@ def test_singular_block_and_errors():
     with pytest.raises(SAError) as e:
         ctx.precond_apply(0, r, torch.zeros_like(r))
     assert e.value.code == n.SA_ESTATE
-    # wall DOFs have zero rows; diag_add = shift and no noise leaves them singular
+    # a fluid at rest without viscosity: the entropy rows of J vanish, so
+    # diag_add = shift without noise leaves every block exactly singular
+    rest = synth.mixing_layer_2d(16, 16, 0.3, 0.0)
+    q_rest = synth.base_flow(rest)
+    q_rest[1] = 0.0
+    ctx.base_set(rest, dev(q_rest))
     with pytest.raises(SAError) as e:
         ctx.precond_setup([0.2], 4, 4, 1, diag_add=0.2, noise_std=0.0, factor_prec=SA_F64)
     assert e.value.code == n.SA_ESINGULAR
@@ -147,6 +191,10 @@ def test_full_size_3d_sampled_blocks():
         wall = (4 * jb + cy == 0) | (4 * jb + cy == ny - 1)
         for s in (0, 7):
             Bs = B + 0.01 * E + (0.1 - shifts[s]) * np.eye(80)
+            # wall DOFs: identity rows and columns (not unknowns of P J P)
+            Bs[wall, :] = 0.0
+            Bs[:, wall] = 0.0
+            Bs[wall, wall] = 1.0
             ref = np.linalg.solve(Bs, r.ravel()[gflat])
             ref[wall] = 0.0
             got = Z[s].ravel()[gflat]

@@ -233,21 +233,41 @@ def test_block_apply_inverts_block_diagonal():
     lay = bj.block_layout(prob, 4, 4)
     Jfull = op.dense_jacobian(prob, q0, interior_only=False)
     B = bj.blocks_from_dense(prob, Jfull, lay)
-    Bs = bj.shifted_blocks(B, 0.15, 0.1, 0.01, seed=3)
+    wall = bj.block_wall_mask(prob, lay)
+    Bs = bj.shifted_blocks(B, 0.15, 0.1, 0.01, seed=3, wall=wall)
     r = synth.random_vector(prob, 1)
     z = bj.apply(prob, Bs, lay, r)
     idx = bj.block_dof_index(prob, lay)
-    # B_b z_b = r_b on the interior entries of every block
     zb = z.ravel()[idx]
     rb = r.ravel()[idx]
-    Bz = np.einsum("bij,bj->bi", Bs, zb)
-    interior = op.interior_mask(prob)
-    mask = np.tile(interior.ravel(), prob.nv)[idx].astype(bool)
-    # wall entries of z are projected out; compare after re-solving with them
-    zfull = np.linalg.solve(Bs, rb[..., None])[..., 0]
-    np.testing.assert_allclose(np.einsum("bij,bj->bi", Bs, zfull), rb, atol=1e-10)
-    np.testing.assert_allclose(zb[mask], zfull[mask], atol=0)
+    # B_b z_b = r_b for every block (wall entries of r are 0, so are those of z)
+    np.testing.assert_allclose(np.einsum("bij,bj->bi", Bs, zb), rb, atol=1e-10)
     assert np.all(z.reshape(prob.shape)[:, 0, :] == 0)
+
+
+def test_wall_dofs_are_identity_in_blocks():
+    # at shift == diag_add and without noise, a wall block's interior part is
+    # exactly P_b J P_b^T on the interior DOFs: the preconditioner must apply
+    # its inverse there (no Schur complement from the wall DOFs)
+    prob = synth.mixing_layer_2d(8, 8, 0.3, 500.0)
+    q0 = synth.random_base(prob, 11)
+    lay = bj.block_layout(prob, 4, 4)
+    Jfull = op.dense_jacobian(prob, q0, interior_only=False)
+    B = bj.blocks_from_dense(prob, Jfull, lay)
+    wall = bj.block_wall_mask(prob, lay)
+    assert wall.any() and not wall.all()
+    Bs = bj.shifted_blocks(B, 0.1, 0.1, 0.0, seed=3, wall=wall)
+    r = synth.random_vector(prob, 2)
+    z = bj.apply(prob, Bs, lay, r)
+    idx = bj.block_dof_index(prob, lay)
+    for b in range(lay["nblocks"]):
+        inn = ~wall[b]
+        Bi = Jfull[np.ix_(idx[b][inn], idx[b][inn])]
+        np.testing.assert_allclose(z.ravel()[idx[b][inn]], np.linalg.solve(Bi, r.ravel()[idx[b][inn]]),
+                                   rtol=1e-10, atol=1e-12)
+        # the wall DOFs of the shifted block form an identity block
+        assert np.array_equal(Bs[b][np.ix_(wall[b], wall[b])], np.eye(wall[b].sum()))
+        assert not Bs[b][np.ix_(wall[b], inn)].any() and not Bs[b][np.ix_(inn, wall[b])].any()
 
 
 def test_philox_known_answers():
