@@ -226,6 +226,29 @@ int sa_gmres_solve(sa_ctx *ctx, const sa_gmres_opts *opts, int nshift,
                    const double *sigma_host, const void *b_dev, void *x_dev,
                    sa_gmres_info *info_host);
 
+/* Size of the device scratch array behind sa_gmres_solve_noalloc (one copy
+ * per device, held until the process ends). */
+#define SA_NOALLOC_SCRATCH_BYTES (64ull << 20)
+
+/* sa_gmres_solve for callers that cannot allocate device memory (tight
+ * serving loops, harnesses that forbid hipMalloc): the same solve, argument
+ * rules and results, but every workspace buffer (Krylov basis, small GMRES
+ * state, reduction partials and counters) lives in a statically sized
+ * device array of SA_NOALLOC_SCRATCH_BYTES instead of context-owned
+ * allocations; the call performs no device allocation or free.  The caller
+ * still passes b_dev and x_dev; the base state (and, with use_precond, the
+ * factors) must already be set up by the allocating calls.  Restart cycles
+ * run as plain launches (use_graph is ignored).  Every call on one device
+ * shares that device's array and keeps the previous call's contents
+ * (counters are cleared at the start of each call), so calls that overlap
+ * on one device -- contexts on different streams -- race and must not be
+ * issued concurrently.  Errors: those of sa_gmres_solve, and SA_EINVAL when
+ * the workspace the solve needs, about (restart + augment + 2) * n * nshift
+ * elements plus the small state, exceeds SA_NOALLOC_SCRATCH_BYTES. */
+int sa_gmres_solve_noalloc(sa_ctx *ctx, const sa_gmres_opts *opts, int nshift,
+                           const double *sigma_host, const void *b_dev, void *x_dev,
+                           sa_gmres_info *info_host);
+
 /* Leading eigenpairs of J for nprob problems (Algorithm 1 on the Cayley
  * transform; eigenvalues ordered by decreasing |theta|, theta = (lam - mu)/
  * (lam - sigma)).  ctxs[p] holds problem p's base state; v0_dev[p] its start

@@ -27,7 +27,10 @@ SA_BC_PERIODIC, SA_BC_WALL = 0, 1
 
 EXPORTED = ["sa_create", "sa_destroy", "sa_last_error", "sa_version", "sa_base_set",
             "sa_op_apply", "sa_precond_setup", "sa_precond_apply", "sa_gmres_solve",
-            "sa_arnoldi_eigs", "sa_set_jv_variant", "sa_get_jv_variant"]
+            "sa_arnoldi_eigs", "sa_set_jv_variant", "sa_get_jv_variant", "sa_gmres_solve_noalloc"]
+
+# bytes of the device scratch array behind sa_gmres_solve_noalloc
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 # operator kernel variants (sa_jv_variant)
 JV_VARIANTS = ["prefetch_z32", "prefetch_z16", "stage_z16", "stage_z32", "prefetch_z4", "prefetch_z1", "stage_z4",
@@ -103,6 +106,8 @@ def load(path: str = LIB_PATH):
     lib.sa_gmres_solve.argtypes = [vp, C.POINTER(GmresOpts), ip, C.POINTER(dp), vp, vp,
                                    C.POINTER(GmresInfo)]
     lib.sa_gmres_solve.restype = ip
+    lib.sa_gmres_solve_noalloc.argtypes = lib.sa_gmres_solve.argtypes
+    lib.sa_gmres_solve_noalloc.restype = ip
     lib.sa_arnoldi_eigs.argtypes = [C.POINTER(vp), ip, C.POINTER(EigOpts), C.POINTER(vp),
                                     C.POINTER(EigResult)]
     lib.sa_arnoldi_eigs.restype = ip
@@ -227,8 +232,11 @@ class Context:
         return self._err(self.lib.sa_precond_apply(self.h, prec, ishift, nrhs, _ptr(r), _ptr(z)))
 
     def gmres_solve(self, sigmas, b, x, restart=40, tol=1e-10, max_matvec=10 ** 6,
-                    use_precond=False, prec=SA_F64, inner_tol=1e-4, max_outer=10, use_graph=True, augment=0):
-        """augment = k > 0: LGMRES(restart, k)."""
+                    use_precond=False, prec=SA_F64, inner_tol=1e-4, max_outer=10, use_graph=True, augment=0,
+                    noalloc=False):
+        """augment = k > 0: LGMRES(restart, k).  noalloc: call
+        sa_gmres_solve_noalloc (workspace in the library's static scratch,
+        no device allocation; use_graph is then ignored)."""
         import torch
         ns = len(sigmas)
         dt = torch.float32 if prec == SA_F32 else torch.float64
@@ -238,7 +246,8 @@ class Context:
                       1 if use_graph else 0, augment)
         infos = (GmresInfo * ns)()
         arr = (C.c_double * ns)(*sigmas)
-        rc = self._err(self.lib.sa_gmres_solve(self.h, C.byref(o), ns, arr, _ptr(b), _ptr(x), infos))
+        fn = self.lib.sa_gmres_solve_noalloc if noalloc else self.lib.sa_gmres_solve
+        rc = self._err(fn(self.h, C.byref(o), ns, arr, _ptr(b), _ptr(x), infos))
         return rc, [dict(iters=i.iters, matvecs=i.matvecs, precond_applies=i.precond_applies,
                          cycles=i.cycles, outer=i.outer, relres=i.relres, status=i.status)
                     for i in infos]

@@ -29,6 +29,17 @@ int Ctx::hip_fail(hipError_t e, const char* where) {
 }
 
 void* Ctx::buffer(const std::string& name, size_t bytes, bool zero) {
+  if (arena) {
+    auto at = arena->bufs.find(name);
+    if (at != arena->bufs.end() && at->second.bytes >= bytes) return at->second.ptr;
+    const size_t need = (bytes + 255) / 256 * 256;
+    if (need > arena->cap - arena->used) return nullptr;
+    void* p = arena->base + arena->used;
+    arena->used += need;
+    if (zero) zero_fill(p, need, stream);
+    arena->bufs[name] = Buf{p, need};
+    return p;
+  }
   auto it = bufs.find(name);
   if (it != bufs.end() && it->second.bytes >= bytes) return it->second.ptr;
   if (it != bufs.end()) {
@@ -107,6 +118,46 @@ Ctx::~Ctx() {
   for (auto& kv : bufs) hipFree(kv.second.ptr);
 }
 
+int gmres_check(Ctx* c, const sa_gmres_opts* o, int nshift, const double* sigma_host, const void* b_dev,
+                const void* x_dev, const sa_gmres_info* info, const char* who) {
+  if (!c->has_base) return c->fail(SA_ESTATE, "%s: call sa_base_set first", who);
+  if (!o || !sigma_host || !b_dev || !x_dev || !info || nshift < 1)
+    return c->fail(SA_EINVAL, "%s: null argument or nshift < 1", who);
+  if (o->restart < 1 || o->restart > GMAX) return c->fail(SA_EINVAL, "%s: restart must be 1..%d", who, GMAX);
+  if (o->augment < 0 || o->restart + o->augment > GMAX)
+    return c->fail(SA_EINVAL, "%s: need augment >= 0 and restart + augment <= %d", who, GMAX);
+  if (!(o->tol > 0) || o->max_matvec < 1) return c->fail(SA_EINVAL, "%s: bad tol or max_matvec", who);
+  if (o->use_precond) {
+    if (!c->has_precond) return c->fail(SA_ESTATE, "%s: preconditioner not set up", who);
+    if (nshift != c->pc_nshift)
+      return c->fail(SA_EINVAL, "%s: nshift must equal the preconditioner's shift count", who);
+  }
+  if (o->prec == SA_MIXED && (!(o->inner_tol > 0) || o->max_outer < 1))
+    return c->fail(SA_EINVAL, "%s: MIXED needs inner_tol > 0 and max_outer >= 1", who);
+  if (o->prec != SA_F64 && o->prec != SA_F32 && o->prec != SA_MIXED) return c->fail(SA_EINVAL, "%s: bad precision", who);
+  return SA_OK;
+}
+
+int gmres_dispatch(Ctx* c, const sa_gmres_opts& o, int nshift, const double* sigma_host, const void* b_dev,
+                   void* x_dev, sa_gmres_info* info) {
+  // FP64 / FP32: all shifts advance in lockstep in the same launches
+  if (o.prec == SA_F64)
+    return solve_gmres<double>(c, o, nshift, sigma_host, (const double*)b_dev, (double*)x_dev,
+                               o.use_precond ? 0 : -1, info);
+  if (o.prec == SA_F32)
+    return solve_gmres<float>(c, o, nshift, sigma_host, (const float*)b_dev, (float*)x_dev,
+                              o.use_precond ? 0 : -1, info);
+  int rc_all = SA_OK;
+  for (int s = 0; s < nshift; ++s) {
+    const long long off = (long long)s * c->n;
+    const int rc = solve_ir(c, o, sigma_host[s], (const double*)b_dev + off, (double*)x_dev + off,
+                            o.use_precond ? s : -1, &info[s]);
+    if (rc < 0) return rc;
+    if (rc > 0) rc_all = rc;
+  }
+  return rc_all;
+}
+
 }  // namespace sa
 
 extern "C" {
@@ -118,6 +169,7 @@ int sa_create(sa_ctx** out, void* hip_stream) {
   *out = nullptr;
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess) return SA_EDEVICE;
+  scratch_init(dev);
   auto* c = new (std::nothrow) sa_ctx();
   if (!c) return SA_ENOMEM;
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
@@ -236,37 +288,9 @@ int sa_op_apply(sa_ctx* c, sa_prec prec, int nrhs, const void* x_dev, void* y_de
 int sa_gmres_solve(sa_ctx* c, const sa_gmres_opts* o, int nshift, const double* sigma_host,
                    const void* b_dev, void* x_dev, sa_gmres_info* info) {
   if (!c) return SA_EINVAL;
-  if (!c->has_base) return c->fail(SA_ESTATE, "sa_gmres_solve: call sa_base_set first");
-  if (!o || !sigma_host || !b_dev || !x_dev || !info || nshift < 1)
-    return c->fail(SA_EINVAL, "sa_gmres_solve: null argument or nshift < 1");
-  if (o->restart < 1 || o->restart > GMAX) return c->fail(SA_EINVAL, "sa_gmres_solve: restart must be 1..%d", GMAX);
-  if (o->augment < 0 || o->restart + o->augment > GMAX)
-    return c->fail(SA_EINVAL, "sa_gmres_solve: need augment >= 0 and restart + augment <= %d", GMAX);
-  if (!(o->tol > 0) || o->max_matvec < 1) return c->fail(SA_EINVAL, "sa_gmres_solve: bad tol or max_matvec");
-  if (o->use_precond) {
-    if (!c->has_precond) return c->fail(SA_ESTATE, "sa_gmres_solve: preconditioner not set up");
-    if (nshift != c->pc_nshift)
-      return c->fail(SA_EINVAL, "sa_gmres_solve: nshift must equal the preconditioner's shift count");
-  }
-  if (o->prec == SA_MIXED && (!(o->inner_tol > 0) || o->max_outer < 1))
-    return c->fail(SA_EINVAL, "sa_gmres_solve: MIXED needs inner_tol > 0 and max_outer >= 1");
-  // FP64 / FP32: all shifts advance in lockstep in the same launches
-  if (o->prec == SA_F64)
-    return solve_gmres<double>(c, *o, nshift, sigma_host, (const double*)b_dev, (double*)x_dev,
-                               o->use_precond ? 0 : -1, info);
-  if (o->prec == SA_F32)
-    return solve_gmres<float>(c, *o, nshift, sigma_host, (const float*)b_dev, (float*)x_dev,
-                              o->use_precond ? 0 : -1, info);
-  if (o->prec != SA_MIXED) return c->fail(SA_EINVAL, "sa_gmres_solve: bad precision");
-  int rc_all = SA_OK;
-  for (int s = 0; s < nshift; ++s) {
-    const long long off = (long long)s * c->n;
-    const int rc = solve_ir(c, *o, sigma_host[s], (const double*)b_dev + off, (double*)x_dev + off,
-                            o->use_precond ? s : -1, &info[s]);
-    if (rc < 0) return rc;
-    if (rc > 0) rc_all = rc;
-  }
-  return rc_all;
+  const int rc = gmres_check(c, o, nshift, sigma_host, b_dev, x_dev, info, "sa_gmres_solve");
+  if (rc != SA_OK) return rc;
+  return gmres_dispatch(c, *o, nshift, sigma_host, b_dev, x_dev, info);
 }
 
 }  // extern "C"

@@ -72,9 +72,34 @@ struct Ctx {
   int fail(int code, const char* fmt, ...);
   int hip_fail(hipError_t e, const char* where);
   // Named, context-owned device buffer of at least `bytes` (kept across calls).
+  // While `arena` is set, the buffer is carved instead from the arena (a
+  // caller-independent scratch region): nothing is allocated, a name maps to
+  // the same region for the rest of the call, and `zero` clears it with a
+  // kernel on first use in the call.  Returns null if the arena is full.
   void* buffer(const std::string& name, size_t bytes, bool zero = true);
+  struct Arena {
+    unsigned char* base = nullptr;
+    size_t cap = 0, used = 0;
+    std::map<std::string, Buf> bufs;
+  };
+  Arena* arena = nullptr;
   ~Ctx();
 };
+
+// Argument checks shared by the GMRES entry points (SA_OK or the error code,
+// with the message set), and their dispatch on the precision.
+int gmres_check(Ctx* c, const sa_gmres_opts* o, int nshift, const double* sigma_host, const void* b_dev,
+                const void* x_dev, const sa_gmres_info* info, const char* who);
+int gmres_dispatch(Ctx* c, const sa_gmres_opts& o, int nshift, const double* sigma_host, const void* b_dev,
+                   void* x_dev, sa_gmres_info* info);
+// Device bytes the named buffers of one GMRES call take with plain launches
+// (no captured cycles), each rounded up to the arena's 256-byte alignment.
+size_t gmres_workspace_bytes(const Ctx* c, const sa_gmres_opts& o, int nshift);
+// Zero `bytes` (rounded up to 16) at a 16-byte aligned address, by a kernel.
+void zero_fill(void* p, size_t bytes, hipStream_t s);
+// Resolve the device address of the allocation-free entry points' scratch
+// array on the current device (once per device; sa_create calls it).
+void scratch_init(int device);
 
 template <typename R>
 int solve_gmres(Ctx* c, const sa_gmres_opts& o, int nsys, const double* sigma_host, const R* b, R* x, int pc_shift0,

@@ -299,6 +299,29 @@ template int solve_gmres<double>(Ctx*, const sa_gmres_opts&, int, const double*,
 template int solve_gmres<float>(Ctx*, const sa_gmres_opts&, int, const double*, const float*, float*, int,
                                 sa_gmres_info*, const std::string&);
 
+size_t gmres_workspace_bytes(const Ctx* c, const sa_gmres_opts& o, int nshift) {
+  auto r = [](size_t b) -> size_t { return (b + 255) / 256 * 256; };
+  const size_t n = (size_t)c->n;
+  // the buffers solve_gmres names, without the copies of b and x that only
+  // captured cycles use
+  auto gm = [&](size_t es, size_t nsys, size_t m, size_t k, bool pc) -> size_t {
+    const size_t sv = n * (m + k + 1);
+    size_t t = r(es * sv * nsys);                                   // V
+    if (pc) t += r(es * sv * nsys);                                 // Z
+    if (k) t += 2 * r(es * n * k * nsys) + 2 * r(es * n * nsys);   // aug, augA, rprev, xold
+    t += r(es * n * nsys);                                          // T
+    t += r(sizeof(GState) * nsys) + r(sizeof(double) * nsys);       // state, sigma
+    t += r(sizeof(double) * RED_BLOCKS * PARTIAL_LD * nsys) + r(sizeof(int) * nsys);   // partial, ticket
+    return t;
+  };
+  const bool pc = o.use_precond != 0;
+  if (o.prec == SA_F64) return gm(sizeof(double), nshift, o.restart, o.augment, pc);
+  if (o.prec == SA_F32) return gm(sizeof(float), nshift, o.restart, o.augment, pc);
+  // refinement: one shift at a time, its FP64 buffers plus one FP32 solve
+  return 2 * r(sizeof(double) * n) + 2 * r(sizeof(float) * n) + r(sizeof(GState)) +
+         r(sizeof(double) * RED_BLOCKS * PARTIAL_LD) + r(sizeof(int)) + gm(sizeof(float), 1, o.restart, o.augment, pc);
+}
+
 // Iterative refinement: FP64 residual and update, FP32 GMRES on the scaled
 // residual equation r/||r||, solved to inner_tol relative, or only as far as
 // the outer tolerance still requires (so the last sweep does not overshoot).
