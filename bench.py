@@ -62,6 +62,13 @@ def measured_traffic(variant):
     return int(fields[name])
 
 
+def kernel_name(variant, real="double"):
+    """The HIP kernel behind an operator variant name (e.g. 'iso_z32')."""
+    kind = variant.split("_z")[0]
+    return {"prefetch": "jv_prefetch_kernel", "stage": "jv_stage_kernel",
+            "iso": "jv_iso_kernel"}.get(kind, "jv_prefetch_kernel") + "<%s,3>" % real
+
+
 def hbm_probe(torch, dev):
     """Achievable HBM bandwidth of plain torch kernels on 4 GiB FP64 tensors
     (context for the Krylov kernels' GB/s): a read-only sum, a two-read
@@ -264,8 +271,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(tuned["f64"]["variant"]),
-                     "kernel": "jv_prefetch_kernel<double,3>" if tuned["f64"]["variant"].startswith("prefetch")
-                     else "jv_stage_kernel<double,3>", "alg_bytes_per_point": 3 * nv * 8},
+                     "kernel": kernel_name(tuned["f64"]["variant"]), "alg_bytes_per_point": 3 * nv * 8},
         "fp32_jv": {"gpts": npts / per32 / 1e9, "ms": per32 * 1e3,
                     "achieved_GBs": 3 * nv * 4 * npts / per32 / 1e9},
         "autotuned_jv": tuned,

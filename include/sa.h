@@ -146,8 +146,13 @@ const char *sa_version(void);
  * the next plane's loads in flight during the pointwise algebra) and a
  * plane-staging one (32 x 8 tiles, two waves per SIMD in FP32), each
  * marching over 32, 16, 4 or 1 z planes per workgroup (the shallow ones give
- * small 3D grids enough workgroups; in 2D the depth is irrelevant).  All give
- * the same product to rounding. */
+ * small 3D grids enough workgroups; in 2D the depth is irrelevant); and the
+ * prefetching organisation specialised to base states whose pressure and
+ * entropy are the same at every grid point (uniform thermodynamic state,
+ * arbitrary velocity; sa_base_set detects this exactly): it reads only the
+ * base-velocity data, and of those only the fields that vary in x or z
+ * stream from memory.  On other base states the iso variants run the
+ * precision's default kernel.  All give the same product to rounding. */
 typedef enum {
   SA_JV_PREFETCH_Z32 = 0,
   SA_JV_PREFETCH_Z16 = 1,
@@ -157,7 +162,11 @@ typedef enum {
   SA_JV_PREFETCH_Z1 = 5,
   SA_JV_STAGE_Z4 = 6,
   SA_JV_STAGE_Z1 = 7,
-  SA_JV_NVARIANTS = 8
+  SA_JV_ISO_Z32 = 8,
+  SA_JV_ISO_Z16 = 9,
+  SA_JV_ISO_Z4 = 10,
+  SA_JV_ISO_Z1 = 11,
+  SA_JV_NVARIANTS = 12
 } sa_jv_variant;
 
 /* Set the base state q0 (eq. model_stabiity: J is linearised about q0).

@@ -34,7 +34,7 @@ NOALLOC_SCRATCH_BYTES = 64 << 20
 
 # operator kernel variants (sa_jv_variant)
 JV_VARIANTS = ["prefetch_z32", "prefetch_z16", "stage_z16", "stage_z32", "prefetch_z4", "prefetch_z1", "stage_z4",
-               "stage_z1"]
+               "stage_z1", "iso_z32", "iso_z16", "iso_z4", "iso_z1"]
 
 
 class Problem(C.Structure):

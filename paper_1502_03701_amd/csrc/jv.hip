@@ -212,7 +212,48 @@ __global__ void base_derive_kernel(OpParams op, double* __restrict__ base, float
   if (bad) atomicOr(flag, 1);
 }
 
+// Exact classification of the base state (see launch_iso_classify).
+struct IsoIdx {
+  int q[ISO_MAXF];
+};
+__global__ void iso_classify_kernel(OpParams op, const double* __restrict__ base, const double* __restrict__ bdata,
+                                    IsoIdx fi, int nf, int* __restrict__ flags) {
+  __shared__ int sf[3];
+  if (threadIdx.x < 3) sf[threadIdx.x] = 0;
+  __syncthreads();
+  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id < op.npts) {
+    const int nv = op.ndim + 2;
+    int nonuni = 0, nz = 0, var = 0;
+    if (base[id] != base[0] || base[(long long)(nv - 1) * op.npts + id] != base[(long long)(nv - 1) * op.npts])
+      nonuni = 1;
+    const int j = (int)((id / op.nx) % op.ny);
+    for (int q = 0; q < nf; ++q) {
+      const double* f = bdata + (long long)fi.q[q] * op.npts;
+      const double v = f[id];
+      if (v != 0.0) nz |= 1 << q;
+      if (v != f[(long long)j * op.nx]) var |= 1 << q;
+    }
+    if (nonuni) atomicOr(&sf[0], 1);
+    if (nz) atomicOr(&sf[1], nz);
+    if (var) atomicOr(&sf[2], var);
+  }
+  __syncthreads();
+  if (threadIdx.x < 3 && sf[threadIdx.x]) atomicOr(&flags[threadIdx.x], sf[threadIdx.x]);
+}
+
 }  // namespace
+
+hipError_t launch_iso_classify(const OpParams& p, const double* base, const double* bdata, const int* fidx, int nf,
+                               int* flags, hipStream_t s) {
+  if (nf > ISO_MAXF) return hipErrorInvalidValue;
+  IsoIdx fi{};
+  for (int q = 0; q < nf; ++q) fi.q[q] = fidx[q];
+  const int threads = 256;
+  const long long blocks = (p.npts + threads - 1) / threads;
+  iso_classify_kernel<<<dim3((unsigned)blocks), dim3(threads), 0, s>>>(p, base, bdata, fi, nf, flags);
+  return hipGetLastError();
+}
 
 template <typename R>
 hipError_t launch_jv_direct(const OpParams& p, const R* base, const R* x, R* y, int nrhs, R shift,
@@ -273,9 +314,14 @@ hipError_t launch_jv_pert(const OpParams& p, const R* base, const R* bdata, cons
   if (k == 5) variant = 2;
   if (variant < 0 || variant >= JV_NVARIANTS) variant = sizeof(R) == 8 ? 0 : 2;
   // kernel (0 prefetch, 1 stage) and z planes per workgroup of each variant
-  static constexpr int kind[JV_NVARIANTS] = {0, 0, 1, 1, 0, 0, 1, 1};
-  static constexpr int depth[JV_NVARIANTS] = {32, 16, 16, 32, 4, 1, 4, 1};
+  // an iso variant on a base state outside that class: the default kernel
+  const IsoBase<R>* ib = static_cast<const IsoBase<R>*>(p.iso[sizeof(R) == 8 ? 0 : 1]);
+  if (jv_variant_is_iso(variant) && !ib) variant = sizeof(R) == 8 ? 0 : 2;
+  static constexpr int kind[JV_NVARIANTS] = {0, 0, 1, 1, 0, 0, 1, 1, 2, 2, 2, 2};
+  static constexpr int depth[JV_NVARIANTS] = {32, 16, 16, 32, 4, 1, 4, 1, 32, 16, 4, 1};
   const int nzc = depth[variant];
+  if (kind[variant] == 2)
+    return launch_jv_iso<R>(p, *ib, x, y, nrhs, shift, active, s, sX, sY, shifts, sA, nzc);
   if (kind[variant] == 0)
     return launch_jv_prefetch<R>(p, base, bdata, x, y, nrhs, shift, active, s, sX, sY, shifts, sA, nzc);
   return launch_jv_stage<R>(p, base, bdata, x, y, nrhs, shift, active, s, sX, sY, shifts, sA, nzc);

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <type_traits>
 
 using namespace sa;
 
@@ -62,6 +63,72 @@ void Ctx::drop_graphs() {
   graphs.clear();
 }
 
+// Detect a base state of uniform thermodynamic state (p0 and s0 equal at
+// every point, compared exactly) and classify the base-data fields the iso
+// kernels read; fill the context's IsoBase records and op.iso.
+static int setup_iso(Ctx* c) {
+  OpParams& op = c->op;
+  op.iso[0] = op.iso[1] = nullptr;
+  c->iso = false;
+  const int nd = op.ndim, nv = c->nv;
+  const int nf = iso_fields(nd);
+  int fidx[ISO_MAXF];
+  for (int i = 0; i < nd; ++i) fidx[i] = 1 + i;                                   // u0_i
+  for (int i = 0; i < nd; ++i)
+    for (int a = 0; a < nd; ++a) fidx[nd + i * nd + a] = 2 + 2 * nd + i * nd + a;   // D_a u0_i
+  for (int i = 0; i < nd; ++i) fidx[nd + nd * nd + i] = 2 + 4 * nd + nd * nd + i;   // L u0_i + G0_i/3
+  int* flags = (int*)c->buffer("iso_flags", 3 * sizeof(int), false);
+  if (!flags) return c->fail(SA_ENOMEM, "sa_base_set: out of device memory");
+  hipError_t e = hipMemsetAsync(flags, 0, 3 * sizeof(int), c->stream);
+  if (e == hipSuccess) e = launch_iso_classify(op, c->base64, c->bdata64, fidx, nf, flags, c->stream);
+  int hf[3] = {0, 0, 0};
+  double h[5] = {0, 0, 0, 0, 0};   // p0, s0, T0, T_p, T_s at point 0
+  const long long np = op.npts;
+  const long long off[5] = {0, (long long)(nv - 1) * np, (long long)nv * np, (long long)(nv + 1) * np,
+                            (long long)(nv + 2) * np};
+  if (e == hipSuccess) e = hipMemcpyAsync(hf, flags, sizeof hf, hipMemcpyDeviceToHost, c->stream);
+  for (int q = 0; q < 5 && e == hipSuccess; ++q)
+    e = hipMemcpyAsync(&h[q], c->base64 + off[q], sizeof(double), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return c->hip_fail(e, "sa_base_set classify");
+  if (hf[0]) return SA_OK;   // p0 or s0 varies: general kernels only
+  const double p0 = h[0], T0 = h[2];
+  const double S = op.suth;
+  const double rho = p0 / (op.R * T0);
+  const double mu0 = op.mu_ref * T0 * std::sqrt(T0) * (1.0 + S) / (T0 + S);
+  const double muT = mu0 * (1.5 / T0 - 1.0 / (T0 + S));
+  auto fill = [&](auto& ib, auto* bd) {
+    using R = std::remove_reference_t<decltype(ib.Tp)>;
+    for (int q = 0; q < ISO_MAXF; ++q) {
+      ib.f[q] = nullptr;
+      ib.kind[q] = ISO_ZERO;
+    }
+    for (int q = 0; q < nf; ++q) {
+      ib.f[q] = bd + (long long)fidx[q] * np;
+      ib.kind[q] = !(hf[1] >> q & 1) ? ISO_ZERO : (!(hf[2] >> q & 1) ? ISO_PROFILE : ISO_GENERAL);
+    }
+    ib.Tp = R(h[3]);
+    ib.Ts = R(h[4]);
+    ib.p0 = R(p0);
+    ib.ip0 = R(1.0 / p0);
+    ib.T0 = R(T0);
+    ib.rho = R(rho);
+    ib.irho = R(1.0 / rho);
+    ib.irT = R(1.0 / (rho * T0));
+    ib.mu0 = R(mu0);
+    ib.muT = R(muT);
+    ib.lam0 = R(op.cp / op.pr * mu0);
+    ib.igam = R(1.0 / op.gamma);
+    ib.icp = R(1.0 / op.cp);
+  };
+  fill(c->iso64, c->bdata64);
+  fill(c->iso32, c->bdata32);
+  c->iso = true;
+  op.iso[0] = &c->iso64;
+  op.iso[1] = &c->iso32;
+  return SA_OK;
+}
+
 // Time each operator kernel variant on this problem (one warm-up and three
 // timed launches, HIP events on the context's stream) and keep the fastest
 // per precision.  Inputs are the base fields themselves (finite values of
@@ -82,6 +149,10 @@ static int autotune_jv(Ctx* c) {
     float best = 0.0f;
     int best_v = -1;
     for (int v = 0; v < JV_NVARIANTS && rc == SA_OK; ++v) {
+      if (jv_variant_is_iso(v) && !c->iso) {
+        c->jv_tune_us[pr][v] = 0.0f;
+        continue;
+      }
       auto launch = [&]() -> hipError_t {
         if (pr == 0)
           return launch_jv<double>(c->op, c->base64, c->bdata64, c->base64, (double*)y, 1, 0.0, nullptr, c->stream, v);
@@ -219,6 +290,8 @@ int sa_base_set(sa_ctx* c, const sa_problem* pb, const double* q0_dev) {
   const size_t nf = (size_t)(c->nv + 3) * op.npts;
   c->has_base = false;
   c->has_precond = false;
+  c->iso = false;
+  op.iso[0] = op.iso[1] = nullptr;
   c->drop_graphs();
   c->base64 = (double*)c->buffer("base64", nf * sizeof(double));
   c->base32 = (float*)c->buffer("base32", nf * sizeof(float));
@@ -245,7 +318,9 @@ int sa_base_set(sa_ctx* c, const sa_problem* pb, const double* q0_dev) {
   cast_d2f((long long)nbd, c->bdata64, c->bdata32, nullptr, c->stream);
   e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return c->hip_fail(e, "sa_base_set base data sync");
-  const int rc = autotune_jv(c);
+  int rc = setup_iso(c);
+  if (rc != SA_OK) return rc;
+  rc = autotune_jv(c);
   if (rc != SA_OK) return rc;
   c->has_base = true;
   return SA_OK;

@@ -23,7 +23,38 @@ struct OpParams {
   double mu_ref;           // 1/Re (0 inviscid)
   double suth;             // Sutherland constant S/T_ref
   double pr;
+  // IsoBase<double> / IsoBase<float> (host memory of the context) when the
+  // base state has a uniform thermodynamic state, else null
+  const void* iso[2];
 };
+
+// Base states with uniform p0 and s0 (so uniform T0, rho0, mu0, dT/dp,
+// dT/ds): the operator needs per point only u0_i, D_a u0_i and
+// L u0_i + G0_i/3 (iso_fields(ND) fields, in that order, D_a u0_i at
+// ND + i ND + a), each classified exactly as identically zero, a y profile
+// (equal along x and z; read at x = 0, z = 0) or general.
+constexpr int ISO_ZERO = 0, ISO_PROFILE = 1, ISO_GENERAL = 2;
+constexpr int ISO_MAXF = 15;
+__host__ __device__ constexpr int iso_fields(int nd) { return nd + nd * nd + nd; }
+template <typename R>
+struct IsoBase {
+  const R* f[ISO_MAXF];    // field q: start of its base-data field (general: [point], profile: [j nx])
+  int kind[ISO_MAXF];      // ISO_ZERO / ISO_PROFILE / ISO_GENERAL
+  R Tp, Ts;                // dT/dp, dT/ds
+  R p0, ip0, T0, rho, irho, irT;   // irT = 1/(rho T0)
+  R mu0, muT, lam0;        // mu(T0), mu'(T0), c_p mu(T0)/Pr
+  R igam, icp;             // 1/gamma, 1/c_p
+};
+template <typename R>
+hipError_t launch_jv_iso(const OpParams& p, const IsoBase<R>& ib, const R* x, R* y, int nrhs, R shift,
+                         const int* active, hipStream_t s, long long sX, long long sY, const double* shifts,
+                         long long sA, int nzc);
+// flags[0] |= 1 if p0 or s0 differ anywhere from their value at point 0;
+// for the iso_fields(ndim) base-data fields fidx[q]: flags[1] |= 1 << q if
+// the field is non-zero somewhere, flags[2] |= 1 << q if it differs from
+// its value at (x = 0, z = 0) of the same row somewhere
+hipError_t launch_iso_classify(const OpParams& p, const double* base, const double* bdata, const int* fidx,
+                               int nf, int* flags, hipStream_t s);
 
 // Kernel launchers (all enqueue on the given stream; no synchronisation).
 // Jv: y = (J - shift I) x for nrhs vectors.  base holds the nv base fields
@@ -52,9 +83,11 @@ hipError_t launch_jv_stage(const OpParams& p, const R* base, const R* bdata, con
 // sa_jv_variant); -1 is the precision's default (prefetch z32 in FP64,
 // stage z16 in FP32).
 // prefetch z32, prefetch z16, stage z16, stage z32, prefetch z4, prefetch z1,
-// stage z4, stage z1 (zN: N planes per workgroup; shallow ones give small 3D
-// grids enough workgroups)
-constexpr int JV_NVARIANTS = 8;
+// stage z4, stage z1, iso z32, iso z16, iso z4, iso z1 (zN: N planes per
+// workgroup; shallow ones give small 3D grids enough workgroups; the iso
+// kernels need a base state of uniform thermodynamic state)
+constexpr int JV_NVARIANTS = 12;
+constexpr bool jv_variant_is_iso(int v) { return v >= 8 && v < 12; }
 template <typename R>
 hipError_t launch_jv_pert(const OpParams& p, const R* base, const R* bdata, const R* x, R* y, int nrhs, R shift,
                           const int* active, hipStream_t s, long long sX = 0, long long sY = 0,

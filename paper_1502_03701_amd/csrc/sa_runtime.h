@@ -40,6 +40,10 @@ struct Ctx {
   float* base32 = nullptr;
   double* bdata64 = nullptr;   // per-point base-state derivative data
   float* bdata32 = nullptr;
+  // uniform thermodynamic state (op.iso points here when set)
+  bool iso = false;
+  IsoBase<double> iso64{};
+  IsoBase<float> iso32{};
 
   // y = (J - shift I) x in precision R on the context's stream
   template <typename R>

@@ -21,6 +21,9 @@ CASES = {
     "c0_48x48_M0.3_Re500": (synth.config0(), "tanh"),
     "kh_24x24_M0.3_Re500": (synth.mixing_layer_2d(24, 24, 0.3, 500.0), "tanh"),
     "kh_32x32_M0.5_Re1000": (synth.mixing_layer_2d(32, 32, 0.5, 1000.0), "tanh"),
+    # reduced 3D: the workload's base (tanh layer plus 1e-3 N(0,1) spanwise
+    # velocity from seed 2) on a 16 x 16 x 8 grid (n = 8 960 interior DOFs)
+    "3d_16x16x8_M0.5_Re1000_w": (synth.mixing_layer_3d(16, 16, 8, 0.5, 1000.0), "tanh_w"),
 }
 
 
@@ -28,7 +31,7 @@ def main(names=None):
     for name, (prob, kind) in CASES.items():
         if names and name not in names:
             continue
-        q0 = synth.base_flow(prob)
+        q0 = synth.base_flow(prob, seed=2, w_noise=1e-3) if kind == "tanh_w" else synth.base_flow(prob)
         J = op.dense_jacobian(prob, q0, batch=256)
         lam = sla.eigvals(J)
         th = (lam + 0.2) / (lam - 0.2)

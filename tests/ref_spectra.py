@@ -1,0 +1,34 @@
+"""Leading eigenvalues of the oracle's operator under the Cayley transform
+(test helper; CPU only).
+
+The oracle's sparse Jacobian (coloured complex-step probing) restricted to
+the interior DOFs, a sparse LU of J - sigma I (SuperLU), and ARPACK's
+implicitly restarted Arnoldi on C = (J - sigma I)^{-1} (J - mu I) for the
+eigenvalues of largest |theta| (eq. cayley_transform), back-transformed by
+lambda = (sigma theta - mu)/(theta - 1).  Library routines on the oracle's
+operator only: no GPU code.  For grids where the dense Jacobian is out of
+reach (3D, larger sweeps); on small grids tests/test_oracle_solvers.py
+checks it against the dense LAPACK spectrum.
+"""
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as ssl
+
+from oracle import operator as op
+
+
+def cayley_leading(prob, q0, k, sigma=0.2, mu=-0.2, tol=1e-14, ncv=None, seed=0):
+    """(lam, theta) of the k eigenvalues of C with largest |theta|, largest
+    first."""
+    S = op.sparse_jacobian(prob, q0)
+    idx = op.interior_index(prob)
+    A = S[idx][:, idx].tocsc()
+    n = A.shape[0]
+    lu = ssl.splu((A - sigma * sp.identity(n, format="csc")).tocsc())
+    C = ssl.LinearOperator((n, n), matvec=lambda v: lu.solve(A @ v - mu * v), dtype=np.float64)
+    v0 = np.random.default_rng(seed).standard_normal(n)
+    th = ssl.eigs(C, k=k, which="LM", tol=tol, ncv=ncv or max(2 * k + 1, 40), v0=v0,
+                  return_eigenvectors=False, maxiter=100000)
+    th = th[np.argsort(-np.abs(th), kind="stable")]
+    lam = (sigma * th - mu) / (th - 1.0)
+    return lam, th

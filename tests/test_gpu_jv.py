@@ -70,14 +70,20 @@ VARIANT_CASES = [
     # nx, ny multiples of 16: the 16 x 16 tiles cover the plane exactly (the
     # FP64 prefetch kernels' branch-free instantiation), z ragged as above
     ("3d-exact-tiles", synth.mixing_layer_3d(32, 16, 40, 0.5, 1000.0), "noise"),
+    # uniform thermodynamic state (the iso kernels run): 2D parallel flow with
+    # ragged tiles, and a small 3D grid with spanwise noise and ragged tiles
+    ("2d-tanh-ragged", synth.mixing_layer_2d(37, 29, 0.5, 1000.0), "tanh"),
+    ("3d-noise-ragged", synth.mixing_layer_3d(21, 19, 11, 0.5, 1000.0), "noise"),
 ]
+NVAR = 12
 
 
-@pytest.mark.parametrize("variant", range(8))
+@pytest.mark.parametrize("variant", range(NVAR))
 @pytest.mark.parametrize("name,prob,kind", VARIANT_CASES, ids=[c[0] for c in VARIANT_CASES])
 def test_jv_every_kernel_variant(ctxs, name, prob, kind, variant):
     """Each operator kernel variant the autotuner may pick, pinned, in both
-    precisions, against the oracle (also with two right-hand sides)."""
+    precisions, against the oracle (also with two right-hand sides).  NaN on
+    both wall rows of the input must be ignored (the operator is P J P)."""
     from paper_1502_03701_amd import SA_F32, SA_F64
     q0 = base_for(prob, kind)
     v = synth.random_vector(prob, 5, nrhs=2)
@@ -87,6 +93,10 @@ def test_jv_every_kernel_variant(ctxs, name, prob, kind, variant):
     ctx.set_jv_variant(SA_F32, variant)
     assert ctx.jv_variant(SA_F64)[0] == variant and ctx.jv_variant(SA_F32)[0] == variant
     ref = np.stack([op.jv_cstep(prob, q0, v[r]) - 0.1 * op.project(prob, v[r]) for r in range(2)])
+    if prob.bc[1] == synth.BC_WALL:
+        v = v.copy()
+        v[..., 0, :] = np.nan
+        v[..., -1, :] = np.nan
     y = torch.empty(2 * prob.ndof, dtype=torch.float64, device="cuda:0")
     ctx.op_apply(dev(v), y, shift=0.1, nrhs=2)
     assert rel(host(y), ref.ravel()) < 1e-12, (name, variant)
@@ -106,11 +116,33 @@ def test_autotuner_picks_a_measured_variant(ctxs):
     ctx.base_set(prob, dev(synth.base_flow(prob, seed=1, w_noise=1e-3)))
     for prec in (SA_F64, SA_F32):
         var, times = ctx.jv_variant(prec)
-        assert 0 <= var < 8
-        assert all(t > 0 for t in times.values())
+        assert 0 <= var < NVAR
+        assert all(t > 0 for t in times.values())      # uniform p0, s0: the iso kernels are timed too
         assert list(times.values())[var] == min(times.values())
     with pytest.raises(SAError):
-        ctx.set_jv_variant(SA_F64, 8)
+        ctx.set_jv_variant(SA_F64, NVAR)
+
+
+def test_uniform_state_detection(ctxs):
+    """The iso kernels are timed (and may be picked) only for base states
+    whose pressure and entropy are the same at every point."""
+    from paper_1502_03701_amd import SA_F32, SA_F64
+    prob = synth.mixing_layer_3d(16, 12, 10, 0.5, 1000.0)
+    from paper_1502_03701_amd._native import JV_VARIANTS
+    ctx = ctxs()
+    iso = [n for n in JV_VARIANTS if n.startswith("iso")]
+    for q0, expect in [(synth.base_flow(prob, seed=3, w_noise=1e-3), True), (synth.random_base(prob, 2), False)]:
+        ctx.base_set(prob, dev(q0))
+        for prec in (SA_F64, SA_F32):
+            var, times = ctx.jv_variant(prec)
+            assert all((times[n] > 0) == expect for n in iso), (expect, times)
+            if not expect:
+                assert not JV_VARIANTS[var].startswith("iso")
+    # a base whose entropy varies in one point only is not of that class
+    q0 = synth.base_flow(prob)
+    q0[-1, 4, 5, 6] = 1e-9
+    ctx.base_set(prob, dev(q0))
+    assert all(ctx.jv_variant(SA_F64)[1][n] == 0 for n in iso)
 
 
 def test_jv_multi_rhs_and_wall_inputs_ignored(ctxs):
@@ -130,18 +162,29 @@ def test_jv_multi_rhs_and_wall_inputs_ignored(ctxs):
         assert np.all(Y[r][:, 0, :] == 0) and np.all(Y[r][:, -1, :] == 0)
 
 
-def test_jv_full_size_3d_sampled_windows(ctxs):
-    """256x128x128 (the 3D benchmark grid): compare windows of the full-size
-    GPU output with the oracle evaluated on the window (valid >= 3 cells away
-    from the window's cut faces, full y range with the walls)."""
+@pytest.mark.parametrize("variant", [None, 8, 0], ids=["autotuned", "iso_z32", "prefetch_z32"])
+def test_jv_full_size_3d_sampled_windows(ctxs, variant):
+    """256x128x128 (the 3D benchmark grid), the kernels bench.py times (the
+    autotuned ones) and the iso and general 32-plane kernels pinned: compare
+    windows of the full-size GPU output, FP64 and FP32, with the oracle
+    evaluated on the window (valid >= 3 cells away from the window's cut
+    faces, full y range with the walls)."""
+    from paper_1502_03701_amd import SA_F32, SA_F64
     prob = synth.config2()
     q0 = synth.base_flow(prob, seed=2, w_noise=1e-3)
     v = synth.random_vector(prob, 2)
     ctx = ctxs()
+    if variant is not None:
+        ctx.set_jv_variant(SA_F64, variant)
+        ctx.set_jv_variant(SA_F32, variant)
     ctx.base_set(prob, dev(q0))
+    print("\nvariants:", ctx.jv_variant(SA_F64)[0], ctx.jv_variant(SA_F32)[0])
     y = torch.empty(prob.ndof, dtype=torch.float64, device="cuda:0")
     ctx.op_apply(dev(v), y, shift=0.2)
     Y = host(y).reshape(prob.shape)
+    y32 = torch.empty(prob.ndof, dtype=torch.float32, device="cuda:0")
+    ctx.op_apply(dev(v, torch.float32), y32, shift=0.2)
+    Y32 = host(y32).reshape(prob.shape)
     rng = np.random.default_rng(0)
     nx, ny, nz = prob.n
     W = 14
@@ -156,9 +199,9 @@ def test_jv_full_size_3d_sampled_windows(ctxs):
         qs = q0[:, kk][:, :, :, ii]
         vs = v[:, kk][:, :, :, ii]
         ref = op.jv_cstep(sub, qs, vs) - 0.2 * op.project(sub, vs)
-        got = Y[:, kk][:, :, :, ii]
         inner = (slice(None), slice(3, W - 3), slice(None), slice(3, W - 3))
-        assert rel(got[inner], ref[inner]) < 1e-12
+        assert rel(Y[:, kk][:, :, :, ii][inner], ref[inner]) < 1e-12
+        assert rel(Y32[:, kk][:, :, :, ii][inner], ref[inner]) < 1e-5
 
 
 def test_jv_deterministic_rerun(ctxs):
