@@ -7,8 +7,10 @@ implicitly restarted Arnoldi on C = (J - sigma I)^{-1} (J - mu I) for the
 eigenvalues of largest |theta| (eq. cayley_transform), back-transformed by
 lambda = (sigma theta - mu)/(theta - 1).  Library routines on the oracle's
 operator only: no GPU code.  For grids where the dense Jacobian is out of
-reach (3D, larger sweeps); on small grids tests/test_oracle_solvers.py
-checks it against the dense LAPACK spectrum.
+reach; on small grids tests/test_oracle_solvers.py checks it against the
+dense LAPACK spectrum.  Only eigenvalues separated from the |theta| ~ 1 ring
+are reliable (ring members differ by ~1e-5 in |theta| and ARPACK settles on
+any of them).
 """
 import numpy as np
 import scipy.sparse as sp

@@ -353,3 +353,22 @@ def test_lgmres_needs_fewer_products_on_a_cayley_system():
     assert ig["converged"] and il["converged"]
     assert np.linalg.norm(b - A @ xl) <= 1e-10 * np.linalg.norm(b) * 1.0001
     assert il["matvecs"] < 0.8 * ig["matvecs"]
+
+
+def test_cayley_leading_reference_matches_dense_spectrum():
+    """The sparse ARPACK reference the GPU sweep test uses (tests/ref_spectra)
+    against the dense LAPACK spectrum of the oracle's Jacobian on the 24x24
+    case (tests/golden): the separated leading pair (the KH mode, |theta| =
+    6.0) is the same to 1e-10.  Beyond it the spectrum is a ring of
+    |theta| ~ 1 whose members differ by 1e-5 in |theta|; ARPACK settles on
+    any of them, so the reference is used for separated eigenvalues only."""
+    import numpy as _np
+    from ref_spectra import cayley_leading
+    prob = synth.mixing_layer_2d(24, 24, 0.3, 500.0)
+    lam, th = cayley_leading(prob, synth.base_flow(prob), 4)
+    a = _np.loadtxt(os.path.join(GOLDEN, "spectrum_kh_24x24_M0.3_Re500.txt"))
+    ref = a[:, 0] + 1j * a[:, 1]
+    for l in lam[:2]:
+        assert abs(l - ref[0]) < 1e-10 * abs(ref[0])
+    assert _np.all(_np.abs(th[:2]) > 5.0) and _np.all(_np.abs(th[2:]) < 1.01)
+
