@@ -31,9 +31,18 @@ METRIC = "Gpt-updates/s of matrix-free Jv; time to 6 eigenpairs, mixed vs FP64 G
 HBM_PEAK_GBS = 8000.0
 
 
-COUNTERS = os.path.join(ROOT, "profiles", "jv_prefetch_fp64_256x128x128_hbm_counters.md")
-KERNEL_SOURCES = ["paper_1502_03701_amd/csrc/jv_prefetch.hip", "paper_1502_03701_amd/csrc/jv_stage.hip",
-                  "paper_1502_03701_amd/csrc/jv_common.h", "paper_1502_03701_amd/csrc/jv.hip"]
+# committed rocprofv3 FETCH_SIZE / WRITE_SIZE summaries: (file, kernel sources
+# hashed at measurement, the key of that hash in the file)
+COUNTERS = {
+    "iso": (os.path.join(ROOT, "profiles", "jv_iso_fp64_256x128x128_hbm_counters.md"),
+            ["paper_1502_03701_amd/csrc/jv_iso.hip", "paper_1502_03701_amd/csrc/jv_common.h",
+             "paper_1502_03701_amd/csrc/sa_internal.h"],
+            "kernel_source_sha256 (jv_iso.hip, jv_common.h, sa_internal.h at measurement)"),
+    "general": (os.path.join(ROOT, "profiles", "jv_prefetch_fp64_256x128x128_hbm_counters.md"),
+                ["paper_1502_03701_amd/csrc/jv_prefetch.hip", "paper_1502_03701_amd/csrc/jv_stage.hip",
+                 "paper_1502_03701_amd/csrc/jv_common.h", "paper_1502_03701_amd/csrc/jv.hip"],
+                "kernel_source_sha256 (jv_prefetch.hip, jv_stage.hip, jv_common.h, jv.hip at measurement)"),
+}
 
 
 def measured_traffic(variant):
@@ -42,8 +51,9 @@ def measured_traffic(variant):
     (calibrated against a copy of known size), or None if that variant was
     not measured or the kernel source changed since."""
     import hashlib
+    path, sources, key = COUNTERS["iso" if variant.startswith("iso") else "general"]
     try:
-        text = open(COUNTERS).read()
+        text = open(path).read()
     except OSError:
         return None
     fields = {}
@@ -52,10 +62,9 @@ def measured_traffic(variant):
             k, v = line.split(":", 1)
             fields[k.strip()] = v.strip()
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in sources:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
-    key = "kernel_source_sha256 (jv_prefetch.hip, jv_stage.hip, jv_common.h, jv.hip at measurement)"
     name = "traffic_bytes_per_launch[%s]" % variant
     if fields.get(key) != h.hexdigest() or name not in fields:
         return None
@@ -244,6 +253,8 @@ def main():
         var, times = ctx.jv_variant(prec)
         tuned[name] = {"variant": JV_VARIANTS[var] if var >= 0 else "default", "tune_us": times}
 
+    traffic = measured_traffic(tuned["f64"]["variant"])
+
     x32 = x.float()
     y32 = torch.empty_like(x32)
     sec32 = timed(lambda: ctx.op_apply(x32, y32, shift=0.2), args.steps, args.warmup, torch)
@@ -271,8 +282,13 @@ def main():
                    "grid": [256, 128, 128], "nv": nv, "shift": 0.2},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(tuned["f64"]["variant"]),
-                     "kernel": kernel_name(tuned["f64"]["variant"]), "alg_bytes_per_point": 3 * nv * 8},
+                     "traffic": traffic,
+                     "kernel": kernel_name(tuned["f64"]["variant"]), "alg_bytes_per_point": 3 * nv * 8,
+                     "frac_basis": "achieved and frac: algorithmic bytes (x, q0 in; y out) per launch over the "
+                                   "HIP-event time; traffic_GBs and traffic_frac: the measured HBM bytes "
+                                   "(rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated) over the same time",
+                     "traffic_GBs": traffic / per / 1e9 if traffic else None,
+                     "traffic_frac": traffic / per / 1e9 / HBM_PEAK_GBS if traffic else None},
         "fp32_jv": {"gpts": npts / per32 / 1e9, "ms": per32 * 1e3,
                     "achieved_GBs": 3 * nv * 4 * npts / per32 / 1e9},
         "autotuned_jv": tuned,

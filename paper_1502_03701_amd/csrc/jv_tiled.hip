@@ -1,13 +1,13 @@
-// Tiled tangent-linear operator y = (J(q0) - shift I) x (same discrete
-// operator as the reference kernel in jv.hip).
+// Base-state derivative data (sa_base_set): the per-point fields the
+// operator kernels read instead of differentiating q0 in every product --
+// p0, u0_i, T0, D p0, D u0, D s0, D T0, L u0 + G0/3, L T0 -- computed with
+// the same discrete stencils as the operator (jv.hip).
 //
 // A workgroup owns a TX x TY column tile and marches over a chunk of z
 // planes.  For each plane:
-//   1. the plane with a 3-point xy halo is staged in LDS for the 12 fields
-//      (perturbation p, u_i, s, T' and base p, u_i, s, T), T' = T_p p' + T_s s'
-//      formed while staging;
+//   1. the plane with a 3-point xy halo is staged in LDS (base p, u_i, s, T);
 //   2. z-derivatives come from the thread's own column (loads of planes
-//      k +- 1..3, cached), accumulated on the fly;
+//      k +- 1..3), accumulated on the fly;
 //   3. mixed derivatives are first differences of staged first-derivative
 //      fields (the tensor-product differences commute):
 //        G_x = D2_x u + D_x (D_y v + D_z w)
@@ -16,7 +16,7 @@
 //      so the staged fields need only an x halo (D_y v + D_z w, D_z u) or a
 //      y halo (D_x u + D_z w, D_z v); their halo values are computed by
 //      spare threads;
-//   4. the pointwise tangent-linear algebra of jv_common.h.
+//   4. the fields are written to the base-data array.
 #include "jv_common.h"
 
 namespace sa {
@@ -36,28 +36,21 @@ __device__ __forceinline__ int wrap(int a, int n) {
   return a < 0 ? a + n : (a >= n ? min(a - n, n - 1) : a);
 }
 
-// MODE_FULL: perturbation and base stencils every call.
-// MODE_BASE: base stencils only; writes the per-point base data (bdata).
-// MODE_PERT: perturbation stencils only; base data read from bdata.
-constexpr int MODE_FULL = 0, MODE_BASE = 1, MODE_PERT = 2;
 
 template <int ND>
 constexpr int bdata_count() { return 1 + ND + 1 + ND + ND * ND + ND + ND + ND + 1; }
 
-template <typename R, int ND, int MODE>
-__global__ void __launch_bounds__(NT) jv_tiled_kernel(OpParams op, const R* __restrict__ base,
-                                                      const R* __restrict__ x, R* __restrict__ y, R shift,
-                                                      const int* __restrict__ active, R* __restrict__ bdata) {
-  if (active && !*active) return;
+template <typename R, int ND>
+__global__ void __launch_bounds__(NT) base_data_kernel(OpParams op, const R* __restrict__ base,
+                                                       R* __restrict__ bdata) {
   constexpr int NF = ND + 3;
-  constexpr int NSET = MODE == MODE_FULL ? 2 : 1;
+  constexpr int NSET = 1;
   constexpr int NPL = NSET * NF;                    // staged plane fields
   __shared__ R sP[NPL][PH][PW];
   // x-staged: [set][0: D_y v + D_z w, 1: D_z u][TY][PW]; y-staged: [set][0: D_x u + D_z w, 1: D_z v][PH][TX]
   __shared__ R sX[NSET][2][TY][PW];
   __shared__ R sY[NSET][2][PH][TX];
-  // set s is the perturbation unless it is the base set
-  auto is_pert = [](int s) -> bool { return MODE == MODE_PERT || (MODE == MODE_FULL && s == 0); };
+  auto is_pert = [](int) -> bool { return false; };   // only the base state is differentiated
 
   const int tid = threadIdx.x;
   const int ti = tid % TX, tj = tid / TX;
@@ -66,8 +59,6 @@ __global__ void __launch_bounds__(NT) jv_tiled_kernel(OpParams op, const R* __re
   const int nx = op.nx, ny = op.ny, nz = op.nz;
   const long long npts = op.npts;
   const bool inside = i < nx && j < ny;
-  const bool wallrow = op.bcy == 1 && (j == 0 || j == ny - 1);
-  const bool active_pt = inside && !wallrow;
   const R ihx = R(op.ihx), ihy = R(op.ihy), ihz = R(op.ihz);
 
   const Axis<R> ax = axis_coefs<R>(6);
@@ -85,15 +76,8 @@ __global__ void __launch_bounds__(NT) jv_tiled_kernel(OpParams op, const R* __re
   };
   auto is_wall = [&](int g) -> bool { return op.bcy == 1 && (g == 0 || g == ny - 1); };
 
-  // value of logical field f (0..NF-1, PERT or BASE) at flat point p
-  auto loadf = [&](bool pert, int f, long long p, bool wall) -> R {
-    if (!pert) return base[(long long)f * npts + p];
-    if (wall) return R(0);
-    if (f < ND + 2) return x[(long long)f * npts + p];
-    const R tp = base[(long long)(ND + 3) * npts + p];
-    const R ts = base[(long long)(ND + 4) * npts + p];
-    return tp * x[p] + ts * x[(long long)(ND + 1) * npts + p];
-  };
+  // base field f (p, u_i, s, then T) at flat point p
+  auto loadf = [&](bool, int f, long long p, bool) -> R { return base[(long long)f * npts + p]; };
 
   // D_z of field f of one set at column (ii, gj) plane k (global loads)
   auto dz1 = [&](bool pert, int f, int gi, int gj, int k, bool wall) -> R {
@@ -302,109 +286,44 @@ __global__ void __launch_bounds__(NT) jv_tiled_kernel(OpParams op, const R* __re
       P[s].G[1] += gy * ihy;
       if (ND == 3) P[s].G[2] += gz1 * ihx + gz2 * ihy;
     }
-    // 5. pointwise algebra and store (or the base data)
+    // 5. the base data of the point
     const long long id = ((long long)k * ny + j) * nx + i;
-    if (MODE == MODE_BASE) {
-      if (inside) {
-        const Pt<R, ND>& b = P[0];
-        int q = 0;
-        auto put = [&](R v) { bdata[(long long)(q++) * npts + id] = v; };
-        put(b.q[0]);
+    if (inside) {
+      const Pt<R, ND>& b = P[0];
+      int q = 0;
+      auto put = [&](R v) { bdata[(long long)(q++) * npts + id] = v; };
+      put(b.q[0]);
 #pragma unroll
-        for (int a = 0; a < ND; ++a) put(b.q[1 + a]);
-        put(b.q[ND + 2]);
+      for (int a = 0; a < ND; ++a) put(b.q[1 + a]);
+      put(b.q[ND + 2]);
 #pragma unroll
-        for (int a = 0; a < ND; ++a) put(b.D[0][a]);
+      for (int a = 0; a < ND; ++a) put(b.D[0][a]);
 #pragma unroll
-        for (int c2 = 0; c2 < ND; ++c2)
+      for (int c2 = 0; c2 < ND; ++c2)
 #pragma unroll
-          for (int a = 0; a < ND; ++a) put(b.D[1 + c2][a]);
+        for (int a = 0; a < ND; ++a) put(b.D[1 + c2][a]);
 #pragma unroll
-        for (int a = 0; a < ND; ++a) put(b.D[ND + 1][a]);
+      for (int a = 0; a < ND; ++a) put(b.D[ND + 1][a]);
 #pragma unroll
-        for (int a = 0; a < ND; ++a) put(b.D[ND + 2][a]);
+      for (int a = 0; a < ND; ++a) put(b.D[ND + 2][a]);
 #pragma unroll
-        for (int a = 0; a < ND; ++a) put(b.Lu[a] + b.G[a] * R(1.0 / 3.0));
-        put(b.LT);
-      }
-    } else if (active_pt) {
-      R out[ND + 2];
-      if (MODE == MODE_FULL) {
-        tangent_point<R, ND>(P[NSET - 1], P[0], op, out);
-      } else {
-        Pt<R, ND> b;
-        int q = 0;
-        auto get = [&]() -> R { return bdata[(long long)(q++) * npts + id]; };
-        b.q[0] = get();
-#pragma unroll
-        for (int a = 0; a < ND; ++a) b.q[1 + a] = get();
-        b.q[ND + 2] = get();
-        b.q[ND + 1] = R(0);
-#pragma unroll
-        for (int a = 0; a < ND; ++a) b.D[0][a] = get();
-#pragma unroll
-        for (int c2 = 0; c2 < ND; ++c2)
-#pragma unroll
-          for (int a = 0; a < ND; ++a) b.D[1 + c2][a] = get();
-#pragma unroll
-        for (int a = 0; a < ND; ++a) b.D[ND + 1][a] = get();
-#pragma unroll
-        for (int a = 0; a < ND; ++a) b.D[ND + 2][a] = get();
-#pragma unroll
-        for (int a = 0; a < ND; ++a) {
-          b.Lu[a] = get();
-          b.G[a] = R(0);
-        }
-        b.LT = get();
-        tangent_point<R, ND>(b, P[0], op, out);
-      }
-#pragma unroll
-      for (int f = 0; f < ND + 2; ++f) {
-        const long long o = (long long)f * npts + id;
-        y[o] = out[f] - shift * P[0].q[f];
-      }
-    } else if (inside) {
-#pragma unroll
-      for (int f = 0; f < ND + 2; ++f) y[(long long)f * npts + id] = R(0);
+      for (int a = 0; a < ND; ++a) put(b.Lu[a] + b.G[a] * R(1.0 / 3.0));
+      put(b.LT);
     }
   }
 }
 
 }  // namespace
 
-template <typename R, int MODE>
-static hipError_t launch_mode(const OpParams& p, const R* base, const R* x, R* y, int nrhs, R shift,
-                              const int* active, R* bdata, hipStream_t s) {
-  const long long ndof = (long long)(p.ndim + 2) * p.npts;
-  dim3 grid((p.nx + TX - 1) / TX, (p.ny + TY - 1) / TY, p.ndim == 3 ? (p.nz + NZC - 1) / NZC : 1);
-  for (int r = 0; r < nrhs; ++r) {
-    const R* xr = x ? x + r * ndof : nullptr;
-    R* yr = y ? y + r * ndof : nullptr;
-    if (p.ndim == 2)
-      jv_tiled_kernel<R, 2, MODE><<<grid, NT, 0, s>>>(p, base, xr, yr, shift, active, bdata);
-    else
-      jv_tiled_kernel<R, 3, MODE><<<grid, NT, 0, s>>>(p, base, xr, yr, shift, active, bdata);
-  }
-  return hipGetLastError();
-}
-
 int base_data_fields(int ndim) { return ndim == 2 ? bdata_count<2>() : bdata_count<3>(); }
 
-template <typename R>
-hipError_t launch_jv_tiled(const OpParams& p, const R* base, const R* x, R* y, int nrhs, R shift,
-                           const int* active, const R* bdata, hipStream_t s) {
-  if (bdata)
-    return launch_mode<R, MODE_PERT>(p, base, x, y, nrhs, shift, active, const_cast<R*>(bdata), s);
-  return launch_mode<R, MODE_FULL>(p, base, x, y, nrhs, shift, active, nullptr, s);
-}
-
 hipError_t launch_base_data(const OpParams& p, const double* base, double* bdata, hipStream_t s) {
-  return launch_mode<double, MODE_BASE>(p, base, nullptr, nullptr, 1, 0.0, nullptr, bdata, s);
+  dim3 grid((p.nx + TX - 1) / TX, (p.ny + TY - 1) / TY, p.ndim == 3 ? (p.nz + NZC - 1) / NZC : 1);
+  if (p.ndim == 2)
+    base_data_kernel<double, 2><<<grid, NT, 0, s>>>(p, base, bdata);
+  else
+    base_data_kernel<double, 3><<<grid, NT, 0, s>>>(p, base, bdata);
+  return hipGetLastError();
 }
-
-template hipError_t launch_jv_tiled<double>(const OpParams&, const double*, const double*, double*, int,
-                                            double, const int*, const double*, hipStream_t);
-template hipError_t launch_jv_tiled<float>(const OpParams&, const float*, const float*, float*, int, float,
-                                           const int*, const float*, hipStream_t);
 
 }  // namespace sa

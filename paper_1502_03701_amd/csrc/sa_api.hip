@@ -134,7 +134,7 @@ static int setup_iso(Ctx* c) {
 // per precision.  Inputs are the base fields themselves (finite values of
 // the right size); the output goes to a scratch buffer.
 static int autotune_jv(Ctx* c) {
-  if (jv_kernel_forced() || (std::getenv("SA_JV_AUTOTUNE") && std::strcmp(std::getenv("SA_JV_AUTOTUNE"), "0") == 0))
+  if (std::getenv("SA_JV_AUTOTUNE") && std::strcmp(std::getenv("SA_JV_AUTOTUNE"), "0") == 0)
     return SA_OK;
   hipEvent_t ev0, ev1;
   if (hipEventCreate(&ev0) != hipSuccess) return c->fail(SA_EDEVICE, "autotune: event");

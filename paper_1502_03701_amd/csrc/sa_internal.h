@@ -57,13 +57,9 @@ hipError_t launch_iso_classify(const OpParams& p, const double* base, const doub
                                int nf, int* flags, hipStream_t s);
 
 // Kernel launchers (all enqueue on the given stream; no synchronisation).
-// Jv: y = (J - shift I) x for nrhs vectors.  base holds the nv base fields
-// followed by three pointwise fields T0, dT/dp, dT/ds (all with walls).
-// Tiled kernel; with bdata (per-point base-state data from launch_base_data,
-// base_data_fields(ndim) fields) only the perturbation is differentiated.
-template <typename R>
-hipError_t launch_jv_tiled(const OpParams& p, const R* base, const R* x, R* y, int nrhs, R shift,
-                           const int* active, const R* bdata, hipStream_t s);
+// base holds the nv base fields followed by three pointwise fields T0, dT/dp,
+// dT/ds (all with walls); bdata the per-point base-state derivative data of
+// launch_base_data (base_data_fields(ndim) fields).
 int base_data_fields(int ndim);
 // Perturbation-only kernels with a register z-queue (need bdata).  nrhs
 // systems in one launch: system r uses x/y + r*sV (sV = 0: n), the shift
@@ -92,30 +88,19 @@ template <typename R>
 hipError_t launch_jv_pert(const OpParams& p, const R* base, const R* bdata, const R* x, R* y, int nrhs, R shift,
                           const int* active, hipStream_t s, long long sX = 0, long long sY = 0,
                           const double* shifts = nullptr, long long sA = 0, int variant = -1);
-// A batch of systems: one launch with the default kernel, else one launch per
-// system.  System r reads x + r*sX, writes y + r*sY; shifts_host / shifts_dev
-// hold the per-system shifts.
+// A batch of systems in one launch: system r reads x + r*sX, writes y + r*sY
+// with the shift shifts_dev[r] (device array; shifts_host holds the same
+// values on the host).
 template <typename R>
 hipError_t launch_jv_batch(const OpParams& p, const R* base, const R* bdata, const R* x, R* y, int nsys,
                            long long sX, long long sY, const double* shifts_host, const double* shifts_dev,
                            const int* active, long long sA, hipStream_t s, int variant = -1);
 hipError_t launch_base_data(const OpParams& p, const double* base, double* bdata, hipStream_t s);
-// Reference kernel (one thread per point, stencil taps straight from memory).
-template <typename R>
-hipError_t launch_jv_direct(const OpParams& p, const R* base, const R* x, R* y, int nrhs, R shift,
-                            const int* active, hipStream_t s);
-// Operator dispatch: the perturbation-only kernel variant given (-1: the
-// precision's default), one of them for both precisions
-// (SA_JV_KERNEL=prefetch or stage), the tiled
-// kernel with precomputed base data (SA_JV_KERNEL=tiled), the tiled kernel
-// differentiating the base state every call (SA_JV_KERNEL=onthefly) or the
-// reference kernel (SA_JV_KERNEL=reference); the variable is read once per
-// process and serves to cross-check kernels.
+// Operator y = (J - shift I) x for nrhs vectors with the kernel variant given
+// (-1: the precision's default).
 template <typename R>
 hipError_t launch_jv(const OpParams& p, const R* base, const R* bdata, const R* x, R* y, int nrhs, R shift,
                      const int* active, hipStream_t s, int variant = -1);
-// Whether SA_JV_KERNEL forces a kernel (then variants are not tuned).
-bool jv_kernel_forced();
 
 // Base-state preprocessing: fields T0, T_p, T_s appended after q0 (FP64),
 // and the FP32 shadow of the whole base array.  Returns via flag (device int)
