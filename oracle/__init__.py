@@ -17,6 +17,9 @@ Contents (each function cites the passage of the paper it follows):
   refine     -- FP64 outer / FP32 inner iterative refinement of the Cayley
                 system (an added precision form, not from the paper).
   blockjac   -- block-Jacobi preconditioner (Section "Preconditioning").
+  fourier_pc -- mean-flow preconditioner: J of the base averaged over the
+                periodic axes, solved exactly (Section "Preconditioning",
+                Conclusions).
   philox     -- Philox4x32-10 counter-based generator (Salmon et al. 2011)
                 plus Box-Muller, for the seeded block noise.
 """
