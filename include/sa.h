@@ -103,12 +103,26 @@ typedef struct {
   int status;          /* SA_OK or SA_NOT_CONVERGED for this system        */
 } sa_gmres_info;
 
+/* Preconditioners of the Cayley systems (Section "Preconditioning").
+ * SA_PC_BLOCK_JACOBI: the paper's local block-Jacobi scheme, dense blocks of
+ * bx x by x bz cells assembled from operator calls.
+ * SA_PC_MEAN_FLOW: the operator of the base state averaged over the
+ * periodic directions (x, and z in 3D), M(s) = P (J(q_bar) - s I) P, solved
+ * exactly: it commutes with the periodic shifts, so it is solved mode by
+ * mode in their Fourier basis, each mode's block banded in y and factored
+ * by banded LU with partial pivoting (the Conclusions' direction of an
+ * approximate operator built from operator calls).  Exact for bases that
+ * do not vary along x and z; needs walls in y. */
+typedef enum { SA_PC_BLOCK_JACOBI = 0, SA_PC_MEAN_FLOW = 1 } sa_pc_kind;
+
 typedef struct {
   int bx, by, bz;          /* block size in cells (bz = 1 in 2D)          */
   double diag_add;         /* added to every block diagonal               */
   double noise_std;        /* std of the seeded N(0,1) noise added         */
   unsigned long long seed; /* Philox4x32-10 key for the noise             */
   sa_prec factor_prec;     /* SA_F32 (default use) or SA_F64 factors      */
+  int kind;                /* sa_pc_kind; the block fields, diag_add,
+                              noise_std and seed apply to block-Jacobi     */
 } sa_precond_opts;
 
 typedef struct {
@@ -198,9 +212,18 @@ int sa_get_jv_variant(const sa_ctx *ctx, sa_prec prec, float *times_us);
 int sa_op_apply(sa_ctx *ctx, sa_prec prec, int nrhs, const void *x_dev, void *y_dev,
                 double shift);
 
-/* Assemble and factor the block-Jacobi preconditioner for nshift shifts
- * (Section "Preconditioning": blocks of the operator assembled from
- * operator calls).  Block b of shift s is
+/* Assemble and factor the preconditioner of opts->kind for nshift shifts.
+ *
+ * SA_PC_MEAN_FLOW: the base state is averaged over the periodic axes, its
+ * operator's band coefficients are taken by 7 nv probes (operator calls on
+ * the averaged base), and for every shift s and Fourier mode of the
+ * periodic axes the mode's banded matrix (bandwidths 4 nv - 1, order
+ * (Ny-2) nv) is factored by LU with partial pivoting in factor_prec, one
+ * wavefront per (mode, shift), all in one launch.  The y axis must have
+ * walls.  Memory: nshift (Nx/2+1) Nz (Ny-2) nv (12 nv - 2) complex entries.
+ *
+ * SA_PC_BLOCK_JACOBI (Section "Preconditioning": blocks of the operator
+ * assembled from operator calls).  Block b of shift s is
  *     B_b(s) = P_b J P_b^T + diag_add I + noise_std E_b - s I
  * on the block's interior DOFs, E_b seeded standard-normal (Philox4x32-10),
  * P_b the restriction to the block's DOFs; on its wall DOFs (which are not
@@ -217,10 +240,13 @@ int sa_op_apply(sa_ctx *ctx, sa_prec prec, int nrhs, const void *x_dev, void *y_
 int sa_precond_setup(sa_ctx *ctx, const sa_precond_opts *opts, int nshift,
                      const double *shifts_host);
 
-/* z = P blockdiag(B_b(shift ishift))^{-1} r for nrhs vectors (double for
- * SA_F64, float for SA_F32), computed in the factor precision.  Wall
- * entries of r are ignored and those of z are 0.  Errors: SA_ESTATE
- * before setup, SA_EINVAL. */
+/* z = P M(shift ishift)^{-1} r for nrhs vectors (double for SA_F64, float
+ * for SA_F32): M the block diagonal of the block-Jacobi blocks, applied in
+ * the factor precision, or the mean-flow operator (forward transforms,
+ * banded substitutions with the factors converted to the vector precision,
+ * inverse transforms; at most nshift vectors per call).  Wall entries of r
+ * are ignored and those of z are 0.  Errors: SA_ESTATE before setup,
+ * SA_EINVAL. */
 int sa_precond_apply(sa_ctx *ctx, sa_prec prec, int ishift, int nrhs, const void *r_dev,
                      void *z_dev);
 

@@ -55,9 +55,13 @@ class GmresInfo(C.Structure):
                 ("status", C.c_int)]
 
 
+SA_PC_BLOCK_JACOBI, SA_PC_MEAN_FLOW = 0, 1
+
+
 class PrecondOpts(C.Structure):
     _fields_ = [("bx", C.c_int), ("by", C.c_int), ("bz", C.c_int), ("diag_add", C.c_double),
-                ("noise_std", C.c_double), ("seed", C.c_ulonglong), ("factor_prec", C.c_int)]
+                ("noise_std", C.c_double), ("seed", C.c_ulonglong), ("factor_prec", C.c_int),
+                ("kind", C.c_int)]
 
 
 class EigOpts(C.Structure):
@@ -216,8 +220,9 @@ class Context:
         return v, {n: float(t[i]) for i, n in enumerate(JV_VARIANTS)}
 
     def precond_setup(self, shifts, bx=4, by=4, bz=1, diag_add=0.1, noise_std=0.01, seed=3,
-                      factor_prec=SA_F32):
-        o = PrecondOpts(bx, by, bz, diag_add, noise_std, seed, factor_prec)
+                      factor_prec=SA_F32, kind=SA_PC_BLOCK_JACOBI):
+        """kind: SA_PC_BLOCK_JACOBI (the block fields apply) or SA_PC_MEAN_FLOW."""
+        o = PrecondOpts(bx, by, bz, diag_add, noise_std, seed, factor_prec, kind)
         arr = (C.c_double * len(shifts))(*shifts)
         self._pc = False
         rc = self._err(self.lib.sa_precond_setup(self.h, C.byref(o), len(shifts), arr))

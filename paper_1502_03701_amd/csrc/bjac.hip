@@ -614,6 +614,7 @@ inline unsigned blocks_for(long long n, int threads) { return (unsigned)((n + th
 template <typename R>
 hipError_t precond_apply(Ctx* c, int ishift, int nrhs, const R* r, R* z, const int* active, int shift_step,
                          long long sV, long long sA, hipStream_t s) {
+  if (c->pc_kind == SA_PC_MEAN_FLOW) return fourier_apply<R>(c, ishift, nrhs, r, z, active, shift_step, sV, sA, s);
   BLayout L = layout_of(c);
   dim3 grid((unsigned)((L.nblocks + 63) / 64), (unsigned)nrhs);
   if (sV == 0) sV = c->n;
@@ -638,6 +639,18 @@ extern "C" int sa_precond_setup(sa_ctx* c, const sa_precond_opts* o, int nshift,
   if (!c) return SA_EINVAL;
   if (!c->has_base) return c->fail(SA_ESTATE, "sa_precond_setup: call sa_base_set first");
   if (!o || !shifts_host || nshift < 1) return c->fail(SA_EINVAL, "sa_precond_setup: null argument or nshift < 1");
+  if (o->kind != SA_PC_BLOCK_JACOBI && o->kind != SA_PC_MEAN_FLOW)
+    return c->fail(SA_EINVAL, "sa_precond_setup: bad preconditioner kind %d", o->kind);
+  if (o->kind == SA_PC_MEAN_FLOW) {
+    c->has_precond = false;
+    c->drop_graphs();
+    const int rc = fourier_setup(c, o, nshift, shifts_host);
+    if (rc != SA_OK) return rc;
+    c->pc_kind = SA_PC_MEAN_FLOW;
+    c->pc_nshift = nshift;
+    c->has_precond = true;
+    return SA_OK;
+  }
   const int bz = c->op.ndim == 2 ? 1 : o->bz;
   if (o->bx < 1 || o->by < 1 || bz < 1) return c->fail(SA_EINVAL, "sa_precond_setup: bad block size");
   if (c->op.nx % o->bx || c->op.ny % o->by || c->op.nz % bz)
@@ -725,6 +738,7 @@ extern "C" int sa_precond_setup(sa_ctx* c, const sa_precond_opts* o, int nshift,
   c->pc_lu = LU;
   c->pc_perm = perm;
   c->pc_f64 = o->factor_prec == SA_F64;
+  c->pc_kind = SA_PC_BLOCK_JACOBI;
   c->pc_nshift = nshift;
   c->pc_nb = L.nb;
   c->pc_nblocks = L.nblocks;
@@ -737,6 +751,9 @@ extern "C" int sa_precond_apply(sa_ctx* c, sa_prec prec, int ishift, int nrhs, c
   if (!c->has_precond) return c->fail(SA_ESTATE, "sa_precond_apply: call sa_precond_setup first");
   if (ishift < 0 || ishift >= c->pc_nshift || nrhs < 1 || !r_dev || !z_dev)
     return c->fail(SA_EINVAL, "sa_precond_apply: bad shift index, nrhs or pointer");
+  if (c->pc_kind == SA_PC_MEAN_FLOW && nrhs > c->fp_nrhs_cap)
+    return c->fail(SA_EINVAL, "sa_precond_apply: the mean-flow preconditioner takes at most %d vectors per call",
+                   c->fp_nrhs_cap);
   hipError_t e;
   if (prec == SA_F64)
     e = precond_apply<double>(c, ishift, nrhs, (const double*)r_dev, (double*)z_dev, nullptr, 0, 0, 0, c->stream);

@@ -163,6 +163,9 @@ __global__ void __launch_bounds__(RED_THREADS) multidot_kernel(long long n, cons
 
 // w_new = w + hsign * sum_c V[c] h[c]; writes w_new to wout (may alias w).
 // norm: partial ||w_new||^2 in column 0.  The coefficients sit in LDS.
+// Columns after the last non-zero coefficient are not read: a GMRES cycle
+// that ends early leaves its later basis columns unwritten (stale, possibly
+// non-finite), and its solution update passes zeros for them.
 template <typename R, int MAXC, int E, bool NT>
 __global__ void __launch_bounds__(RED_THREADS) update_kernel(
     long long n, const R* __restrict__ V, long long ldv, int ncol, const double* __restrict__ h, double hsign,
@@ -176,8 +179,17 @@ __global__ void __launch_bounds__(RED_THREADS) update_kernel(
   h += sys * sR;
   partial += sys * sP;
   __shared__ double hc[MAXC];
+  __shared__ int s_nc;
   for (int c = threadIdx.x; c < MAXC; c += blockDim.x) hc[c] = c < ncol ? hsign * h[c] : 0.0;
   __syncthreads();
+  if (threadIdx.x == 0) {
+    int last = 0;
+    for (int c = 0; c < ncol; ++c)
+      if (hc[c] != 0.0) last = c + 1;
+    s_nc = last;
+  }
+  __syncthreads();
+  const int nc = s_nc;
   double acc[1] = {0.0};
   const long long nch = n / E;
   const long long stride = (long long)gridDim.x * blockDim.x;
@@ -189,7 +201,7 @@ __global__ void __launch_bounds__(RED_THREADS) update_kernel(
 #pragma unroll
     for (int q = 0; q < E; ++q) sum[q] = (double)wv[q];
 #pragma unroll 8
-    for (int c = 0; c < ncol; ++c) {
+    for (int c = 0; c < nc; ++c) {
       R v[E];
       vload<R, E, NT>(V + (long long)c * ldv + k * E, v);
 #pragma unroll

@@ -1,0 +1,656 @@
+// Mean-flow preconditioner (Section "Preconditioning"; the Conclusions'
+// direction of a cheaper approximate operator): M(s) = P (J(q_bar) - s I) P,
+// the operator of the base state averaged over the periodic axes,
+// q_bar(y) = mean over x (and z) of q0, solved exactly.
+//
+// For q_bar the discrete operator commutes with shifts along x and z, so it
+// is block diagonal in their Fourier modes; each mode's block couples y rows
+// only within the stencil reach (3), i.e. it is banded with kl = ku =
+// 4 nv - 1 in the unknown order u = (j-1) nv + v (interior rows j = 1 ..
+// ny-2).  Setup:
+//   * q_bar and its base-derivative data (the same kernels as sa_base_set);
+//   * the operator's columns by probing: 7 y-colours x nv variables, each
+//     probe a unit at (x = 0, z = 0) on every interior row of its colour
+//     (rows 7 apart, beyond the reach), nv probes per operator launch; the
+//     responses at x, z offsets -3..3 give every band entry's stencil
+//     coefficients S[u][b][dz][dx];
+//   * per (mode, shift) one wavefront builds the mode's rows on the fly,
+//     A_k[u][u'] = sum_{dx,dz} S[u][b][dz][dx] e^{-i(kx dx 2pi/nx + kz dz 2pi/nz)}
+//     - s delta, and factors them by banded LU with partial pivoting in a
+//     sliding (kl+1) x (kl+ku+1) window in LDS: U rows (kl+ku+1 entries),
+//     L multipliers (kl) and pivot offsets are written per step.
+// Apply z = M(s)^{-1} r: real-to-complex DFT along x (and a complex DFT along
+// z), one wavefront per (mode, system) for the banded forward and back
+// substitutions with the mode's vector in LDS, the inverse transforms, and
+// zero wall rows.  The DFTs are direct sums with twiddle tables in LDS
+// (x lines) or LDS-staged tiles (z lines), which serves every grid size.
+#include <cmath>
+#include <vector>
+
+#include "sa_runtime.h"
+
+namespace sa {
+namespace {
+
+template <typename T>
+struct cx {
+  T re, im;
+};
+
+constexpr int REACH = 3;
+constexpr int NOFF = 2 * REACH + 1;   // offsets -3 .. 3
+constexpr int NCOL = 7;               // y colours of the probes (> 2 REACH)
+constexpr size_t LDS_CAP = 65536;     // dynamic LDS a launch of this file may take
+
+struct FGeom {
+  int nd, nv, nx, ny, nz;
+  int mx, mz, nmodes;   // modes: kx = 0 .. mx-1 (real DFT), kz = 0 .. mz-1
+  int N, kl, ku, KW;    // unknowns per mode, bandwidths, window width
+  long long npts, n;
+};
+
+FGeom geom_of(const Ctx* c) {
+  FGeom g{};
+  g.nd = c->op.ndim;
+  g.nv = c->nv;
+  g.nx = c->op.nx;
+  g.ny = c->op.ny;
+  g.nz = c->op.nz;
+  g.mx = g.nx / 2 + 1;
+  g.mz = g.nd == 3 ? g.nz : 1;
+  g.nmodes = g.mx * g.mz;
+  g.N = (g.ny - 2) * g.nv;
+  g.kl = g.ku = REACH * g.nv + g.nv - 1;
+  g.KW = g.kl + g.ku + 1;
+  g.npts = c->op.npts;
+  g.n = c->n;
+  return g;
+}
+
+// ---------------------------------------------------------------- setup ----
+
+// q_bar: one workgroup per (variable, row) sums q0 over x and z in a fixed
+// order and writes the mean to every point of that (variable, row)
+__global__ void __launch_bounds__(256) mean_base_kernel(FGeom g, const double* __restrict__ q0,
+                                                        double* __restrict__ qbar) {
+  const int v = blockIdx.x / g.ny, j = blockIdx.x % g.ny;
+  const int nxz = g.nx * g.nz;
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int t = threadIdx.x; t < nxz; t += 256) {
+    const int k = t / g.nx, i = t % g.nx;
+    acc += q0[(((long long)v * g.nz + k) * g.ny + j) * g.nx + i];
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double mean = red[0] / (double)nxz;
+  for (int t = threadIdx.x; t < nxz; t += 256) {
+    const int k = t / g.nx, i = t % g.nx;
+    qbar[(((long long)v * g.nz + k) * g.ny + j) * g.nx + i] = mean;
+  }
+}
+
+// probes of colour c: vector v' has 1 at (x = 0, z = 0, row j, variable v')
+// for every interior row j = c (mod 7)
+__global__ void probe_kernel(FGeom g, int c, double* __restrict__ P) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nrow = g.ny - 2;
+  if (t >= g.nv * nrow) return;
+  const int vp = t / nrow, j = 1 + t % nrow;
+  if (j % NCOL != c) return;
+  P[(long long)vp * g.n + (((long long)vp * g.nz + 0) * g.ny + j) * g.nx + 0] = 1.0;
+}
+
+// stencil coefficients S[u][b][dz][dx] of the band entries whose column row
+// j' has colour c, from the responses Y[v'] of that colour's probes
+__global__ void gather_kernel(FGeom g, int c, const double* __restrict__ Y, double* __restrict__ S) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long tot = (long long)g.N * g.KW * NOFF * NOFF;
+  if (t >= tot) return;
+  const int dx = (int)(t % NOFF) - REACH;
+  const int dz = (int)((t / NOFF) % NOFF) - REACH;
+  const int b = (int)((t / (NOFF * NOFF)) % g.KW);
+  const int u = (int)(t / ((long long)NOFF * NOFF * g.KW));
+  const int up = u - g.kl + b;
+  if (up < 0 || up >= g.N) {
+    if (c == 0) S[t] = 0.0;   // outside the matrix: written once
+    return;
+  }
+  const int j = 1 + u / g.nv, v = u % g.nv;
+  const int jp = 1 + up / g.nv, vp = up % g.nv;
+  if (jp % NCOL != c) return;
+  double val = 0.0;
+  const bool zok = g.nd == 3 || dz == 0;
+  if (zok && abs(j - jp) <= REACH) {
+    const int ii = (dx + g.nx) % g.nx, kk = g.nd == 3 ? (dz + g.nz) % g.nz : 0;
+    val = Y[(long long)vp * g.n + (((long long)v * g.nz + kk) * g.ny + j) * g.nx + ii];
+  }
+  S[t] = val;
+}
+
+// Band LU with partial pivoting of A_k - s I for one (mode, shift) per
+// wavefront.  Window W: logical row i (matrix row col + i) at physical row
+// (r0 + i) % KH, logical column jj (matrix column col + jj) at physical
+// column (c0 + jj) % KW.  Factor layout per (shift, mode): U[u][0 .. KW),
+// U[u][d] = U(u, u + d); L[u][0 .. kl), the multiplier of row u + 1 + d at
+// step u; piv[u] in [0, kl], row u exchanged with row u + piv[u].
+template <typename F>
+__global__ void __launch_bounds__(64) band_lu_kernel(FGeom g, const double* __restrict__ S,
+                                                     const double* __restrict__ shifts, cx<F>* __restrict__ Uo,
+                                                     cx<F>* __restrict__ Lo, int* __restrict__ pivo,
+                                                     int* __restrict__ singular) {
+  constexpr int MAXKH = 4 * 5;        // kl + 1 <= 4 nv <= 20
+  constexpr int MAXKW = 2 * 4 * 5 - 1;   // kl + ku + 1 <= 39
+  __shared__ cx<F> W[MAXKH][MAXKW];
+  __shared__ cx<F> lw[MAXKH];
+  const int lane = threadIdx.x;
+  const int m = blockIdx.x % g.nmodes, s = blockIdx.x / g.nmodes;
+  const int kx = m % g.mx, kz = m / g.mx;
+  const double sig = shifts[s];
+  const int kl = g.kl, KW = g.KW, KH = g.kl + 1, N = g.N;
+  // twiddles e^{-i theta d}, d = -3 .. 3
+  double exr[NOFF], exi[NOFF], ezr[NOFF], ezi[NOFF];
+#pragma unroll
+  for (int d = 0; d < NOFF; ++d) {
+    const double ax = -2.0 * M_PI * (double)kx * (double)(d - REACH) / (double)g.nx;
+    exr[d] = cos(ax);
+    exi[d] = sin(ax);
+    const double az = g.nd == 3 ? -2.0 * M_PI * (double)kz * (double)(d - REACH) / (double)g.nz : 0.0;
+    ezr[d] = cos(az);
+    ezi[d] = sin(az);
+  }
+  const long long fo = (long long)s * g.nmodes + m;
+  cx<F>* U = Uo + fo * (long long)N * KW;
+  cx<F>* L = Lo + fo * (long long)N * kl;
+  int* piv = pivo + fo * (long long)N;
+  // entry (u, col + jj) of A_k - s I into physical W[pr][(c0 + jj) % KW], one column per lane
+  auto gen_row = [&](int u, int col, int pr, int c0) {
+    for (int jj = lane; jj < KW; jj += 64) {
+      const int b = col + jj - u + kl;
+      const int up = col + jj;
+      double vr = 0.0, vi = 0.0;
+      if (u < N && up < N && b >= 0 && b < KW) {
+        const double* Sb = S + ((long long)u * KW + b) * NOFF * NOFF;
+        const int z0 = g.nd == 3 ? 0 : REACH, z1 = g.nd == 3 ? NOFF : REACH + 1;
+        for (int dz = z0; dz < z1; ++dz) {
+          double sr = 0.0, si = 0.0;
+#pragma unroll
+          for (int dx = 0; dx < NOFF; ++dx) {
+            const double c = Sb[dz * NOFF + dx];
+            sr += c * exr[dx];
+            si += c * exi[dx];
+          }
+          vr += sr * ezr[dz] - si * ezi[dz];
+          vi += sr * ezi[dz] + si * ezr[dz];
+        }
+        if (b == kl) vr -= sig;
+      }
+      W[pr][(c0 + jj) % KW] = cx<F>{(F)vr, (F)vi};
+    }
+  };
+  int r0 = 0, c0 = 0;
+  for (int i = 0; i < KH; ++i) gen_row(i, 0, i, 0);
+  __syncthreads();
+  bool sing = false;
+  for (int col = 0; col < N; ++col) {
+    const int imax = min(kl, N - 1 - col);
+    // pivot: first largest |re| + |im| among the window's first column
+    F best = F(-1);
+    int bi = 0;
+    if (lane <= imax) {
+      const cx<F> a = W[(r0 + lane) % KH][c0];
+      best = fabs(a.re) + fabs(a.im);
+      bi = lane;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const F ob = __shfl_xor(best, off, 64);
+      const int oi = __shfl_xor(bi, off, 64);
+      if (ob > best || (ob == best && oi < bi)) {
+        best = ob;
+        bi = oi;
+      }
+    }
+    const int p = bi;
+    if (!(best > F(0))) sing = true;
+    // exchange logical rows 0 and p
+    if (p != 0) {
+      for (int jj = lane; jj < KW; jj += 64) {
+        const int pc = (c0 + jj) % KW;
+        const cx<F> t0 = W[r0 % KH][pc];
+        W[r0 % KH][pc] = W[(r0 + p) % KH][pc];
+        W[(r0 + p) % KH][pc] = t0;
+      }
+    }
+    __syncthreads();
+    const cx<F> pv = W[r0 % KH][c0];
+    const F den = pv.re * pv.re + pv.im * pv.im;
+    // multipliers l_i = a_i0 / pivot, and the U row
+    if (lane >= 1 && lane <= kl) {
+      cx<F> l{F(0), F(0)};
+      if (lane <= imax && den > F(0)) {
+        const cx<F> a = W[(r0 + lane) % KH][c0];
+        l.re = (a.re * pv.re + a.im * pv.im) / den;
+        l.im = (a.im * pv.re - a.re * pv.im) / den;
+      }
+      lw[lane] = l;
+      L[(long long)col * kl + lane - 1] = l;
+    }
+    for (int jj = lane; jj < KW; jj += 64) U[(long long)col * KW + jj] = W[r0 % KH][(c0 + jj) % KW];
+    if (lane == 0) piv[col] = p;
+    __syncthreads();
+    // trailing update of the window: W[i][jj] -= l_i W[0][jj]
+    const int nupd = kl * (KW - 1);
+    for (int e = lane; e < nupd; e += 64) {
+      const int i = 1 + e / (KW - 1), jj = 1 + e % (KW - 1);
+      const int pc = (c0 + jj) % KW;
+      const cx<F> u0 = W[r0 % KH][pc];
+      const cx<F> l = lw[i];
+      cx<F>& w = W[(r0 + i) % KH][pc];
+      w.re -= l.re * u0.re - l.im * u0.im;
+      w.im -= l.re * u0.im + l.im * u0.re;
+    }
+    __syncthreads();
+    // slide: the consumed column becomes the last one (zero for the rows
+    // already in the window) and the pivot row's slot takes row col+kl+1
+    const int oldc = c0, oldr = r0 % KH;
+    c0 = (c0 + 1) % KW;
+    r0 = r0 + 1;
+    if (lane < kl) W[(r0 + lane) % KH][oldc] = cx<F>{F(0), F(0)};
+    gen_row(col + 1 + kl, col + 1, oldr, c0);
+    __syncthreads();
+  }
+  if (sing && lane == 0) atomicOr(singular, 1);
+}
+
+// ---------------------------------------------------------------- apply ----
+
+// Forward real DFT along x of the interior rows: one workgroup per (line,
+// system), line = (k, j, v); out[sys][k][kx][u] (2D: the spectrum itself).
+template <typename R>
+__global__ void __launch_bounds__(256) dft_x_fwd(FGeom g, const R* __restrict__ r, long long sV,
+                                                 const cx<R>* __restrict__ tw, cx<R>* __restrict__ out,
+                                                 const int* __restrict__ active, long long sA) {
+  extern __shared__ unsigned char smem[];
+  cx<R>* stw = reinterpret_cast<cx<R>*>(smem);
+  R* line = reinterpret_cast<R*>(stw + g.nx);
+  const int sys = blockIdx.y;
+  if (active && !active[sys * sA]) return;
+  const int nrow = g.ny - 2;
+  const int lid = blockIdx.x;   // (k, jrow, v)
+  const int v = lid % g.nv, jr = (lid / g.nv) % nrow, k = lid / (g.nv * nrow);
+  const int j = jr + 1;
+  const int u = jr * g.nv + v;
+  const R* src = r + (long long)sys * sV + (((long long)v * g.nz + k) * g.ny + j) * g.nx;
+  for (int i = threadIdx.x; i < g.nx; i += 256) {
+    stw[i] = tw[i];
+    line[i] = src[i];
+  }
+  __syncthreads();
+  cx<R>* dst = out + ((long long)sys * g.nz + k) * (long long)g.mx * g.N;
+  for (int kxx = threadIdx.x; kxx < g.mx; kxx += 256) {
+    R ar = R(0), ai = R(0);
+    int idx = 0;
+    for (int i = 0; i < g.nx; ++i) {
+      const cx<R> w = stw[idx];
+      ar += line[i] * w.re;
+      ai += line[i] * w.im;
+      idx += kxx;
+      if (idx >= g.nx) idx -= g.nx;
+    }
+    dst[(long long)kxx * g.N + u] = cx<R>{ar, ai};
+  }
+}
+
+// Complex DFT along z between in[sys][k][kx][u] and out[sys][kz][kx][u]
+// (sign -1 forward, +1 inverse), a workgroup per (kx, ub consecutive u):
+// the nz x ub input tile in LDS, each output a sum over k.
+template <typename R>
+__global__ void __launch_bounds__(256) dft_z(FGeom g, const cx<R>* __restrict__ in, const cx<R>* __restrict__ tw,
+                                             int inverse, int ub, cx<R>* __restrict__ out,
+                                             const int* __restrict__ active, long long sA) {
+  extern __shared__ unsigned char smem[];
+  cx<R>* stw = reinterpret_cast<cx<R>*>(smem);
+  cx<R>* tile = stw + g.nz;
+  const int sys = blockIdx.y;
+  if (active && !active[sys * sA]) return;
+  const int nub = (g.N + ub - 1) / ub;
+  const int kxx = blockIdx.x / nub;
+  const int u0 = (blockIdx.x % nub) * ub;
+  const long long plane = (long long)g.mx * g.N;
+  const cx<R>* src = in + (long long)sys * g.nz * plane;
+  cx<R>* dst = out + (long long)sys * g.nz * plane;
+  for (int t = threadIdx.x; t < g.nz; t += 256) stw[t] = tw[t];
+  for (int t = threadIdx.x; t < g.nz * ub; t += 256) {
+    const int k = t / ub, uu = t % ub;
+    const int u = u0 + uu;
+    tile[t] = u < g.N ? src[(long long)k * plane + (long long)kxx * g.N + u] : cx<R>{R(0), R(0)};
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < g.nz * ub; t += 256) {
+    const int kz = t / ub, uu = t % ub;
+    const int u = u0 + uu;
+    if (u >= g.N) continue;
+    R ar = R(0), ai = R(0);
+    int idx = 0;
+    for (int k = 0; k < g.nz; ++k) {
+      const cx<R> w = stw[idx];              // e^{-2 pi i idx / nz}
+      const R ci = inverse ? -w.im : w.im;   // conjugate for the inverse
+      const cx<R> a = tile[k * ub + uu];
+      ar += a.re * w.re - a.im * ci;
+      ai += a.re * ci + a.im * w.re;
+      idx += kz;
+      if (idx >= g.nz) idx -= g.nz;
+    }
+    dst[(long long)kz * plane + (long long)kxx * g.N + u] = cx<R>{ar, ai};
+  }
+}
+
+// Inverse real DFT along x (complex-to-real) into the SoA vector, scaled by
+// 1/(nx nz); wall rows of z are written 0 by zero_walls.
+template <typename R>
+__global__ void __launch_bounds__(256) dft_x_inv(FGeom g, const cx<R>* __restrict__ in, const cx<R>* __restrict__ tw,
+                                                 R* __restrict__ z, long long sV, const int* __restrict__ active,
+                                                 long long sA) {
+  extern __shared__ unsigned char smem[];
+  cx<R>* stw = reinterpret_cast<cx<R>*>(smem);
+  cx<R>* spec = stw + g.nx;
+  const int sys = blockIdx.y;
+  if (active && !active[sys * sA]) return;
+  const int nrow = g.ny - 2;
+  const int lid = blockIdx.x;
+  const int v = lid % g.nv, jr = (lid / g.nv) % nrow, k = lid / (g.nv * nrow);
+  const int j = jr + 1;
+  const int u = jr * g.nv + v;
+  const cx<R>* src = in + ((long long)sys * g.nz + k) * (long long)g.mx * g.N;
+  for (int t = threadIdx.x; t < g.nx; t += 256) stw[t] = tw[t];
+  for (int t = threadIdx.x; t < g.mx; t += 256) spec[t] = src[(long long)t * g.N + u];
+  __syncthreads();
+  const R scale = R(1) / (R(g.nx) * R(g.nz));
+  const bool even = g.nx % 2 == 0;
+  R* dst = z + (long long)sys * sV + (((long long)v * g.nz + k) * g.ny + j) * g.nx;
+  for (int i = threadIdx.x; i < g.nx; i += 256) {
+    R acc = spec[0].re;
+    int idx = 0;
+    for (int kxx = 1; kxx < g.mx; ++kxx) {
+      idx += i;
+      if (idx >= g.nx) idx -= g.nx;
+      const cx<R> w = stw[idx];   // e^{-2 pi i kx i / nx}; the inverse uses its conjugate
+      const cx<R> a = spec[kxx];
+      const R re = a.re * w.re + a.im * w.im;   // Re(a conj(w))
+      acc += (even && kxx == g.mx - 1) ? re : R(2) * re;
+    }
+    dst[i] = acc * scale;
+  }
+}
+
+template <typename R>
+__global__ void zero_walls(FGeom g, R* __restrict__ z, long long sV, const int* __restrict__ active, long long sA) {
+  const int sys = blockIdx.y;
+  if (active && !active[sys * sA]) return;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long per = (long long)g.nv * g.nz * 2 * g.nx;
+  if (t >= per) return;
+  const int i = (int)(t % g.nx);
+  const int w = (int)((t / g.nx) % 2);
+  const long long vk = t / (2LL * g.nx);   // v * nz + k
+  const int j = w ? g.ny - 1 : 0;
+  z[(long long)sys * sV + (vk * g.ny + j) * g.nx + i] = R(0);
+}
+
+// Banded forward and back substitution of one (mode, system) per wavefront,
+// the mode's vector in LDS.  System sys uses the factors of shift
+// shift0 + sys * shift_step.
+template <typename F, typename R>
+__global__ void __launch_bounds__(64) band_solve_kernel(FGeom g, const cx<F>* __restrict__ Uo,
+                                                        const cx<F>* __restrict__ Lo, const int* __restrict__ pivo,
+                                                        int shift0, int shift_step, cx<R>* __restrict__ spec,
+                                                        const int* __restrict__ active, long long sA) {
+  extern __shared__ unsigned char smem[];
+  cx<R>* Z = reinterpret_cast<cx<R>*>(smem);
+  const int m = blockIdx.x, sys = blockIdx.y;
+  if (active && !active[sys * sA]) return;
+  const int lane = threadIdx.x;
+  const int N = g.N, kl = g.kl, KW = g.KW;
+  const long long fo = (long long)(shift0 + sys * shift_step) * g.nmodes + m;
+  const cx<F>* U = Uo + fo * (long long)N * KW;
+  const cx<F>* L = Lo + fo * (long long)N * kl;
+  const int* piv = pivo + fo * (long long)N;
+  cx<R>* vec = spec + ((long long)sys * g.nmodes + m) * N;   // mode m = kz mx + kx
+  for (int u = lane; u < N; u += 64) Z[u] = vec[u];
+  __syncthreads();
+  // forward: P, then L (unit lower, kl multipliers per column)
+  for (int col = 0; col < N; ++col) {
+    const int p = piv[col];
+    if (p != 0 && lane == 0) {
+      const cx<R> t0 = Z[col];
+      Z[col] = Z[col + p];
+      Z[col + p] = t0;
+    }
+    __syncthreads();
+    const cx<R> zc = Z[col];
+    if (lane >= 1 && lane <= kl && col + lane < N) {
+      const cx<F> l = L[(long long)col * kl + lane - 1];
+      cx<R>& w = Z[col + lane];
+      w.re -= (R)l.re * zc.re - (R)l.im * zc.im;
+      w.im -= (R)l.re * zc.im + (R)l.im * zc.re;
+    }
+    __syncthreads();
+  }
+  // back: z_col = (z_col - sum_{d>=1} U[col][d] z_{col+d}) / U[col][0]
+  for (int col = N - 1; col >= 0; --col) {
+    R sr = R(0), si = R(0);
+    if (lane >= 1 && lane < KW && col + lane < N) {
+      const cx<F> a = U[(long long)col * KW + lane];
+      const cx<R> zz = Z[col + lane];
+      sr = (R)a.re * zz.re - (R)a.im * zz.im;
+      si = (R)a.re * zz.im + (R)a.im * zz.re;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      sr += __shfl_xor(sr, off, 64);
+      si += __shfl_xor(si, off, 64);
+    }
+    if (lane == 0) {
+      const cx<F> d = U[(long long)col * KW];
+      const R dr = (R)d.re, di = (R)d.im;
+      const R den = dr * dr + di * di;
+      const R nr = Z[col].re - sr, ni = Z[col].im - si;
+      Z[col] = den > R(0) ? cx<R>{(nr * dr + ni * di) / den, (ni * dr - nr * di) / den} : cx<R>{R(0), R(0)};
+    }
+    __syncthreads();
+  }
+  for (int u = lane; u < N; u += 64) vec[u] = Z[u];
+}
+
+template <typename R>
+const cx<R>* twx_of(const Ctx* c);
+template <>
+const cx<double>* twx_of<double>(const Ctx* c) {
+  return reinterpret_cast<const cx<double>*>(c->fp_twx64);
+}
+template <>
+const cx<float>* twx_of<float>(const Ctx* c) {
+  return reinterpret_cast<const cx<float>*>(c->fp_twx32);
+}
+template <typename R>
+const cx<R>* twz_of(const Ctx* c);
+template <>
+const cx<double>* twz_of<double>(const Ctx* c) {
+  return reinterpret_cast<const cx<double>*>(c->fp_twz64);
+}
+template <>
+const cx<float>* twz_of<float>(const Ctx* c) {
+  return reinterpret_cast<const cx<float>*>(c->fp_twz32);
+}
+
+}  // namespace
+
+// Workspace of the apply for nrhs systems: the spectrum and, in 3D, the
+// x-transformed planes (complex, precision R).
+size_t fourier_spec_bytes(const Ctx* c, int nrhs, size_t es) {
+  const FGeom g = geom_of(c);
+  return (size_t)nrhs * g.nz * g.mx * g.N * 2 * es;
+}
+
+template <typename R>
+hipError_t fourier_apply(Ctx* c, int ishift, int nrhs, const R* r, R* z, const int* active, int shift_step,
+                         long long sV, long long sA, hipStream_t s) {
+  const FGeom g = geom_of(c);
+  if (sV == 0) sV = c->n;
+  const size_t es = sizeof(R);
+  if (nrhs > c->fp_nrhs_cap) return hipErrorInvalidValue;
+  cx<R>* A = reinterpret_cast<cx<R>*>(es == 8 ? c->fp_specA64 : c->fp_specA32);
+  cx<R>* B = reinterpret_cast<cx<R>*>(es == 8 ? c->fp_specB64 : c->fp_specB32);
+  const cx<R>* tx = twx_of<R>(c);
+  const cx<R>* tz = twz_of<R>(c);
+  const int nlines = g.nz * (g.ny - 2) * g.nv;
+  const dim3 gl((unsigned)nlines, (unsigned)nrhs);
+  // forward: x (into A), then z (A -> B) in 3D
+  dft_x_fwd<R><<<gl, 256, g.nx * sizeof(cx<R>) + g.nx * es, s>>>(g, r, sV, tx, A, active, sA);
+  cx<R>* spec = A;
+  // z tiles of ub u-columns, the tile and the twiddles within 64 KiB of LDS
+  int ub = 32;
+  while (ub > 1 && (size_t)g.nz * (ub + 1) * sizeof(cx<R>) > LDS_CAP) ub /= 2;
+  const unsigned nzb = (unsigned)(g.mx * ((g.N + ub - 1) / ub));
+  const size_t zlds = (size_t)g.nz * (ub + 1) * sizeof(cx<R>);
+  if (g.nd == 3) {
+    dft_z<R><<<dim3(nzb, (unsigned)nrhs), 256, zlds, s>>>(g, A, tz, 0, ub, B, active, sA);
+    spec = B;
+  }
+  const size_t lds = (size_t)g.N * sizeof(cx<R>);
+  if (c->fp_f64)
+    band_solve_kernel<double, R><<<dim3((unsigned)g.nmodes, (unsigned)nrhs), 64, lds, s>>>(
+        g, (const cx<double>*)c->fp_U, (const cx<double>*)c->fp_L, c->fp_piv, ishift, shift_step, spec, active, sA);
+  else
+    band_solve_kernel<float, R><<<dim3((unsigned)g.nmodes, (unsigned)nrhs), 64, lds, s>>>(
+        g, (const cx<float>*)c->fp_U, (const cx<float>*)c->fp_L, c->fp_piv, ishift, shift_step, spec, active, sA);
+  cx<R>* xin = spec;
+  if (g.nd == 3) {
+    dft_z<R><<<dim3(nzb, (unsigned)nrhs), 256, zlds, s>>>(g, B, tz, 1, ub, A, active, sA);
+    xin = A;
+  }
+  dft_x_inv<R><<<gl, 256, (size_t)(g.nx + g.mx) * sizeof(cx<R>), s>>>(g, xin, tx, z, sV, active, sA);
+  const long long per = (long long)g.nv * g.nz * 2 * g.nx;
+  zero_walls<R><<<dim3((unsigned)((per + 255) / 256), (unsigned)nrhs), 256, 0, s>>>(g, z, sV, active, sA);
+  return hipGetLastError();
+}
+template hipError_t fourier_apply<double>(Ctx*, int, int, const double*, double*, const int*, int, long long,
+                                          long long, hipStream_t);
+template hipError_t fourier_apply<float>(Ctx*, int, int, const float*, float*, const int*, int, long long, long long,
+                                         hipStream_t);
+
+int fourier_setup(Ctx* c, const sa_precond_opts* o, int nshift, const double* shifts_host) {
+  if (c->op.bcy != 1) return c->fail(SA_EINVAL, "sa_precond_setup: the mean-flow preconditioner needs walls in y");
+  if (o->factor_prec != SA_F32 && o->factor_prec != SA_F64)
+    return c->fail(SA_EINVAL, "sa_precond_setup: factor precision must be SA_F32 or SA_F64");
+  const FGeom g = geom_of(c);
+  // the probes' responses must not wrap onto each other along x and z, and
+  // a mode's vector (complex FP64) and the x lines must fit in LDS
+  if (g.nx < NOFF || (g.nd == 3 && g.nz < NOFF) || g.ny - 2 < 1)
+    return c->fail(SA_EINVAL, "sa_precond_setup: the mean-flow preconditioner needs nx, nz >= %d", NOFF);
+  if ((size_t)g.N * sizeof(cx<double>) > LDS_CAP || (size_t)g.nx * 3 * sizeof(double) > LDS_CAP ||
+      (size_t)g.nz * 2 * sizeof(cx<double>) > LDS_CAP)
+    return c->fail(SA_EINVAL, "sa_precond_setup: grid too large for the mean-flow preconditioner");
+  if (c->nv > 5) return c->fail(SA_EINVAL, "sa_precond_setup: at most 5 variables");
+  hipStream_t s = c->stream;
+  const long long n = c->n, np = c->op.npts;
+  const int nv = c->nv;
+  // q_bar with its pointwise fields and base-derivative data
+  double* qb = (double*)c->buffer("fp_qbar", sizeof(double) * (size_t)(nv + 3) * np, false);
+  float* qb32 = (float*)c->buffer("fp_qbar32", sizeof(float) * (size_t)(nv + 3) * np, false);
+  double* bd = (double*)c->buffer("fp_bdata", sizeof(double) * (size_t)base_data_fields(g.nd) * np, false);
+  // zero_fill writes whole 16-byte words: the buffers it clears are padded
+  int* flag = (int*)c->buffer("fp_flag", 16, false);
+  double* P = (double*)c->buffer("fp_probe", sizeof(double) * (size_t)nv * n + 16, false);
+  double* Y = (double*)c->buffer("fp_resp", sizeof(double) * (size_t)nv * n, false);
+  const size_t nS = (size_t)g.N * g.KW * NOFF * NOFF;
+  double* S = (double*)c->buffer("fp_stencil", sizeof(double) * nS + 16, false);
+  double* sh = (double*)c->buffer("fp_shifts", sizeof(double) * nshift, false);
+  const size_t fs = o->factor_prec == SA_F64 ? sizeof(double) : sizeof(float);
+  const size_t nfac = (size_t)nshift * g.nmodes * g.N;
+  void* Uf = c->buffer("fp_U", 2 * fs * nfac * g.KW, false);
+  void* Lf = c->buffer("fp_L", 2 * fs * nfac * g.kl, false);
+  int* pv = (int*)c->buffer("fp_piv", sizeof(int) * nfac, false);
+  const int cap = nshift > 1 ? nshift : 1;
+  void* A64 = c->buffer("fp_specA64", fourier_spec_bytes(c, cap, 8), false);
+  void* B64 = c->buffer("fp_specB64", fourier_spec_bytes(c, cap, 8), false);
+  void* A32 = c->buffer("fp_specA32", fourier_spec_bytes(c, cap, 4), false);
+  void* B32 = c->buffer("fp_specB32", fourier_spec_bytes(c, cap, 4), false);
+  void* tx64 = c->buffer("fp_twx64", 16 * (size_t)g.nx, false);
+  void* tx32 = c->buffer("fp_twx32", 8 * (size_t)g.nx, false);
+  void* tz64 = c->buffer("fp_twz64", 16 * (size_t)g.nz, false);
+  void* tz32 = c->buffer("fp_twz32", 8 * (size_t)g.nz, false);
+  if (!qb || !qb32 || !bd || !flag || !P || !Y || !S || !sh || !Uf || !Lf || !pv || !A64 || !B64 || !A32 || !B32 ||
+      !tx64 || !tx32 || !tz64 || !tz32)
+    return c->fail(SA_ENOMEM, "sa_precond_setup: out of device memory");
+  // twiddle tables e^{-2 pi i m / n}
+  {
+    std::vector<double> h64(2 * (size_t)std::max(g.nx, g.nz));
+    std::vector<float> h32(h64.size());
+    for (int pass = 0; pass < 2; ++pass) {
+      const int len = pass == 0 ? g.nx : g.nz;
+      for (int m = 0; m < len; ++m) {
+        const double a = -2.0 * M_PI * (double)m / (double)len;
+        h64[2 * m] = std::cos(a);
+        h64[2 * m + 1] = std::sin(a);
+        h32[2 * m] = (float)h64[2 * m];
+        h32[2 * m + 1] = (float)h64[2 * m + 1];
+      }
+      hipError_t e = hipMemcpy(pass == 0 ? tx64 : tz64, h64.data(), 16 * (size_t)len, hipMemcpyHostToDevice);
+      if (e == hipSuccess) e = hipMemcpy(pass == 0 ? tx32 : tz32, h32.data(), 8 * (size_t)len, hipMemcpyHostToDevice);
+      if (e != hipSuccess) return c->hip_fail(e, "sa_precond_setup twiddles");
+    }
+  }
+  hipError_t e = hipMemcpyAsync(sh, shifts_host, sizeof(double) * nshift, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return c->hip_fail(e, "sa_precond_setup shifts");
+  mean_base_kernel<<<(unsigned)(nv * g.ny), 256, 0, s>>>(g, c->base64, qb);
+  zero_fill(flag, 16, s);
+  OpParams op = c->op;
+  op.iso[0] = op.iso[1] = nullptr;
+  e = launch_base_derive(op, qb, qb32, flag, s);
+  if (e == hipSuccess) e = launch_base_data(op, qb, bd, s);
+  if (e != hipSuccess) return c->hip_fail(e, "sa_precond_setup mean base");
+  zero_fill(S, sizeof(double) * nS, s);
+  for (int col = 0; col < NCOL; ++col) {
+    zero_fill(P, sizeof(double) * (size_t)nv * n, s);
+    const int nrow = g.ny - 2;
+    probe_kernel<<<(unsigned)((nv * nrow + 255) / 256), 256, 0, s>>>(g, col, P);
+    e = launch_jv<double>(op, qb, bd, P, Y, nv, 0.0, nullptr, s, -1);
+    if (e != hipSuccess) return c->hip_fail(e, "sa_precond_setup probes");
+    gather_kernel<<<(unsigned)((nS + 255) / 256), 256, 0, s>>>(g, col, Y, S);
+  }
+  zero_fill(flag, 16, s);
+  const unsigned nblk = (unsigned)((long long)g.nmodes * nshift);
+  if (o->factor_prec == SA_F64)
+    band_lu_kernel<double><<<nblk, 64, 0, s>>>(g, S, sh, (cx<double>*)Uf, (cx<double>*)Lf, pv, flag);
+  else
+    band_lu_kernel<float><<<nblk, 64, 0, s>>>(g, S, sh, (cx<float>*)Uf, (cx<float>*)Lf, pv, flag);
+  e = hipGetLastError();
+  if (e != hipSuccess) return c->hip_fail(e, "sa_precond_setup factor");
+  int hflag = 0;
+  e = hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return c->hip_fail(e, "sa_precond_setup sync");
+  if (hflag) return c->fail(SA_ESINGULAR, "sa_precond_setup: zero pivot in a mode of the mean-flow operator");
+  c->fp_U = Uf;
+  c->fp_L = Lf;
+  c->fp_piv = pv;
+  c->fp_f64 = o->factor_prec == SA_F64;
+  c->fp_specA64 = A64;
+  c->fp_specB64 = B64;
+  c->fp_specA32 = A32;
+  c->fp_specB32 = B32;
+  c->fp_twx64 = tx64;
+  c->fp_twx32 = tx32;
+  c->fp_twz64 = tz64;
+  c->fp_twz32 = tz32;
+  c->fp_nrhs_cap = cap;
+  return SA_OK;
+}
+
+}  // namespace sa

@@ -66,6 +66,16 @@ struct Ctx {
   void* pc_lu = nullptr;   // L\U of each block
   int* pc_perm = nullptr;  // [nshift][group][nb][64] row permutation of the pivoting
   bool pc_f64 = false;     // factor precision
+  int pc_kind = 0;         // SA_PC_BLOCK_JACOBI or SA_PC_MEAN_FLOW
+  // mean-flow preconditioner (fourier_pc.hip): per (shift, mode) banded
+  // factors, the apply's spectrum buffers and twiddle tables
+  void* fp_U = nullptr;
+  void* fp_L = nullptr;
+  int* fp_piv = nullptr;
+  bool fp_f64 = false;
+  void *fp_specA64 = nullptr, *fp_specB64 = nullptr, *fp_specA32 = nullptr, *fp_specB32 = nullptr;
+  void *fp_twx64 = nullptr, *fp_twx32 = nullptr, *fp_twz64 = nullptr, *fp_twz32 = nullptr;
+  int fp_nrhs_cap = 0;
 
   // cached cycle graphs (captured on cap_stream, launched on stream); dropped
   // whenever the base state or the preconditioner changes
@@ -111,7 +121,14 @@ int solve_gmres(Ctx* c, const sa_gmres_opts& o, int nsys, const double* sigma_ho
 int solve_ir(Ctx* c, const sa_gmres_opts& o, double sigma, const double* b, double* x, int pc_shift,
              sa_gmres_info* info);
 
-// block-Jacobi apply z = P M^{-1} r (bjac.hip)
+// mean-flow preconditioner (fourier_pc.hip): setup, and z = M^{-1} r for
+// nrhs systems (at most the setup's shift count)
+int fourier_setup(Ctx* c, const sa_precond_opts* o, int nshift, const double* shifts_host);
+template <typename R>
+hipError_t fourier_apply(Ctx* c, int ishift, int nrhs, const R* r, R* z, const int* active, int shift_step,
+                         long long sV, long long sA, hipStream_t s);
+
+// preconditioner apply z = P M^{-1} r (bjac.hip; dispatches on pc_kind)
 template <typename R>
 hipError_t precond_apply(Ctx* c, int ishift, int nrhs, const R* r, R* z, const int* active, int shift_step,
                          long long sV, long long sA, hipStream_t s);

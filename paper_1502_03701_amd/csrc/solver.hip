@@ -218,6 +218,11 @@ int solve_gmres(Ctx* c, const sa_gmres_opts& o, int nsys, const double* sigma, c
                             (const void*)bdata, (const void*)c->pc_lu, (const void*)c->pc_perm})
       put(key, ptr);
     for (const void* ptr : {(const void*)AUG, (const void*)AUGA, (const void*)RPREV, (const void*)XOLD}) put(key, ptr);
+    put(key, c->pc_kind);
+    for (const void* ptr : {(const void*)c->fp_U, (const void*)c->fp_L, (const void*)c->fp_piv,
+                            (const void*)c->fp_specA64, (const void*)c->fp_specB64, (const void*)c->fp_specA32,
+                            (const void*)c->fp_specB32})
+      put(key, ptr);
     for (int i = 0; i < nsys; ++i) put(key, sigma[i]);
     exec = find_graph(c, key);
     if (!exec) {
