@@ -9,7 +9,9 @@ one point = one update).
 
 Also reported: the roofline record of the operator kernel (algorithmic bytes
 = read x + read q0 + write y = 3 nv 8 B per point, against 8 TB/s), the same
-operator in FP32, optional extras (--extras: GMRES(40) at 2D 512 x 512, the
+operator in FP32, the time to the 6 leading eigenpairs of the same workload
+in the FP64 and the mixed form (Cayley-IRAM with mean-flow-preconditioned
+inner solves; --no-eigs skips it), optional extras (--extras: GMRES(40) at 2D 512 x 512, the
 block-Jacobi preconditioner of the 3D grid with 8 shifts, 8-shift batched
 GMRES cycles, time to eigenpairs FP64 vs mixed on a small case, a reduced
 sweep of uneven base flows run in turn and concurrently), and the oracle
@@ -162,6 +164,7 @@ def main():
     ap.add_argument("--extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-eigs", action="store_true", help="skip the eigen-time record")
+    ap.add_argument("--eigs-only", action="store_true", help="only the eigen-time record (3D workload)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a device copy of known size (counter calibration)")
     ap.add_argument("--bjac-only", action="store_true",
@@ -207,6 +210,9 @@ def main():
     if args.sweep_mid:
         print(json.dumps(sweep(torch, dev, augment=3, modes=("concurrent",), sides=(64, 96, 128), tag="mid",
                                max_matvec=30000, log=lambda m: print(m, file=sys.stderr, flush=True))))
+        return
+    if args.eigs_only:
+        print(json.dumps(eigs_c2(torch, dev, log=lambda m: print(m, file=sys.stderr, flush=True))))
         return
     if args.eigs_64:
         print(json.dumps(eigs_3d(torch, dev, side=64, max_restarts=20, augment=3,
@@ -294,7 +300,7 @@ def main():
         "autotuned_jv": tuned,
     }
     if not args.no_eigs:
-        out["eigs"] = eigs_record(torch, dev, log=lambda m: print(m, file=sys.stderr, flush=True))
+        out["eigs"] = eigs_c2(torch, dev, log=lambda m: print(m, file=sys.stderr, flush=True))
     if args.extras:
         out["extras"] = extras(torch, dev, ctx, prob)
     if not args.no_cpu:
@@ -438,35 +444,53 @@ def extras(torch, dev, ctx3, prob3):
     return res
 
 
-def eigs_record(torch, dev, log=None):
-    """The metric's second half, time to eigenpairs, mixed against FP64 on the
-    GPU, on the 3D mixing layer at 64^3 (the workload's base flow and
-    parameters; 1.3 M DOFs).  At the full 256 x 128 x 128 grid one Cayley
-    system alone takes 25.7 s mixed / 46.5 s FP64 to 1e-10 with
-    unpreconditioned inner solves, and an eigen solve needs ~30 of them per
-    restart, far beyond a bench run; at 64^3 the whole solve takes about a
-    minute.  With Arnoldi dimension 16, two eigenpairs (the KH pair and its
-    spanwise twin split by the noise) converge; eigenpairs 3-6 lie in a ring
-    of |theta| ~ 1 that IRAM does not separate at these shifts.  Reported:
-    wall seconds per form, products, the relative difference of each mixed
-    eigenvalue from the FP64 one, and each pair's true residual with the
-    library's FP64 operator (the oracle residuals are checked by the GPU
-    tests)."""
-    r = eigs_3d(torch, dev, side=64, max_restarts=20, augment=3, log=log)
-    f, m = r["eigs_3d_64_nev2_lgmres_fp64"], r["eigs_3d_64_nev2_lgmres_mixed"]
-    lf = [complex(*x) for x in f["lam"]]
-    lm = [complex(*x) for x in m["lam"]]
-    rel = [abs(a - b) / abs(a) for a, b in zip(sorted(lf, key=lambda z: (-z.real, z.imag)),
-                                               sorted(lm, key=lambda z: (-z.real, z.imag)))]
-    return {"workload": "3D mixing layer 64^3 (x, z periodic, y walls), 5 vars, tanh + 1e-3 N(0,1) spanwise "
-                        "base, M=0.5 Re=1000; sigma=0.2, mu=-0.2, Arnoldi dimension 16, 2 eigenpairs, "
-                        "LGMRES(37,3) inner solves to 1e-12 (mixed: FP32 inner solves to 1e-4 inside FP64 "
-                        "refinement)",
-            "why_not_full_grid": "one Cayley system of the 256x128x128 grid takes 25.7 s mixed / 46.5 s FP64 to "
-                                 "1e-10 without a preconditioner; an eigen solve needs hundreds of them",
-            "fp64_seconds": f["seconds"], "mixed_seconds": m["seconds"],
-            "speedup_mixed_vs_fp64": f["seconds"] / m["seconds"],
-            "fp64": f, "mixed": m, "rel_diff_mixed_vs_fp64": rel}
+def eigs_c2(torch, dev, log=None, max_restarts=60):
+    """The metric's second half, time to 6 eigenpairs, mixed against FP64 on
+    the GPU, at the full 3D workload (256 x 128 x 128, 5 vars, tanh + 1e-3
+    spanwise noise, M = 0.5, Re = 1000; sigma = 0.2, mu = -0.2, Arnoldi
+    dimension 30, 6 eigenpairs, tol 1e-10).  Inner Cayley solves: GMRES(30)
+    right-preconditioned with the mean-flow operator M(sigma) (the operator of
+    the base averaged over x and z, factored per Fourier mode).  FP64 form:
+    FP64 GMRES, operator and factors, solves to 1e-12.  Mixed form: FP32
+    GMRES, operator and factors for solves to 1e-4, inside FP64 refinement to
+    1e-12.  The timed region covers the preconditioner setup, the IRAM solve,
+    the Ritz vectors and their FP64 true residuals."""
+    import synth
+    from paper_1502_03701_amd import SA_F32, SA_F64, SA_MIXED, SA_PC_MEAN_FLOW, Context, arnoldi_eigs
+    p = synth.config2()
+    ctx = Context()
+    ctx.base_set(p, torch.from_numpy(synth.base_flow(p, seed=2, w_noise=1e-3).ravel()).to(dev))
+    v0 = torch.from_numpy(synth.random_vector(p, 0).ravel()).to(dev)
+    nev = 6
+    evr = torch.empty(nev * p.ndof, dtype=torch.float64, device=dev)
+    evi = torch.empty_like(evr)
+    out, lam = {}, {}
+    for name, prec, fprec in (("fp64", SA_F64, SA_F64), ("mixed", SA_MIXED, SA_F32)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.precond_setup([0.2], factor_prec=fprec, kind=SA_PC_MEAN_FLOW)
+        rc, r = arnoldi_eigs([ctx], [v0], nev=nev, ncv=30, sigma=0.2, mu=-0.2, tol=1e-10,
+                             max_restarts=max_restarts, restart=30, lin_tol=1e-12, use_precond=True, prec=prec,
+                             inner_tol=1e-4, max_outer=30, evecs=[(evr, evi)])
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        r = r[0]
+        lam[name] = r["lam"]
+        out[name] = {"seconds": el, "rc": rc, "nconv": r["nconv"], "restarts": r["restarts"],
+                     "n_cayley": r["n_cayley"], "n_matvec": r["n_matvec"], "n_precond": r["n_precond"],
+                     "lam": [[l.real, l.imag] for l in r["lam"]], "resid": r["resid"]}
+        if log:
+            log("eigs c2 %s: %.2f s, nconv %d, %d Cayley solves, %d products" % (name, el, r["nconv"],
+                                                                              r["n_cayley"], r["n_matvec"]))
+    key = lambda z: (-z.real, z.imag)   # noqa: E731
+    rel = [abs(a - b) / abs(a) for a, b in zip(sorted(lam["fp64"], key=key), sorted(lam["mixed"], key=key))]
+    ctx.close()
+    return {"workload": "3D mixing layer 256x128x128 (x, z periodic, y walls), 5 vars, tanh + 1e-3 N(0,1) "
+                        "spanwise base, M=0.5 Re=1000; sigma=0.2, mu=-0.2, Arnoldi dimension 30, 6 eigenpairs, "
+                        "tol 1e-10; GMRES(30) inner solves right-preconditioned with the mean-flow operator",
+            "fp64_seconds": out["fp64"]["seconds"], "mixed_seconds": out["mixed"]["seconds"],
+            "speedup_mixed_vs_fp64": out["fp64"]["seconds"] / out["mixed"]["seconds"],
+            "fp64": out["fp64"], "mixed": out["mixed"], "rel_diff_mixed_vs_fp64": rel}
 
 
 def eigs_c0(torch, dev, log=None):

@@ -19,11 +19,12 @@
 //     - s delta, and factors them by banded LU with partial pivoting in a
 //     sliding (kl+1) x (kl+ku+1) window in LDS: U rows (kl+ku+1 entries),
 //     L multipliers (kl) and pivot offsets are written per step.
-// Apply z = M(s)^{-1} r: real-to-complex DFT along x (and a complex DFT along
-// z), one wavefront per (mode, system) for the banded forward and back
-// substitutions with the mode's vector in LDS, the inverse transforms, and
-// zero wall rows.  The DFTs are direct sums with twiddle tables in LDS
-// (x lines) or LDS-staged tiles (z lines), which serves every grid size.
+// Apply z = M(s)^{-1} r: real-to-complex FFT along x (two real lines packed
+// into one complex transform) and a complex FFT along z, one wavefront per
+// (mode, system) for the banded forward and back substitutions, the inverse
+// transforms, and zero wall rows.  The FFTs are self-sorting mixed-radix
+// (Stockham) transforms in LDS for any length: radix 4, then 2, then the odd
+// prime factors, each stage a direct sum over its radix.
 #include <cmath>
 #include <vector>
 
@@ -41,6 +42,7 @@ constexpr int REACH = 3;
 constexpr int NOFF = 2 * REACH + 1;   // offsets -3 .. 3
 constexpr int NCOL = 7;               // y colours of the probes (> 2 REACH)
 constexpr size_t LDS_CAP = 65536;     // dynamic LDS a launch of this file may take
+constexpr int BS_GROUP = 16;          // steps per prefetch group of the banded solve
 
 struct FGeom {
   int nd, nv, nx, ny, nz;
@@ -135,9 +137,11 @@ __global__ void gather_kernel(FGeom g, int c, const double* __restrict__ Y, doub
 // Band LU with partial pivoting of A_k - s I for one (mode, shift) per
 // wavefront.  Window W: logical row i (matrix row col + i) at physical row
 // (r0 + i) % KH, logical column jj (matrix column col + jj) at physical
-// column (c0 + jj) % KW.  Factor layout per (shift, mode): U[u][0 .. KW),
-// U[u][d] = U(u, u + d); L[u][0 .. kl), the multiplier of row u + 1 + d at
-// step u; piv[u] in [0, kl], row u exchanged with row u + piv[u].
+// column (c0 + jj) % KW.  Factor layout per (shift, mode), each row of it
+// what one substitution step reads: Ut[c][0] = 1 / U(c, c) and Ut[c][d] =
+// U(c - d, c) for d = 1 .. KW-1 (column c of U upwards from the diagonal);
+// L[u][0 .. kl), the multiplier of row u + 1 + d at step u; piv[u] in
+// [0, kl], row u exchanged with row u + piv[u].
 template <typename F>
 __global__ void __launch_bounds__(64) band_lu_kernel(FGeom g, const double* __restrict__ S,
                                                      const double* __restrict__ shifts, cx<F>* __restrict__ Uo,
@@ -240,7 +244,11 @@ __global__ void __launch_bounds__(64) band_lu_kernel(FGeom g, const double* __re
       lw[lane] = l;
       L[(long long)col * kl + lane - 1] = l;
     }
-    for (int jj = lane; jj < KW; jj += 64) U[(long long)col * KW + jj] = W[r0 % KH][(c0 + jj) % KW];
+    for (int jj = lane; jj < KW; jj += 64) {
+      cx<F> val = W[r0 % KH][(c0 + jj) % KW];
+      if (jj == 0) val = den > F(0) ? cx<F>{pv.re / den, -pv.im / den} : cx<F>{F(0), F(0)};
+      if (col + jj < N) U[(long long)(col + jj) * KW + jj] = val;
+    }
     if (lane == 0) piv[col] = p;
     __syncthreads();
     // trailing update of the window: W[i][jj] -= l_i W[0][jj]
@@ -269,122 +277,199 @@ __global__ void __launch_bounds__(64) band_lu_kernel(FGeom g, const double* __re
 
 // ---------------------------------------------------------------- apply ----
 
-// Forward real DFT along x of the interior rows: one workgroup per (line,
-// system), line = (k, j, v); out[sys][k][kx][u] (2D: the spectrum itself).
+// Radices of a length-n transform, in the order they are applied.
+struct FPlan {
+  int n, ns;
+  int rad[24];
+};
+
+FPlan plan_of(int n) {
+  FPlan p{};
+  p.n = n;
+  int m = n;
+  while (m % 4 == 0) { p.rad[p.ns++] = 4; m /= 4; }
+  while (m % 2 == 0) { p.rad[p.ns++] = 2; m /= 2; }
+  for (int f = 3; f * f <= m; f += 2)
+    while (m % f == 0) { p.rad[p.ns++] = f; m /= f; }
+  if (m > 1) p.rad[p.ns++] = m;
+  return p;
+}
+
+// Self-sorting FFT of P sequences of length n held one after another in a
+// (LDS), with b as the second buffer; returns the buffer with the result.
+// After the stages of radices p_0 .. p_{t-1} (product L), entry j + (n/L) k
+// of a holds the length-L DFT, at frequency k, of the subsequence that
+// starts at j with stride n/L; a stage of radix p combines p of them:
+//   A'[j', k'] = sum_r e^{-2 pi i r k' / (L p)} A[j' + m' r, k' mod L],  m' = n/(L p).
+// inverse: conjugate twiddles (unscaled).  Every thread of the block calls it.
 template <typename R>
-__global__ void __launch_bounds__(256) dft_x_fwd(FGeom g, const R* __restrict__ r, long long sV,
+__device__ cx<R>* stockham(const FPlan& pl, cx<R>* a, cx<R>* b, int P, const cx<R>* __restrict__ tw, bool inverse) {
+  const int n = pl.n;
+  int L = 1;
+  for (int t = 0; t < pl.ns; ++t) {
+    const int p = pl.rad[t];
+    const int mp = n / (L * p), m = mp * p;
+    for (int o = threadIdx.x; o < P * n; o += blockDim.x) {
+      const int sq = o / n, idx = o - sq * n;
+      const int kp = idx / mp, jp = idx - kp * mp;
+      const cx<R>* src = a + sq * n + jp + m * (kp % L);
+      const int step = kp * mp;   // < n
+      R ar = R(0), ai = R(0);
+      int q = 0;
+      for (int r = 0; r < p; ++r) {
+        const cx<R> x = src[mp * r];
+        const cx<R> w = tw[q];
+        const R wi = inverse ? -w.im : w.im;
+        ar += x.re * w.re - x.im * wi;
+        ai += x.re * wi + x.im * w.re;
+        q += step;
+        if (q >= n) q -= n;
+      }
+      b[o] = cx<R>{ar, ai};
+    }
+    __syncthreads();
+    cx<R>* t2 = a;
+    a = b;
+    b = t2;
+    L *= p;
+  }
+  return a;
+}
+
+// address of interior line lid = k N + u (u = (j-1) nv + v) of system sys
+template <typename R>
+__device__ __forceinline__ long long line_off(const FGeom& g, int lid) {
+  const int k = lid / g.N, u = lid - k * g.N;
+  const int jr = u / g.nv, v = u - jr * g.nv;
+  return (((long long)v * g.nz + k) * g.ny + jr + 1) * g.nx;
+}
+
+// Forward real FFT along x of the interior lines, two lines (a, b) per
+// complex transform z = a + i b: A_k = (Z_k + conj Z_{n-k}) / 2,
+// B_k = -i (Z_k - conj Z_{n-k}) / 2.  P line pairs per workgroup;
+// out[sys][k][kx][u] for kx = 0 .. nx/2.
+template <typename R>
+__global__ void __launch_bounds__(256) fft_x_fwd(FGeom g, FPlan pl, int P, const R* __restrict__ r, long long sV,
                                                  const cx<R>* __restrict__ tw, cx<R>* __restrict__ out,
                                                  const int* __restrict__ active, long long sA) {
   extern __shared__ unsigned char smem[];
+  const int n = g.nx;
   cx<R>* stw = reinterpret_cast<cx<R>*>(smem);
-  R* line = reinterpret_cast<R*>(stw + g.nx);
+  cx<R>* b0 = stw + n;
+  cx<R>* b1 = b0 + P * n;
   const int sys = blockIdx.y;
   if (active && !active[sys * sA]) return;
-  const int nrow = g.ny - 2;
-  const int lid = blockIdx.x;   // (k, jrow, v)
-  const int v = lid % g.nv, jr = (lid / g.nv) % nrow, k = lid / (g.nv * nrow);
-  const int j = jr + 1;
-  const int u = jr * g.nv + v;
-  const R* src = r + (long long)sys * sV + (((long long)v * g.nz + k) * g.ny + j) * g.nx;
-  for (int i = threadIdx.x; i < g.nx; i += 256) {
-    stw[i] = tw[i];
-    line[i] = src[i];
+  const int nl = g.nz * g.N;
+  const int pair0 = blockIdx.x * P;
+  const R* src = r + (long long)sys * sV;
+  for (int t = threadIdx.x; t < n; t += 256) stw[t] = tw[t];
+  for (int t = threadIdx.x; t < P * n; t += 256) {
+    const int sq = t / n, i = t - sq * n;
+    const int la = 2 * (pair0 + sq), lb = la + 1;
+    const R a = la < nl ? src[line_off<R>(g, la) + i] : R(0);
+    const R b = lb < nl ? src[line_off<R>(g, lb) + i] : R(0);
+    b0[t] = cx<R>{a, b};
   }
   __syncthreads();
-  cx<R>* dst = out + ((long long)sys * g.nz + k) * (long long)g.mx * g.N;
-  for (int kxx = threadIdx.x; kxx < g.mx; kxx += 256) {
-    R ar = R(0), ai = R(0);
-    int idx = 0;
-    for (int i = 0; i < g.nx; ++i) {
-      const cx<R> w = stw[idx];
-      ar += line[i] * w.re;
-      ai += line[i] * w.im;
-      idx += kxx;
-      if (idx >= g.nx) idx -= g.nx;
+  const cx<R>* Z = stockham<R>(pl, b0, b1, P, stw, false);
+  cx<R>* dst = out + (long long)sys * g.nz * g.mx * g.N;
+  for (int t = threadIdx.x; t < P * g.mx; t += 256) {
+    const int kx = t / P, sq = t - kx * P;   // consecutive threads: consecutive lines
+    const int la = 2 * (pair0 + sq), lb = la + 1;
+    if (la >= nl) continue;
+    const cx<R> zk = Z[sq * n + kx], zn = Z[sq * n + (kx == 0 ? 0 : n - kx)];
+    const R h = R(0.5);
+    const int ka = la / g.N, ua = la - ka * g.N;
+    dst[((long long)ka * g.mx + kx) * g.N + ua] = cx<R>{h * (zk.re + zn.re), h * (zk.im - zn.im)};
+    if (lb < nl) {
+      const int kb = lb / g.N, ub = lb - kb * g.N;
+      dst[((long long)kb * g.mx + kx) * g.N + ub] = cx<R>{h * (zk.im + zn.im), -h * (zk.re - zn.re)};
     }
-    dst[(long long)kxx * g.N + u] = cx<R>{ar, ai};
   }
 }
 
-// Complex DFT along z between in[sys][k][kx][u] and out[sys][kz][kx][u]
-// (sign -1 forward, +1 inverse), a workgroup per (kx, ub consecutive u):
-// the nz x ub input tile in LDS, each output a sum over k.
+// Complex FFT along z between in[sys][k][kx][u] and out[sys][kz][kx][u],
+// a workgroup per (kx, ub consecutive u): the ub sequences in LDS.
 template <typename R>
-__global__ void __launch_bounds__(256) dft_z(FGeom g, const cx<R>* __restrict__ in, const cx<R>* __restrict__ tw,
-                                             int inverse, int ub, cx<R>* __restrict__ out,
+__global__ void __launch_bounds__(256) fft_z(FGeom g, FPlan pl, int ub, const cx<R>* __restrict__ in,
+                                             const cx<R>* __restrict__ tw, int inverse, cx<R>* __restrict__ out,
                                              const int* __restrict__ active, long long sA) {
   extern __shared__ unsigned char smem[];
+  const int n = g.nz;
   cx<R>* stw = reinterpret_cast<cx<R>*>(smem);
-  cx<R>* tile = stw + g.nz;
+  cx<R>* b0 = stw + n;
+  cx<R>* b1 = b0 + ub * n;
   const int sys = blockIdx.y;
   if (active && !active[sys * sA]) return;
   const int nub = (g.N + ub - 1) / ub;
-  const int kxx = blockIdx.x / nub;
-  const int u0 = (blockIdx.x % nub) * ub;
+  const int kx = blockIdx.x / nub;
+  const int u0 = (blockIdx.x - kx * nub) * ub;
   const long long plane = (long long)g.mx * g.N;
-  const cx<R>* src = in + (long long)sys * g.nz * plane;
-  cx<R>* dst = out + (long long)sys * g.nz * plane;
-  for (int t = threadIdx.x; t < g.nz; t += 256) stw[t] = tw[t];
-  for (int t = threadIdx.x; t < g.nz * ub; t += 256) {
-    const int k = t / ub, uu = t % ub;
-    const int u = u0 + uu;
-    tile[t] = u < g.N ? src[(long long)k * plane + (long long)kxx * g.N + u] : cx<R>{R(0), R(0)};
+  const cx<R>* src = in + (long long)sys * n * plane + (long long)kx * g.N + u0;
+  cx<R>* dst = out + (long long)sys * n * plane + (long long)kx * g.N + u0;
+  for (int t = threadIdx.x; t < n; t += 256) stw[t] = tw[t];
+  for (int t = threadIdx.x; t < ub * n; t += 256) {
+    const int k = t / ub, uu = t - k * ub;
+    b0[uu * n + k] = u0 + uu < g.N ? src[(long long)k * plane + uu] : cx<R>{R(0), R(0)};
   }
   __syncthreads();
-  for (int t = threadIdx.x; t < g.nz * ub; t += 256) {
-    const int kz = t / ub, uu = t % ub;
-    const int u = u0 + uu;
-    if (u >= g.N) continue;
-    R ar = R(0), ai = R(0);
-    int idx = 0;
-    for (int k = 0; k < g.nz; ++k) {
-      const cx<R> w = stw[idx];              // e^{-2 pi i idx / nz}
-      const R ci = inverse ? -w.im : w.im;   // conjugate for the inverse
-      const cx<R> a = tile[k * ub + uu];
-      ar += a.re * w.re - a.im * ci;
-      ai += a.re * ci + a.im * w.re;
-      idx += kz;
-      if (idx >= g.nz) idx -= g.nz;
-    }
-    dst[(long long)kz * plane + (long long)kxx * g.N + u] = cx<R>{ar, ai};
+  const cx<R>* Z = stockham<R>(pl, b0, b1, ub, stw, inverse != 0);
+  for (int t = threadIdx.x; t < ub * n; t += 256) {
+    const int k = t / ub, uu = t - k * ub;
+    if (u0 + uu < g.N) dst[(long long)k * plane + uu] = Z[uu * n + k];
   }
 }
 
-// Inverse real DFT along x (complex-to-real) into the SoA vector, scaled by
-// 1/(nx nz); wall rows of z are written 0 by zero_walls.
+// Inverse real FFT along x (two lines per complex transform: Z = A + i B
+// over the full circle from the Hermitian halves, imaginary parts of the
+// k = 0 and Nyquist terms dropped) into the SoA vector, scaled by
+// 1/(nx nz).  Wall rows of z are written 0 by zero_walls.
 template <typename R>
-__global__ void __launch_bounds__(256) dft_x_inv(FGeom g, const cx<R>* __restrict__ in, const cx<R>* __restrict__ tw,
-                                                 R* __restrict__ z, long long sV, const int* __restrict__ active,
-                                                 long long sA) {
+__global__ void __launch_bounds__(256) fft_x_inv(FGeom g, FPlan pl, int P, const cx<R>* __restrict__ in,
+                                                 const cx<R>* __restrict__ tw, R* __restrict__ z, long long sV,
+                                                 const int* __restrict__ active, long long sA) {
   extern __shared__ unsigned char smem[];
+  const int n = g.nx;
   cx<R>* stw = reinterpret_cast<cx<R>*>(smem);
-  cx<R>* spec = stw + g.nx;
+  cx<R>* b0 = stw + n;
+  cx<R>* b1 = b0 + P * n;
   const int sys = blockIdx.y;
   if (active && !active[sys * sA]) return;
-  const int nrow = g.ny - 2;
-  const int lid = blockIdx.x;
-  const int v = lid % g.nv, jr = (lid / g.nv) % nrow, k = lid / (g.nv * nrow);
-  const int j = jr + 1;
-  const int u = jr * g.nv + v;
-  const cx<R>* src = in + ((long long)sys * g.nz + k) * (long long)g.mx * g.N;
-  for (int t = threadIdx.x; t < g.nx; t += 256) stw[t] = tw[t];
-  for (int t = threadIdx.x; t < g.mx; t += 256) spec[t] = src[(long long)t * g.N + u];
-  __syncthreads();
-  const R scale = R(1) / (R(g.nx) * R(g.nz));
-  const bool even = g.nx % 2 == 0;
-  R* dst = z + (long long)sys * sV + (((long long)v * g.nz + k) * g.ny + j) * g.nx;
-  for (int i = threadIdx.x; i < g.nx; i += 256) {
-    R acc = spec[0].re;
-    int idx = 0;
-    for (int kxx = 1; kxx < g.mx; ++kxx) {
-      idx += i;
-      if (idx >= g.nx) idx -= g.nx;
-      const cx<R> w = stw[idx];   // e^{-2 pi i kx i / nx}; the inverse uses its conjugate
-      const cx<R> a = spec[kxx];
-      const R re = a.re * w.re + a.im * w.im;   // Re(a conj(w))
-      acc += (even && kxx == g.mx - 1) ? re : R(2) * re;
+  const int nl = g.nz * g.N;
+  const int pair0 = blockIdx.x * P;
+  const cx<R>* src = in + (long long)sys * g.nz * g.mx * g.N;
+  for (int t = threadIdx.x; t < n; t += 256) stw[t] = tw[t];
+  const bool even = n % 2 == 0;
+  for (int t = threadIdx.x; t < P * g.mx; t += 256) {
+    const int kx = t / P, sq = t - kx * P;
+    const int la = 2 * (pair0 + sq), lb = la + 1;
+    cx<R> A{R(0), R(0)}, B{R(0), R(0)};
+    if (la < nl) {
+      const int ka = la / g.N, ua = la - ka * g.N;
+      A = src[((long long)ka * g.mx + kx) * g.N + ua];
     }
-    dst[i] = acc * scale;
+    if (lb < nl) {
+      const int kb = lb / g.N, ubb = lb - kb * g.N;
+      B = src[((long long)kb * g.mx + kx) * g.N + ubb];
+    }
+    if (kx == 0 || (even && kx == n / 2)) {
+      A.im = R(0);
+      B.im = R(0);
+    }
+    b0[sq * n + kx] = cx<R>{A.re - B.im, A.im + B.re};                 // A_k + i B_k
+    if (kx != 0 && !(even && kx == n / 2))
+      b0[sq * n + n - kx] = cx<R>{A.re + B.im, B.re - A.im};           // conj A_k + i conj B_k
+  }
+  __syncthreads();
+  const cx<R>* Z = stockham<R>(pl, b0, b1, P, stw, true);
+  const R scale = R(1) / (R(g.nx) * R(g.nz));
+  R* dst = z + (long long)sys * sV;
+  for (int t = threadIdx.x; t < P * n; t += 256) {
+    const int sq = t / n, i = t - sq * n;
+    const int la = 2 * (pair0 + sq), lb = la + 1;
+    const cx<R> v = Z[t];
+    if (la < nl) dst[line_off<R>(g, la) + i] = v.re * scale;
+    if (lb < nl) dst[line_off<R>(g, lb) + i] = v.im * scale;
   }
 }
 
@@ -402,69 +487,163 @@ __global__ void zero_walls(FGeom g, R* __restrict__ z, long long sV, const int* 
   z[(long long)sys * sV + (vk * g.ny + j) * g.nx + i] = R(0);
 }
 
+__device__ __forceinline__ float rdlane(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double rdlane(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <typename R>
+__device__ __forceinline__ cx<R> rdlane(cx<R> v, int l) {
+  return cx<R>{rdlane(v.re, l), rdlane(v.im, l)};
+}
+
 // Banded forward and back substitution of one (mode, system) per wavefront,
-// the mode's vector in LDS.  System sys uses the factors of shift
-// shift0 + sys * shift_step.
+// in place on the mode's vector.  Row i of the moving window lives in a
+// register of lane i mod 64; a step broadcasts the finished row with
+// readlane and every window lane updates its own row, so a step is a short
+// chain of ALU operations.  Work is grouped by G steps: everything a group
+// reads from memory (factor rows, the G rows that enter the window) is
+// loaded while the previous group runs, into one of two register sets used
+// in turn; the entering rows are placed at the start of the group (their
+// lanes are free: kl + 1 + G and KW + G do not exceed 64) and the rows the
+// group finishes are stored at its end.  A row's vector entry is only ever
+// read and written by the lane that owns it, so no LDS and no barriers are
+// needed.  System sys uses the factors of shift shift0 + sys * shift_step.
 template <typename F, typename R>
-__global__ void __launch_bounds__(64) band_solve_kernel(FGeom g, const cx<F>* __restrict__ Uo,
-                                                        const cx<F>* __restrict__ Lo, const int* __restrict__ pivo,
+__global__ void __launch_bounds__(64) band_solve_kernel(FGeom g, const cx<F>* __restrict__ Lo,
+                                                        const cx<F>* __restrict__ Uo, const int* __restrict__ pivo,
                                                         int shift0, int shift_step, cx<R>* __restrict__ spec,
                                                         const int* __restrict__ active, long long sA) {
-  extern __shared__ unsigned char smem[];
-  cx<R>* Z = reinterpret_cast<cx<R>*>(smem);
+  constexpr int G = BS_GROUP;
   const int m = blockIdx.x, sys = blockIdx.y;
   if (active && !active[sys * sA]) return;
   const int lane = threadIdx.x;
   const int N = g.N, kl = g.kl, KW = g.KW;
   const long long fo = (long long)(shift0 + sys * shift_step) * g.nmodes + m;
-  const cx<F>* U = Uo + fo * (long long)N * KW;
   const cx<F>* L = Lo + fo * (long long)N * kl;
+  const cx<F>* Ut = Uo + fo * (long long)N * KW;
   const int* piv = pivo + fo * (long long)N;
   cx<R>* vec = spec + ((long long)sys * g.nmodes + m) * N;   // mode m = kz mx + kx
-  for (int u = lane; u < N; u += 64) Z[u] = vec[u];
-  __syncthreads();
-  // forward: P, then L (unit lower, kl multipliers per column)
-  for (int col = 0; col < N; ++col) {
-    const int p = piv[col];
-    if (p != 0 && lane == 0) {
-      const cx<R> t0 = Z[col];
-      Z[col] = Z[col + p];
-      Z[col + p] = t0;
+  // the loads are unconditional (clamped addresses, the value selected
+  // afterwards): branch-free loads let the next group's stay in flight
+  auto ldv = [&](bool ok, long long i) {
+    const cx<R> v = vec[ok ? i : 0];
+    return cx<R>{ok ? v.re : R(0), ok ? v.im : R(0)};
+  };
+  auto ldf = [&](const cx<F>* base, bool ok, long long i) {
+    const cx<F> v = base[ok ? i : 0];
+    return cx<F>{ok ? v.re : F(0), ok ? v.im : F(0)};
+  };
+  // forward: P, then L (unit lower, kl multipliers per column); window rows
+  // col .. col + kl
+  cx<R> z = ldv(lane <= kl && lane < N, lane);
+  struct FwdSet {
+    cx<F> l[G];
+    cx<R> ent;   // this lane's row entering during the group, if any
+    int pv;      // lane s < G: the pivot offset of column c0 + s
+  };
+  auto load_fwd = [&](int c0, FwdSet& f) {
+#pragma unroll
+    for (int s = 0; s < G; ++s) {
+      const int col = c0 + s;
+      const int d = (lane - col - 1) & 63;
+      f.l[s] = ldf(L, col < N && d < kl && col + 1 + d < N, (long long)col * kl + d);
     }
-    __syncthreads();
-    const cx<R> zc = Z[col];
-    if (lane >= 1 && lane <= kl && col + lane < N) {
-      const cx<F> l = L[(long long)col * kl + lane - 1];
-      cx<R>& w = Z[col + lane];
-      w.re -= (R)l.re * zc.re - (R)l.im * zc.im;
-      w.im -= (R)l.re * zc.im + (R)l.im * zc.re;
-    }
-    __syncthreads();
-  }
-  // back: z_col = (z_col - sum_{d>=1} U[col][d] z_{col+d}) / U[col][0]
-  for (int col = N - 1; col >= 0; --col) {
-    R sr = R(0), si = R(0);
-    if (lane >= 1 && lane < KW && col + lane < N) {
-      const cx<F> a = U[(long long)col * KW + lane];
-      const cx<R> zz = Z[col + lane];
-      sr = (R)a.re * zz.re - (R)a.im * zz.im;
-      si = (R)a.re * zz.im + (R)a.im * zz.re;
+    const int e0 = c0 + kl + 1;
+    const int ne = e0 + ((lane - e0) & 63);
+    f.ent = ldv(ne - e0 < G && ne < N, ne);
+    const int pc = c0 + (lane & (G - 1));
+    f.pv = piv[pc < N ? pc : N - 1];
+  };
+  auto fwd_group = [&](int c0, const FwdSet& f) {
+    {
+      const int e0 = c0 + kl + 1;
+      if (((lane - e0) & 63) < G) z = f.ent;
     }
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      sr += __shfl_xor(sr, off, 64);
-      si += __shfl_xor(si, off, 64);
+    for (int s = 0; s < G; ++s) {
+      const int col = c0 + s;
+      if (col < N) {
+        const int l0 = col & 63;
+        const int p = __builtin_amdgcn_readlane(f.pv, s);
+        const cx<R> b = rdlane(z, (col + p) & 63);
+        if (p != 0) {   // uniform: exchange rows col and col + p
+          const cx<R> a = rdlane(z, l0);
+          const int lp = (col + p) & 63;
+          z.re = lane == lp ? a.re : (lane == l0 ? b.re : z.re);
+          z.im = lane == lp ? a.im : (lane == l0 ? b.im : z.im);
+        }
+        const R lr = (R)f.l[s].re, li = (R)f.l[s].im;
+        z.re -= lr * b.re - li * b.im;
+        z.im -= lr * b.im + li * b.re;
+      }
     }
-    if (lane == 0) {
-      const cx<F> d = U[(long long)col * KW];
-      const R dr = (R)d.re, di = (R)d.im;
-      const R den = dr * dr + di * di;
-      const R nr = Z[col].re - sr, ni = Z[col].im - si;
-      Z[col] = den > R(0) ? cx<R>{(nr * dr + ni * di) / den, (ni * dr - nr * di) / den} : cx<R>{R(0), R(0)};
-    }
-    __syncthreads();
+    // rows c0 .. c0 + G - 1 are final; their lanes keep them past the group
+    const int o = (lane - c0) & 63;
+    if (o < G && c0 + o < N) vec[c0 + o] = z;
+  };
+  FwdSet fa, fb;
+  load_fwd(0, fa);
+  for (int c0 = 0; c0 < N; c0 += 2 * G) {
+    load_fwd(c0 + G, fb);
+    fwd_group(c0, fa);
+    load_fwd(c0 + 2 * G, fa);
+    fwd_group(c0 + G, fb);
   }
-  for (int u = lane; u < N; u += 64) vec[u] = Z[u];
+  // back: column col of U upwards; window rows col - KW + 1 .. col
+  cx<R> r;
+  {
+    const int i = N - 1 - ((N - 1 - lane) & 63);
+    r = ldv(i >= 0 && i >= N - KW, i);
+  }
+  struct BwdSet {
+    cx<F> u[G];
+    cx<R> ent;
+  };
+  auto load_bwd = [&](int c0, BwdSet& b) {
+#pragma unroll
+    for (int s = 0; s < G; ++s) {
+      const int col = c0 - s;
+      const int d = (col - lane) & 63;
+      b.u[s] = ldf(Ut, col >= 0 && d < KW && col - d >= 0, (long long)col * KW + d);
+    }
+    const int e0 = c0 - KW;   // entering rows e0, e0 - 1, .., e0 - G + 1
+    const int ne = e0 - ((e0 - lane) & 63);
+    b.ent = ldv(e0 - ne < G && ne >= 0, ne);
+  };
+  auto bwd_group = [&](int c0, const BwdSet& b) {
+    {
+      const int e0 = c0 - KW;
+      if (((e0 - lane) & 63) < G) r = b.ent;
+    }
+#pragma unroll
+    for (int s = 0; s < G; ++s) {
+      const int col = c0 - s;
+      if (col >= 0) {
+        const int l0 = col & 63;
+        const cx<R> u{(R)b.u[s].re, (R)b.u[s].im};
+        const cx<R> t{r.re * u.re - r.im * u.im, r.re * u.im + r.im * u.re};   // lane l0: r / U(col, col)
+        const cx<R> zc = rdlane(t, l0);
+        const bool own = lane == l0;
+        r.re = own ? t.re : r.re - (u.re * zc.re - u.im * zc.im);
+        r.im = own ? t.im : r.im - (u.re * zc.im + u.im * zc.re);
+      }
+    }
+    const int o = (c0 - lane) & 63;
+    if (o < G && c0 - o >= 0) vec[c0 - o] = r;
+  };
+  BwdSet ba, bb;
+  load_bwd(N - 1, ba);
+  for (int c0 = N - 1; c0 >= 0; c0 -= 2 * G) {
+    load_bwd(c0 - G, bb);
+    bwd_group(c0, ba);
+    load_bwd(c0 - 2 * G, ba);
+    bwd_group(c0 - G, bb);
+  }
 }
 
 template <typename R>
@@ -497,6 +676,24 @@ size_t fourier_spec_bytes(const Ctx* c, int nrhs, size_t es) {
   return (size_t)nrhs * g.nz * g.mx * g.N * 2 * es;
 }
 
+// line pairs per workgroup of the x transforms (two LDS buffers of P n
+// complex values and the twiddles within LDS_CAP), and sequences per
+// workgroup of the z transforms
+template <typename R>
+int x_pairs(int n) {
+  const int cap = (int)(LDS_CAP / sizeof(cx<R>));
+  int P = (cap - n) / (2 * n);
+  if (P > 16) P = 16;
+  return P < 1 ? 1 : P;
+}
+template <typename R>
+int z_seqs(int n) {
+  const int cap = (int)(LDS_CAP / sizeof(cx<R>));
+  int ub = (cap - n) / (2 * n);
+  if (ub > 32) ub = 32;
+  return ub < 1 ? 1 : ub;
+}
+
 template <typename R>
 hipError_t fourier_apply(Ctx* c, int ishift, int nrhs, const R* r, R* z, const int* active, int shift_step,
                          long long sV, long long sA, hipStream_t s) {
@@ -508,33 +705,33 @@ hipError_t fourier_apply(Ctx* c, int ishift, int nrhs, const R* r, R* z, const i
   cx<R>* B = reinterpret_cast<cx<R>*>(es == 8 ? c->fp_specB64 : c->fp_specB32);
   const cx<R>* tx = twx_of<R>(c);
   const cx<R>* tz = twz_of<R>(c);
-  const int nlines = g.nz * (g.ny - 2) * g.nv;
-  const dim3 gl((unsigned)nlines, (unsigned)nrhs);
+  const FPlan px = plan_of(g.nx), pz = plan_of(g.nz);
+  const int P = x_pairs<R>(g.nx);
+  const int npair = (g.nz * g.N + 1) / 2;
+  const dim3 gx((unsigned)((npair + P - 1) / P), (unsigned)nrhs);
+  const size_t xlds = (size_t)(g.nx + 2 * P * g.nx) * sizeof(cx<R>);
+  const int ub = z_seqs<R>(g.nz);
+  const dim3 gz((unsigned)(g.mx * ((g.N + ub - 1) / ub)), (unsigned)nrhs);
+  const size_t zlds = (size_t)(g.nz + 2 * ub * g.nz) * sizeof(cx<R>);
   // forward: x (into A), then z (A -> B) in 3D
-  dft_x_fwd<R><<<gl, 256, g.nx * sizeof(cx<R>) + g.nx * es, s>>>(g, r, sV, tx, A, active, sA);
+  fft_x_fwd<R><<<gx, 256, xlds, s>>>(g, px, P, r, sV, tx, A, active, sA);
   cx<R>* spec = A;
-  // z tiles of ub u-columns, the tile and the twiddles within 64 KiB of LDS
-  int ub = 32;
-  while (ub > 1 && (size_t)g.nz * (ub + 1) * sizeof(cx<R>) > LDS_CAP) ub /= 2;
-  const unsigned nzb = (unsigned)(g.mx * ((g.N + ub - 1) / ub));
-  const size_t zlds = (size_t)g.nz * (ub + 1) * sizeof(cx<R>);
   if (g.nd == 3) {
-    dft_z<R><<<dim3(nzb, (unsigned)nrhs), 256, zlds, s>>>(g, A, tz, 0, ub, B, active, sA);
+    fft_z<R><<<gz, 256, zlds, s>>>(g, pz, ub, A, tz, 0, B, active, sA);
     spec = B;
   }
-  const size_t lds = (size_t)g.N * sizeof(cx<R>);
   if (c->fp_f64)
-    band_solve_kernel<double, R><<<dim3((unsigned)g.nmodes, (unsigned)nrhs), 64, lds, s>>>(
-        g, (const cx<double>*)c->fp_U, (const cx<double>*)c->fp_L, c->fp_piv, ishift, shift_step, spec, active, sA);
+    band_solve_kernel<double, R><<<dim3((unsigned)g.nmodes, (unsigned)nrhs), 64, 0, s>>>(
+        g, (const cx<double>*)c->fp_L, (const cx<double>*)c->fp_U, c->fp_piv, ishift, shift_step, spec, active, sA);
   else
-    band_solve_kernel<float, R><<<dim3((unsigned)g.nmodes, (unsigned)nrhs), 64, lds, s>>>(
-        g, (const cx<float>*)c->fp_U, (const cx<float>*)c->fp_L, c->fp_piv, ishift, shift_step, spec, active, sA);
+    band_solve_kernel<float, R><<<dim3((unsigned)g.nmodes, (unsigned)nrhs), 64, 0, s>>>(
+        g, (const cx<float>*)c->fp_L, (const cx<float>*)c->fp_U, c->fp_piv, ishift, shift_step, spec, active, sA);
   cx<R>* xin = spec;
   if (g.nd == 3) {
-    dft_z<R><<<dim3(nzb, (unsigned)nrhs), 256, zlds, s>>>(g, B, tz, 1, ub, A, active, sA);
+    fft_z<R><<<gz, 256, zlds, s>>>(g, pz, ub, B, tz, 1, A, active, sA);
     xin = A;
   }
-  dft_x_inv<R><<<gl, 256, (size_t)(g.nx + g.mx) * sizeof(cx<R>), s>>>(g, xin, tx, z, sV, active, sA);
+  fft_x_inv<R><<<gx, 256, xlds, s>>>(g, px, P, xin, tx, z, sV, active, sA);
   const long long per = (long long)g.nv * g.nz * 2 * g.nx;
   zero_walls<R><<<dim3((unsigned)((per + 255) / 256), (unsigned)nrhs), 256, 0, s>>>(g, z, sV, active, sA);
   return hipGetLastError();
@@ -553,10 +750,12 @@ int fourier_setup(Ctx* c, const sa_precond_opts* o, int nshift, const double* sh
   // a mode's vector (complex FP64) and the x lines must fit in LDS
   if (g.nx < NOFF || (g.nd == 3 && g.nz < NOFF) || g.ny - 2 < 1)
     return c->fail(SA_EINVAL, "sa_precond_setup: the mean-flow preconditioner needs nx, nz >= %d", NOFF);
-  if ((size_t)g.N * sizeof(cx<double>) > LDS_CAP || (size_t)g.nx * 3 * sizeof(double) > LDS_CAP ||
-      (size_t)g.nz * 2 * sizeof(cx<double>) > LDS_CAP)
+  if ((size_t)g.N * sizeof(cx<double>) > LDS_CAP || (size_t)g.nx * 3 * sizeof(cx<double>) > LDS_CAP ||
+      (size_t)g.nz * 3 * sizeof(cx<double>) > LDS_CAP)
     return c->fail(SA_EINVAL, "sa_precond_setup: grid too large for the mean-flow preconditioner");
-  if (c->nv > 5) return c->fail(SA_EINVAL, "sa_precond_setup: at most 5 variables");
+  // the banded solve keeps the window and a group's entering rows in one
+  // wavefront: KW + BS_GROUP <= 64 (KW = 8 nv - 1), i.e. nv <= 5
+  if (c->nv > 5 || g.KW + BS_GROUP > 64) return c->fail(SA_EINVAL, "sa_precond_setup: at most 5 variables");
   hipStream_t s = c->stream;
   const long long n = c->n, np = c->op.npts;
   const int nv = c->nv;
