@@ -165,6 +165,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-eigs", action="store_true", help="skip the eigen-time record")
     ap.add_argument("--eigs-only", action="store_true", help="only the eigen-time record (3D workload)")
+    ap.add_argument("--sweep", action="store_true", help="only the 48-flow sweep (128^2 - 768^2)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a device copy of known size (counter calibration)")
     ap.add_argument("--bjac-only", action="store_true",
@@ -210,6 +211,9 @@ def main():
     if args.sweep_mid:
         print(json.dumps(sweep(torch, dev, augment=3, modes=("concurrent",), sides=(64, 96, 128), tag="mid",
                                max_matvec=30000, log=lambda m: print(m, file=sys.stderr, flush=True))))
+        return
+    if args.sweep:
+        print(json.dumps(sweep_c4(torch, dev, log=lambda m: print(m, file=sys.stderr, flush=True))))
         return
     if args.eigs_only:
         print(json.dumps(eigs_c2(torch, dev, log=lambda m: print(m, file=sys.stderr, flush=True))))
@@ -606,6 +610,66 @@ def sweep(torch, dev, nev=2, augment=0, modes=("sequential", "concurrent"), log=
             "p99_s": float(np.percentile(secs, 99)), "n_matvec": int(sum(x["n_matvec"] for x in r))}
         if log:
             log("sweep %s %s%s: %.2f s" % (tag, "lgmres " if augment else "", mode, el))
+        for c in ctxs:
+            c.close()
+    return out
+
+
+def sweep_c4(torch, dev, log=None, nev=2):
+    """The 48-flow sweep as configured (sides 128^2 - 768^2, M ~ U[0.1, 0.8],
+    Re ~ U[300, 2000], seed 4), each flow its own Cayley-IRAM problem (nev
+    leading eigenpairs, Arnoldi dimension 16, tol 1e-10) in the mixed form,
+    inner solves right-preconditioned with the mean-flow operator (for
+    these parallel bases, J - sigma I itself, factored per x-Fourier mode).
+    Run twice: in turn on one stream, and concurrently, 16 problems at a
+    time on one stream each (one host thread per problem; torch hands out
+    at most 32 distinct streams per device).  The timed region covers each
+    problem's preconditioner setup and its eigen solve; p50/p99 are over the
+    library's per-problem wall times."""
+    import numpy as np
+    import synth
+    from paper_1502_03701_amd import SA_F32, SA_MIXED, SA_PC_MEAN_FLOW, Context, arnoldi_eigs
+    items = synth.config4_sweep()
+    kw = dict(nev=nev, ncv=16, sigma=0.2, mu=-0.2, tol=1e-10, max_restarts=60, restart=30, lin_tol=1e-12,
+              prec=SA_MIXED, inner_tol=1e-4, use_precond=True)
+    out = {}
+    for mode in ("sequential", "concurrent"):
+        conc = 16
+        pool = [torch.cuda.Stream() for _ in range(conc)]
+        streams = ([torch.cuda.current_stream()] * len(items) if mode == "sequential"
+                   else [pool[i % conc] for i in range(len(items))])
+        ctxs, v0s = [], []
+        for it, st in zip(items, streams):
+            c = Context(stream=st)
+            c.base_set(it.problem, torch.from_numpy(synth.base_flow(it.problem).ravel()).to(dev))
+            ctxs.append(c)
+            v0s.append(torch.from_numpy(synth.random_vector(it.problem, it.seed).ravel()).to(dev))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if mode == "sequential":
+            r = []
+            for c, v in zip(ctxs, v0s):
+                c.precond_setup([0.2], factor_prec=SA_F32, kind=SA_PC_MEAN_FLOW)
+                r += arnoldi_eigs([c], [v], **kw)[1]
+        else:
+            r = []
+            for b in range(0, len(items), conc):
+                for c in ctxs[b:b + conc]:
+                    c.precond_setup([0.2], factor_prec=SA_F32, kind=SA_PC_MEAN_FLOW)
+                r += arnoldi_eigs(ctxs[b:b + conc], v0s[b:b + conc], **kw)[1]
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        secs = np.array([x["seconds"] for x in r])
+        pairs = int(sum(min(x["nconv"], nev) for x in r))
+        out[mode] = {"problems": len(items), "eigenpairs": pairs, "seconds": el, "eigenpairs_per_s": pairs / el,
+                     "p50_s": float(np.percentile(secs, 50)), "p99_s": float(np.percentile(secs, 99)),
+                     "n_cayley": int(sum(x["n_cayley"] for x in r)),
+                     "n_matvec": int(sum(x["n_matvec"] for x in r))}
+        if mode == "sequential":
+            out["leading"] = [[it.problem.n[0], it.problem.mach, it.problem.re, max(x["lam"], key=lambda z: z.real).real]
+                              for it, x in zip(items, r)]
+        if log:
+            log("sweep c4 %s: %.2f s, %d eigenpairs" % (mode, el, pairs))
         for c in ctxs:
             c.close()
     return out

@@ -20,6 +20,9 @@ Contents (each function cites the passage of the paper it follows):
   fourier_pc -- mean-flow preconditioner: J of the base averaged over the
                 periodic axes, solved exactly (Section "Preconditioning",
                 Conclusions).
+  modes      -- x-Fourier blocks A_k of J for bases uniform along x, read
+                off the operator on a seven-point-long grid (the spectrum
+                of J is the union of theirs).
   philox     -- Philox4x32-10 counter-based generator (Salmon et al. 2011)
                 plus Box-Muller, for the seeded block noise.
 """

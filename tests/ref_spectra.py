@@ -34,3 +34,15 @@ def cayley_leading(prob, q0, k, sigma=0.2, mu=-0.2, tol=1e-14, ncv=None, seed=0)
     th = th[np.argsort(-np.abs(th), kind="stable")]
     lam = (sigma * th - mu) / (th - 1.0)
     return lam, th
+
+
+def mode_leading(prob, q0, k=1, sigma=0.25, n=4):
+    """Eigenvalues of the x-Fourier block A_k of the oracle's operator
+    (oracle/modes.py; bases uniform along x) nearest sigma, by ARPACK in
+    shift-invert mode on the sparse banded block, largest real part first.
+    Grid-size independent in cost along x, so it serves full-size 2D grids."""
+    from oracle import modes
+    A = modes.mode_matrix(prob, q0, k, sparse=True)
+    lam = ssl.eigs(A.tocsc(), k=n, sigma=sigma, which="LM", tol=1e-14, return_eigenvectors=False,
+                   v0=np.ones(A.shape[0], dtype=complex))
+    return lam[np.argsort(-lam.real, kind="stable")]

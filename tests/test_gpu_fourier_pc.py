@@ -234,3 +234,38 @@ def test_full_size_3d_residual(fprec):
     ctx.op_apply(z, y, shift=0.2)
     res = float(torch.linalg.norm(y - r) / torch.linalg.norm(r))
     assert res < (1e-9 if fprec == "f64" else 1e-3), res
+
+
+def test_sweep_problems_full_size_against_mode_oracle():
+    """Three problems of the 48-flow sweep at their full size (the smallest
+    and the largest side, and one between), run concurrently on their own
+    streams in the mixed form with the mean-flow preconditioner: the
+    leading (Kelvin-Helmholtz) pair of each against the leading eigenvalue
+    of the oracle's x-Fourier block k = 1 (the x-wavenumber of the box),
+    within 1e-8."""
+    need_gpu()
+    from ref_spectra import mode_leading
+    from paper_1502_03701_amd import SA_F32, SA_MIXED, SA_PC_MEAN_FLOW, Context, arnoldi_eigs
+    items = synth.config4_sweep()
+    sides = [it.problem.n[0] for it in items]
+    pick = [int(np.argmin(sides)), int(np.argmax(sides)), 11]
+    streams = [torch.cuda.Stream() for _ in pick]
+    ctxs, v0s = [], []
+    for i, st in zip(pick, streams):
+        it = items[i]
+        c = Context(stream=st)
+        c.base_set(it.problem, dev(synth.base_flow(it.problem)))
+        c.precond_setup([0.2], factor_prec=SA_F32, kind=SA_PC_MEAN_FLOW)
+        ctxs.append(c)
+        v0s.append(dev(synth.random_vector(it.problem, it.seed)))
+    torch.cuda.synchronize()
+    rc, res = arnoldi_eigs(ctxs, v0s, nev=2, ncv=16, tol=1e-10, max_restarts=60, restart=30, lin_tol=1e-12,
+                           prec=SA_MIXED, inner_tol=1e-4, use_precond=True)
+    assert rc == 0
+    for i, r in zip(pick, res):
+        it = items[i]
+        ref = mode_leading(it.problem, synth.base_flow(it.problem))[0]
+        got = max(r["lam"][:2], key=lambda z: z.real)
+        assert r["nconv"] >= 2
+        assert abs(got - ref) < 1e-8 * abs(ref), (it.problem.n, got, ref)
+        assert all(abs(l - ref) < 1e-8 * abs(ref) for l in r["lam"][:2])

@@ -82,3 +82,55 @@ def test_cuts_iterations_on_a_varying_base():
     assert pre["matvecs"] * 10 < plain["matvecs"]
     xs = np.linalg.solve(J - sigma * np.eye(J.shape[0]), b)
     assert np.linalg.norm(xp - xs) / np.linalg.norm(xs) < 1e-8
+
+
+# ---- x-Fourier blocks of the operator (oracle/modes.py) ----
+
+def test_mode_blocks_map_fourier_perturbations():
+    """J applied to Re(e^{i theta_k i} phi_j) is Re(e^{i theta_k i} (A_k phi)_j)
+    for a random complex phi (the defining property, checked with the full
+    operator on the full grid)."""
+    from oracle import modes
+    prob = synth.mixing_layer_2d(12, 11, 0.5, 800.0)
+    q0 = synth.base_flow(prob)
+    nv, ny, nx = prob.nv, prob.n[1], prob.n[0]
+    rng = np.random.default_rng(3)
+    for k in (0, 1, 5, 6):
+        A = modes.mode_matrix(prob, q0, k)
+        phi = rng.standard_normal(A.shape[0]) + 1j * rng.standard_normal(A.shape[0])
+        ph = np.exp(2j * np.pi * k * np.arange(nx) / nx)
+        def field(w):
+            f = np.zeros(prob.shape, dtype=complex)
+            f[:, 1:ny - 1, :] = w.reshape(ny - 2, nv).T[:, :, None] * ph[None, None, :]
+            return f
+        lhs = op.jv_cstep(prob, q0, field(phi).real)
+        rhs = field(A @ phi).real
+        assert np.abs(lhs - rhs).max() < 1e-12 * np.abs(rhs).max(), k
+
+
+def test_mode_spectra_union_is_the_dense_spectrum():
+    """The union over k of the spectra of A_k is the spectrum of the dense
+    Jacobian; A_{Nx-k} = conj(A_k)."""
+    from oracle import modes
+    prob = synth.mixing_layer_2d(8, 10, 0.4, 600.0)
+    q0 = synth.base_flow(prob)
+    ev = np.linalg.eigvals(op.dense_jacobian(prob, q0))
+    st = modes.stencil(prob, q0)
+    parts = [np.linalg.eigvals(modes.mode_matrix(prob, q0, k, st=st)) for k in range(prob.n[0])]
+    em = np.concatenate(parts)
+    assert len(em) == len(ev)
+    scale = np.abs(ev).max()
+    for lam in ev:
+        assert np.min(np.abs(em - lam)) < 1e-9 * scale
+    for lam in em:
+        assert np.min(np.abs(ev - lam)) < 1e-9 * scale
+    A1 = modes.mode_matrix(prob, q0, 1, st=st)
+    A7 = modes.mode_matrix(prob, q0, 7, st=st)
+    np.testing.assert_allclose(A7, A1.conj(), rtol=0, atol=1e-14 * np.abs(A1).max())
+
+
+def test_mode_blocks_refuse_x_varying_bases():
+    from oracle import modes
+    prob = synth.mixing_layer_2d(8, 10, 0.4, 600.0)
+    with pytest.raises(ValueError):
+        modes.mode_matrix(prob, synth.random_base(prob, 1), 1)
