@@ -42,7 +42,9 @@ constexpr int REACH = 3;
 constexpr int NOFF = 2 * REACH + 1;   // offsets -3 .. 3
 constexpr int NCOL = 7;               // y colours of the probes (> 2 REACH)
 constexpr size_t LDS_CAP = 65536;     // dynamic LDS a launch of this file may take
-constexpr int BS_GROUP = 16;          // steps per prefetch group of the banded solve
+constexpr int BS_GROUP = 16;          // forward steps per prefetch group of the banded solve
+constexpr int BS_GROUP_BACK = 8;      // back-substitution steps per group
+constexpr int FFT_THREADS = 512;      // threads per FFT workgroup (8 waves: LDS-bound occupancy)
 
 struct FGeom {
   int nd, nv, nx, ny, nz;
@@ -168,8 +170,8 @@ __global__ void __launch_bounds__(64) band_lu_kernel(FGeom g, const double* __re
     ezi[d] = sin(az);
   }
   const long long fo = (long long)s * g.nmodes + m;
-  cx<F>* U = Uo + fo * (long long)N * KW;
-  cx<F>* L = Lo + fo * (long long)N * kl;
+  cx<F>* U = Uo + fo * ((long long)N * KW + 1);
+  cx<F>* L = Lo + fo * ((long long)N * kl + 1);
   int* piv = pivo + fo * (long long)N;
   // entry (u, col + jj) of A_k - s I into physical W[pr][(c0 + jj) % KW], one column per lane
   auto gen_row = [&](int u, int col, int pr, int c0) {
@@ -196,6 +198,16 @@ __global__ void __launch_bounds__(64) band_lu_kernel(FGeom g, const double* __re
       W[pr][(c0 + jj) % KW] = cx<F>{(F)vr, (F)vi};
     }
   };
+  // entries Ut[c][d] with d > c (above row 0) are no matrix entries: zero;
+  // so are the slots after each factor, which the solve's idle lanes read
+  if (lane == 0) {
+    U[(long long)N * KW] = cx<F>{F(0), F(0)};
+    L[(long long)N * kl] = cx<F>{F(0), F(0)};
+  }
+  for (int e = lane; e < KW * KW; e += 64) {
+    const int c = e / KW, d = e - c * KW;
+    if (c < N && d > c) U[(long long)c * KW + d] = cx<F>{F(0), F(0)};
+  }
   int r0 = 0, c0 = 0;
   for (int i = 0; i < KH; ++i) gen_row(i, 0, i, 0);
   __syncthreads();
@@ -277,22 +289,62 @@ __global__ void __launch_bounds__(64) band_lu_kernel(FGeom g, const double* __re
 
 // ---------------------------------------------------------------- apply ----
 
-// Radices of a length-n transform, in the order they are applied.
+// Division by a small runtime divisor d with a multiply-high: for a d < 2^32,
+// floor(a / d) = umulhi(a, floor(2^32 / d) + 1).  Magic 0 stands for d = 1.
+unsigned magic_of(int d) { return d <= 1 ? 0u : (unsigned)((1ull << 32) / (unsigned)d + 1ull); }
+__device__ __forceinline__ int fdiv(int a, unsigned m) { return m ? (int)__umulhi((unsigned)a, m) : a; }
+
+// Radices of a length-n transform, in the order they are applied, with each
+// stage's m' = n / (L p) and L (the product of the earlier radices) and
+// their division magics.
+constexpr int FMAX_STAGES = 24;
 struct FPlan {
   int n, ns;
-  int rad[24];
+  unsigned nm;
+  int rad[FMAX_STAGES], mp[FMAX_STAGES], L[FMAX_STAGES];
+  unsigned mpm[FMAX_STAGES], Lm[FMAX_STAGES];
 };
 
 FPlan plan_of(int n) {
   FPlan p{};
   p.n = n;
+  p.nm = magic_of(n);
   int m = n;
   while (m % 4 == 0) { p.rad[p.ns++] = 4; m /= 4; }
   while (m % 2 == 0) { p.rad[p.ns++] = 2; m /= 2; }
   for (int f = 3; f * f <= m; f += 2)
     while (m % f == 0) { p.rad[p.ns++] = f; m /= f; }
   if (m > 1) p.rad[p.ns++] = m;
+  int L = 1;
+  for (int t = 0; t < p.ns; ++t) {
+    p.L[t] = L;
+    p.Lm[t] = magic_of(L);
+    p.mp[t] = n / (L * p.rad[t]);
+    p.mpm[t] = magic_of(p.mp[t]);
+    L *= p.rad[t];
+  }
   return p;
+}
+
+// one output of a stage of radix P_ (0: the runtime radix p)
+template <typename R, int P_>
+__device__ __forceinline__ cx<R> stage_out(const cx<R>* src, int mp, int p, int step, int n, const cx<R>* tw,
+                                           bool inverse) {
+  const int pr = P_ ? P_ : p;
+  R ar = R(0), ai = R(0);
+  int q = 0;
+#pragma unroll
+  for (int r = 0; r < (P_ ? P_ : 64); ++r) {
+    if (!P_ && r >= pr) break;
+    const cx<R> x = src[mp * r];
+    const cx<R> w = tw[q];
+    const R wi = inverse ? -w.im : w.im;
+    ar += x.re * w.re - x.im * wi;
+    ai += x.re * wi + x.im * w.re;
+    q += step;
+    if (q >= n) q -= n;
+  }
+  return cx<R>{ar, ai};
 }
 
 // Self-sorting FFT of P sequences of length n held one after another in a
@@ -305,43 +357,51 @@ FPlan plan_of(int n) {
 template <typename R>
 __device__ cx<R>* stockham(const FPlan& pl, cx<R>* a, cx<R>* b, int P, const cx<R>* __restrict__ tw, bool inverse) {
   const int n = pl.n;
-  int L = 1;
   for (int t = 0; t < pl.ns; ++t) {
-    const int p = pl.rad[t];
-    const int mp = n / (L * p), m = mp * p;
+    const int p = pl.rad[t], mp = pl.mp[t], L = pl.L[t];
+    const unsigned mpm = pl.mpm[t], Lm = pl.Lm[t];
+    const int m = mp * p;
     for (int o = threadIdx.x; o < P * n; o += blockDim.x) {
-      const int sq = o / n, idx = o - sq * n;
-      const int kp = idx / mp, jp = idx - kp * mp;
-      const cx<R>* src = a + sq * n + jp + m * (kp % L);
+      const int sq = fdiv(o, pl.nm), idx = o - sq * n;
+      const int kp = fdiv(idx, mpm), jp = idx - kp * mp;
+      const int kk = kp - fdiv(kp, Lm) * L;
+      const cx<R>* src = a + sq * n + jp + m * kk;
       const int step = kp * mp;   // < n
-      R ar = R(0), ai = R(0);
-      int q = 0;
-      for (int r = 0; r < p; ++r) {
-        const cx<R> x = src[mp * r];
-        const cx<R> w = tw[q];
-        const R wi = inverse ? -w.im : w.im;
-        ar += x.re * w.re - x.im * wi;
-        ai += x.re * wi + x.im * w.re;
-        q += step;
-        if (q >= n) q -= n;
-      }
-      b[o] = cx<R>{ar, ai};
+      b[o] = p == 4   ? stage_out<R, 4>(src, mp, p, step, n, tw, inverse)
+             : p == 2 ? stage_out<R, 2>(src, mp, p, step, n, tw, inverse)
+                      : stage_out<R, 0>(src, mp, p, step, n, tw, inverse);
     }
     __syncthreads();
     cx<R>* t2 = a;
     a = b;
     b = t2;
-    L *= p;
   }
   return a;
 }
 
-// address of interior line lid = k N + u (u = (j-1) nv + v) of system sys
-template <typename R>
+// address of interior line lid = k N + u (u = (j-1) nv + v) within a system,
+// and the offset of its spectrum in [k][kx][u] (add kx N)
 __device__ __forceinline__ long long line_off(const FGeom& g, int lid) {
   const int k = lid / g.N, u = lid - k * g.N;
   const int jr = u / g.nv, v = u - jr * g.nv;
   return (((long long)v * g.nz + k) * g.ny + jr + 1) * g.nx;
+}
+__device__ __forceinline__ long long spec_off(const FGeom& g, int lid) {
+  const int k = lid / g.N, u = lid - k * g.N;
+  return (long long)k * g.mx * g.N + u;
+}
+
+constexpr int XMAX_PAIRS = 16;   // line pairs per workgroup of the x transforms
+
+// the workgroup's lines 2 pair0 .. 2 pair0 + 2P - 1: vector and spectrum
+// offsets (-1 past the last line), computed once into LDS
+__device__ __forceinline__ void line_table(const FGeom& g, int pair0, int P, long long* s_in, long long* s_sp) {
+  const int nl = g.nz * g.N;
+  if (threadIdx.x < 2 * P) {
+    const int lid = 2 * pair0 + threadIdx.x;
+    s_in[threadIdx.x] = lid < nl ? line_off(g, lid) : -1;
+    s_sp[threadIdx.x] = lid < nl ? spec_off(g, lid) : -1;
+  }
 }
 
 // Forward real FFT along x of the interior lines, two lines (a, b) per
@@ -349,51 +409,52 @@ __device__ __forceinline__ long long line_off(const FGeom& g, int lid) {
 // B_k = -i (Z_k - conj Z_{n-k}) / 2.  P line pairs per workgroup;
 // out[sys][k][kx][u] for kx = 0 .. nx/2.
 template <typename R>
-__global__ void __launch_bounds__(256) fft_x_fwd(FGeom g, FPlan pl, int P, const R* __restrict__ r, long long sV,
-                                                 const cx<R>* __restrict__ tw, cx<R>* __restrict__ out,
-                                                 const int* __restrict__ active, long long sA) {
+__global__ void __launch_bounds__(FFT_THREADS) fft_x_fwd(FGeom g, FPlan pl, int P, unsigned Pm, const R* __restrict__ r,
+                                                         long long sV, const cx<R>* __restrict__ tw,
+                                                         cx<R>* __restrict__ out, const int* __restrict__ active,
+                                                         long long sA) {
   extern __shared__ unsigned char smem[];
+  __shared__ long long s_in[2 * XMAX_PAIRS], s_sp[2 * XMAX_PAIRS];
   const int n = g.nx;
   cx<R>* stw = reinterpret_cast<cx<R>*>(smem);
   cx<R>* b0 = stw + n;
   cx<R>* b1 = b0 + P * n;
   const int sys = blockIdx.y;
   if (active && !active[sys * sA]) return;
-  const int nl = g.nz * g.N;
   const int pair0 = blockIdx.x * P;
   const R* src = r + (long long)sys * sV;
-  for (int t = threadIdx.x; t < n; t += 256) stw[t] = tw[t];
-  for (int t = threadIdx.x; t < P * n; t += 256) {
-    const int sq = t / n, i = t - sq * n;
-    const int la = 2 * (pair0 + sq), lb = la + 1;
-    const R a = la < nl ? src[line_off<R>(g, la) + i] : R(0);
-    const R b = lb < nl ? src[line_off<R>(g, lb) + i] : R(0);
+  line_table(g, pair0, P, s_in, s_sp);
+  for (int t = threadIdx.x; t < n; t += FFT_THREADS) stw[t] = tw[t];
+  __syncthreads();
+  for (int t = threadIdx.x; t < P * n; t += FFT_THREADS) {
+    const int sq = fdiv(t, pl.nm), i = t - sq * n;
+    const long long oa = s_in[2 * sq], ob = s_in[2 * sq + 1];
+    const R a = oa >= 0 ? src[oa + i] : R(0);
+    const R b = ob >= 0 ? src[ob + i] : R(0);
     b0[t] = cx<R>{a, b};
   }
   __syncthreads();
   const cx<R>* Z = stockham<R>(pl, b0, b1, P, stw, false);
   cx<R>* dst = out + (long long)sys * g.nz * g.mx * g.N;
-  for (int t = threadIdx.x; t < P * g.mx; t += 256) {
-    const int kx = t / P, sq = t - kx * P;   // consecutive threads: consecutive lines
-    const int la = 2 * (pair0 + sq), lb = la + 1;
-    if (la >= nl) continue;
+  const long long kxs = g.N;
+  for (int t = threadIdx.x; t < P * g.mx; t += FFT_THREADS) {
+    const int kx = fdiv(t, Pm), sq = t - kx * P;   // consecutive threads: consecutive lines
+    const long long sa = s_sp[2 * sq], sb = s_sp[2 * sq + 1];
+    if (sa < 0) continue;
     const cx<R> zk = Z[sq * n + kx], zn = Z[sq * n + (kx == 0 ? 0 : n - kx)];
     const R h = R(0.5);
-    const int ka = la / g.N, ua = la - ka * g.N;
-    dst[((long long)ka * g.mx + kx) * g.N + ua] = cx<R>{h * (zk.re + zn.re), h * (zk.im - zn.im)};
-    if (lb < nl) {
-      const int kb = lb / g.N, ub = lb - kb * g.N;
-      dst[((long long)kb * g.mx + kx) * g.N + ub] = cx<R>{h * (zk.im + zn.im), -h * (zk.re - zn.re)};
-    }
+    dst[sa + kx * kxs] = cx<R>{h * (zk.re + zn.re), h * (zk.im - zn.im)};
+    if (sb >= 0) dst[sb + kx * kxs] = cx<R>{h * (zk.im + zn.im), -h * (zk.re - zn.re)};
   }
 }
 
 // Complex FFT along z between in[sys][k][kx][u] and out[sys][kz][kx][u],
 // a workgroup per (kx, ub consecutive u): the ub sequences in LDS.
 template <typename R>
-__global__ void __launch_bounds__(256) fft_z(FGeom g, FPlan pl, int ub, const cx<R>* __restrict__ in,
-                                             const cx<R>* __restrict__ tw, int inverse, cx<R>* __restrict__ out,
-                                             const int* __restrict__ active, long long sA) {
+__global__ void __launch_bounds__(FFT_THREADS) fft_z(FGeom g, FPlan pl, int ub, unsigned ubm,
+                                                     const cx<R>* __restrict__ in, const cx<R>* __restrict__ tw,
+                                                     int inverse, cx<R>* __restrict__ out,
+                                                     const int* __restrict__ active, long long sA) {
   extern __shared__ unsigned char smem[];
   const int n = g.nz;
   cx<R>* stw = reinterpret_cast<cx<R>*>(smem);
@@ -407,15 +468,15 @@ __global__ void __launch_bounds__(256) fft_z(FGeom g, FPlan pl, int ub, const cx
   const long long plane = (long long)g.mx * g.N;
   const cx<R>* src = in + (long long)sys * n * plane + (long long)kx * g.N + u0;
   cx<R>* dst = out + (long long)sys * n * plane + (long long)kx * g.N + u0;
-  for (int t = threadIdx.x; t < n; t += 256) stw[t] = tw[t];
-  for (int t = threadIdx.x; t < ub * n; t += 256) {
-    const int k = t / ub, uu = t - k * ub;
+  for (int t = threadIdx.x; t < n; t += FFT_THREADS) stw[t] = tw[t];
+  for (int t = threadIdx.x; t < ub * n; t += FFT_THREADS) {
+    const int k = fdiv(t, ubm), uu = t - k * ub;
     b0[uu * n + k] = u0 + uu < g.N ? src[(long long)k * plane + uu] : cx<R>{R(0), R(0)};
   }
   __syncthreads();
   const cx<R>* Z = stockham<R>(pl, b0, b1, ub, stw, inverse != 0);
-  for (int t = threadIdx.x; t < ub * n; t += 256) {
-    const int k = t / ub, uu = t - k * ub;
+  for (int t = threadIdx.x; t < ub * n; t += FFT_THREADS) {
+    const int k = fdiv(t, ubm), uu = t - k * ub;
     if (u0 + uu < g.N) dst[(long long)k * plane + uu] = Z[uu * n + k];
   }
 }
@@ -425,33 +486,30 @@ __global__ void __launch_bounds__(256) fft_z(FGeom g, FPlan pl, int ub, const cx
 // k = 0 and Nyquist terms dropped) into the SoA vector, scaled by
 // 1/(nx nz).  Wall rows of z are written 0 by zero_walls.
 template <typename R>
-__global__ void __launch_bounds__(256) fft_x_inv(FGeom g, FPlan pl, int P, const cx<R>* __restrict__ in,
-                                                 const cx<R>* __restrict__ tw, R* __restrict__ z, long long sV,
-                                                 const int* __restrict__ active, long long sA) {
+__global__ void __launch_bounds__(FFT_THREADS) fft_x_inv(FGeom g, FPlan pl, int P, unsigned Pm,
+                                                         const cx<R>* __restrict__ in, const cx<R>* __restrict__ tw,
+                                                         R* __restrict__ z, long long sV,
+                                                         const int* __restrict__ active, long long sA) {
   extern __shared__ unsigned char smem[];
+  __shared__ long long s_in[2 * XMAX_PAIRS], s_sp[2 * XMAX_PAIRS];
   const int n = g.nx;
   cx<R>* stw = reinterpret_cast<cx<R>*>(smem);
   cx<R>* b0 = stw + n;
   cx<R>* b1 = b0 + P * n;
   const int sys = blockIdx.y;
   if (active && !active[sys * sA]) return;
-  const int nl = g.nz * g.N;
   const int pair0 = blockIdx.x * P;
   const cx<R>* src = in + (long long)sys * g.nz * g.mx * g.N;
-  for (int t = threadIdx.x; t < n; t += 256) stw[t] = tw[t];
+  line_table(g, pair0, P, s_in, s_sp);
+  for (int t = threadIdx.x; t < n; t += FFT_THREADS) stw[t] = tw[t];
+  __syncthreads();
   const bool even = n % 2 == 0;
-  for (int t = threadIdx.x; t < P * g.mx; t += 256) {
-    const int kx = t / P, sq = t - kx * P;
-    const int la = 2 * (pair0 + sq), lb = la + 1;
-    cx<R> A{R(0), R(0)}, B{R(0), R(0)};
-    if (la < nl) {
-      const int ka = la / g.N, ua = la - ka * g.N;
-      A = src[((long long)ka * g.mx + kx) * g.N + ua];
-    }
-    if (lb < nl) {
-      const int kb = lb / g.N, ubb = lb - kb * g.N;
-      B = src[((long long)kb * g.mx + kx) * g.N + ubb];
-    }
+  const long long kxs = g.N;
+  for (int t = threadIdx.x; t < P * g.mx; t += FFT_THREADS) {
+    const int kx = fdiv(t, Pm), sq = t - kx * P;
+    const long long sa = s_sp[2 * sq], sb = s_sp[2 * sq + 1];
+    cx<R> A = sa >= 0 ? src[sa + kx * kxs] : cx<R>{R(0), R(0)};
+    cx<R> B = sb >= 0 ? src[sb + kx * kxs] : cx<R>{R(0), R(0)};
     if (kx == 0 || (even && kx == n / 2)) {
       A.im = R(0);
       B.im = R(0);
@@ -464,12 +522,12 @@ __global__ void __launch_bounds__(256) fft_x_inv(FGeom g, FPlan pl, int P, const
   const cx<R>* Z = stockham<R>(pl, b0, b1, P, stw, true);
   const R scale = R(1) / (R(g.nx) * R(g.nz));
   R* dst = z + (long long)sys * sV;
-  for (int t = threadIdx.x; t < P * n; t += 256) {
-    const int sq = t / n, i = t - sq * n;
-    const int la = 2 * (pair0 + sq), lb = la + 1;
+  for (int t = threadIdx.x; t < P * n; t += FFT_THREADS) {
+    const int sq = fdiv(t, pl.nm), i = t - sq * n;
+    const long long oa = s_in[2 * sq], ob = s_in[2 * sq + 1];
     const cx<R> v = Z[t];
-    if (la < nl) dst[line_off<R>(g, la) + i] = v.re * scale;
-    if (lb < nl) dst[line_off<R>(g, lb) + i] = v.im * scale;
+    if (oa >= 0) dst[oa + i] = v.re * scale;
+    if (ob >= 0) dst[ob + i] = v.im * scale;
   }
 }
 
@@ -501,148 +559,140 @@ __device__ __forceinline__ cx<R> rdlane(cx<R> v, int l) {
   return cx<R>{rdlane(v.re, l), rdlane(v.im, l)};
 }
 
+// whole-wavefront rotation: lane i receives lane (i + 1) mod 64 (DPP wave_rol:1)
+__device__ __forceinline__ float rol1(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x134, 0xf, 0xf, false));
+}
+__device__ __forceinline__ double rol1(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), 0x134, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x134, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <typename R>
+__device__ __forceinline__ cx<R> rol1(cx<R> v) {
+  return cx<R>{rol1(v.re), rol1(v.im)};
+}
+
 // Banded forward and back substitution of one (mode, system) per wavefront,
-// in place on the mode's vector.  Row i of the moving window lives in a
-// register of lane i mod 64; a step broadcasts the finished row with
-// readlane and every window lane updates its own row, so a step is a short
-// chain of ALU operations.  Work is grouped by G steps: everything a group
-// reads from memory (factor rows, the G rows that enter the window) is
-// loaded while the previous group runs, into one of two register sets used
-// in turn; the entering rows are placed at the start of the group (their
-// lanes are free: kl + 1 + G and KW + G do not exceed 64) and the rows the
-// group finishes are stored at its end.  A row's vector entry is only ever
-// read and written by the lane that owns it, so no LDS and no barriers are
-// needed.  System sys uses the factors of shift shift0 + sys * shift_step.
+// in place on the mode's vector.  The moving window sits in registers with
+// lane k holding row col + k (forward) or col - k (back), so a step's factor
+// row is lane-aligned (one load at a uniform address), the finished row is
+// read from lane 0 with readlane, every window lane updates its own row, and
+// the wavefront then rotates by one lane: the next rows move down and the
+// finished row moves to lane 63, where the rows a group finishes collect
+// for one store at the group's end.  The G rows a group brings into the
+// window are loaded, with its factor rows and pivots, while the previous
+// group runs (two register sets used in turn) and placed above the window
+// at the group's start (window + entering + finished rows fit in 64 lanes).
+// System sys uses the factors of shift shift0 + sys * shift_step.
 template <typename F, typename R>
 __global__ void __launch_bounds__(64) band_solve_kernel(FGeom g, const cx<F>* __restrict__ Lo,
                                                         const cx<F>* __restrict__ Uo, const int* __restrict__ pivo,
                                                         int shift0, int shift_step, cx<R>* __restrict__ spec,
                                                         const int* __restrict__ active, long long sA) {
-  constexpr int G = BS_GROUP;
+  constexpr int GF = BS_GROUP, GB = BS_GROUP_BACK;
   const int m = blockIdx.x, sys = blockIdx.y;
   if (active && !active[sys * sA]) return;
   const int lane = threadIdx.x;
   const int N = g.N, kl = g.kl, KW = g.KW;
   const long long fo = (long long)(shift0 + sys * shift_step) * g.nmodes + m;
-  const cx<F>* L = Lo + fo * (long long)N * kl;
-  const cx<F>* Ut = Uo + fo * (long long)N * KW;
+  const cx<F>* L = Lo + fo * ((long long)N * kl + 1);
+  const cx<F>* Ut = Uo + fo * ((long long)N * KW + 1);
   const int* piv = pivo + fo * (long long)N;
   cx<R>* vec = spec + ((long long)sys * g.nmodes + m) * N;   // mode m = kz mx + kx
-  // the loads are unconditional (clamped addresses, the value selected
-  // afterwards): branch-free loads let the next group's stay in flight
+  // loads are unconditional and need no select after them (idle lanes read
+  // the zero slot after the factor; rows past the matrix read a clamped row,
+  // which only rows past the matrix use), so the next group's stay in flight
   auto ldv = [&](bool ok, long long i) {
     const cx<R> v = vec[ok ? i : 0];
     return cx<R>{ok ? v.re : R(0), ok ? v.im : R(0)};
   };
-  auto ldf = [&](const cx<F>* base, bool ok, long long i) {
-    const cx<F> v = base[ok ? i : 0];
-    return cx<F>{ok ? v.re : F(0), ok ? v.im : F(0)};
-  };
-  // forward: P, then L (unit lower, kl multipliers per column); window rows
-  // col .. col + kl
+  // ---- forward: P, then L; lanes 0 .. kl hold rows col .. col + kl
+  const bool lmul = lane >= 1 && lane <= kl;         // lanes with a multiplier
+  const bool fent = lane > kl && lane <= kl + GF;    // lanes of a group's entering rows
+  const long long lzero = (long long)N * kl;         // the zero slot
   cx<R> z = ldv(lane <= kl && lane < N, lane);
   struct FwdSet {
-    cx<F> l[G];
-    cx<R> ent;   // this lane's row entering during the group, if any
-    int pv;      // lane s < G: the pivot offset of column c0 + s
+    cx<F> l[GF];
+    cx<R> ent;
+    int pv;   // lane s < GF: the pivot offset of column c0 + s
   };
   auto load_fwd = [&](int c0, FwdSet& f) {
 #pragma unroll
-    for (int s = 0; s < G; ++s) {
-      const int col = c0 + s;
-      const int d = (lane - col - 1) & 63;
-      f.l[s] = ldf(L, col < N && d < kl && col + 1 + d < N, (long long)col * kl + d);
+    for (int s = 0; s < GF; ++s) {
+      const int col = min(c0 + s, N - 1);   // steps past the end run on row N-1's multipliers
+      f.l[s] = L[lmul ? (long long)col * kl + lane - 1 : lzero];
     }
-    const int e0 = c0 + kl + 1;
-    const int ne = e0 + ((lane - e0) & 63);
-    f.ent = ldv(ne - e0 < G && ne < N, ne);
-    const int pc = c0 + (lane & (G - 1));
-    f.pv = piv[pc < N ? pc : N - 1];
+    f.ent = vec[min(c0 + lane, N - 1)];
+    f.pv = piv[min(c0 + (lane & (GF - 1)), N - 1)];
   };
   auto fwd_group = [&](int c0, const FwdSet& f) {
-    {
-      const int e0 = c0 + kl + 1;
-      if (((lane - e0) & 63) < G) z = f.ent;
-    }
+    if (fent) z = f.ent;
 #pragma unroll
-    for (int s = 0; s < G; ++s) {
-      const int col = c0 + s;
-      if (col < N) {
-        const int l0 = col & 63;
-        const int p = __builtin_amdgcn_readlane(f.pv, s);
-        const cx<R> b = rdlane(z, (col + p) & 63);
-        if (p != 0) {   // uniform: exchange rows col and col + p
-          const cx<R> a = rdlane(z, l0);
-          const int lp = (col + p) & 63;
-          z.re = lane == lp ? a.re : (lane == l0 ? b.re : z.re);
-          z.im = lane == lp ? a.im : (lane == l0 ? b.im : z.im);
-        }
-        const R lr = (R)f.l[s].re, li = (R)f.l[s].im;
-        z.re -= lr * b.re - li * b.im;
-        z.im -= lr * b.im + li * b.re;
+    for (int s = 0; s < GF; ++s) {
+      const int p = __builtin_amdgcn_readlane(f.pv, s);
+      const cx<R> b = rdlane(z, p);
+      if (p != 0) {   // uniform: exchange rows col and col + p
+        const cx<R> a = rdlane(z, 0);
+        z.re = lane == p ? a.re : (lane == 0 ? b.re : z.re);
+        z.im = lane == p ? a.im : (lane == 0 ? b.im : z.im);
       }
+      const R lr = (R)f.l[s].re, li = (R)f.l[s].im;
+      z.re -= lr * b.re - li * b.im;
+      z.im -= lr * b.im + li * b.re;
+      z = rol1(z);
     }
-    // rows c0 .. c0 + G - 1 are final; their lanes keep them past the group
-    const int o = (lane - c0) & 63;
-    if (o < G && c0 + o < N) vec[c0 + o] = z;
+    const int o = lane - (64 - GF);   // lane 64 - GF + s holds row c0 + s
+    if (o >= 0 && c0 + o < N) vec[c0 + o] = z;
   };
   FwdSet fa, fb;
   load_fwd(0, fa);
-  for (int c0 = 0; c0 < N; c0 += 2 * G) {
-    load_fwd(c0 + G, fb);
+  for (int c0 = 0; c0 < N; c0 += 2 * GF) {
+    load_fwd(c0 + GF, fb);
     fwd_group(c0, fa);
-    load_fwd(c0 + 2 * G, fa);
-    fwd_group(c0 + G, fb);
+    load_fwd(c0 + 2 * GF, fa);
+    fwd_group(c0 + GF, fb);
   }
-  // back: column col of U upwards; window rows col - KW + 1 .. col
-  cx<R> r;
-  {
-    const int i = N - 1 - ((N - 1 - lane) & 63);
-    r = ldv(i >= 0 && i >= N - KW, i);
-  }
+  __syncthreads();   // the back substitution reads rows other lanes stored
+  // ---- back: U by columns; lanes 0 .. KW-1 hold rows col .. col - KW + 1
+  const bool umul = lane < KW;
+  const bool bent = lane >= KW && lane < KW + GB;
+  const long long uzero = (long long)N * KW;
+  cx<R> r = ldv(umul && N - 1 - lane >= 0, (long long)N - 1 - lane);
   struct BwdSet {
-    cx<F> u[G];
+    cx<F> u[GB];
     cx<R> ent;
   };
   auto load_bwd = [&](int c0, BwdSet& b) {
 #pragma unroll
-    for (int s = 0; s < G; ++s) {
-      const int col = c0 - s;
-      const int d = (col - lane) & 63;
-      b.u[s] = ldf(Ut, col >= 0 && d < KW && col - d >= 0, (long long)col * KW + d);
+    for (int s = 0; s < GB; ++s) {
+      const int col = max(c0 - s, 0);   // steps past the start run on row 0's column
+      b.u[s] = Ut[umul ? (long long)col * KW + lane : uzero];
     }
-    const int e0 = c0 - KW;   // entering rows e0, e0 - 1, .., e0 - G + 1
-    const int ne = e0 - ((e0 - lane) & 63);
-    b.ent = ldv(e0 - ne < G && ne >= 0, ne);
+    b.ent = vec[max(c0 - lane, 0)];
   };
   auto bwd_group = [&](int c0, const BwdSet& b) {
-    {
-      const int e0 = c0 - KW;
-      if (((e0 - lane) & 63) < G) r = b.ent;
-    }
+    if (bent) r = b.ent;
 #pragma unroll
-    for (int s = 0; s < G; ++s) {
-      const int col = c0 - s;
-      if (col >= 0) {
-        const int l0 = col & 63;
-        const cx<R> u{(R)b.u[s].re, (R)b.u[s].im};
-        const cx<R> t{r.re * u.re - r.im * u.im, r.re * u.im + r.im * u.re};   // lane l0: r / U(col, col)
-        const cx<R> zc = rdlane(t, l0);
-        const bool own = lane == l0;
-        r.re = own ? t.re : r.re - (u.re * zc.re - u.im * zc.im);
-        r.im = own ? t.im : r.im - (u.re * zc.im + u.im * zc.re);
-      }
+    for (int s = 0; s < GB; ++s) {
+      const R ur = (R)b.u[s].re, ui = (R)b.u[s].im;
+      const cx<R> t{r.re * ur - r.im * ui, r.re * ui + r.im * ur};   // lane 0: r / U(col, col)
+      const cx<R> zc = rdlane(t, 0);
+      r.re = lane == 0 ? t.re : r.re - (ur * zc.re - ui * zc.im);
+      r.im = lane == 0 ? t.im : r.im - (ur * zc.im + ui * zc.re);
+      r = rol1(r);
     }
-    const int o = (c0 - lane) & 63;
-    if (o < G && c0 - o >= 0) vec[c0 - o] = r;
+    const int o = lane - (64 - GB);   // lane 64 - GB + s holds row c0 - s
+    if (o >= 0 && c0 - o >= 0) vec[c0 - o] = r;
   };
   BwdSet ba, bb;
   load_bwd(N - 1, ba);
-  for (int c0 = N - 1; c0 >= 0; c0 -= 2 * G) {
-    load_bwd(c0 - G, bb);
+  for (int c0 = N - 1; c0 >= 0; c0 -= 2 * GB) {
+    load_bwd(c0 - GB, bb);
     bwd_group(c0, ba);
-    load_bwd(c0 - 2 * G, ba);
-    bwd_group(c0 - G, bb);
+    load_bwd(c0 - 2 * GB, ba);
+    bwd_group(c0 - GB, bb);
   }
 }
 
@@ -683,7 +733,7 @@ template <typename R>
 int x_pairs(int n) {
   const int cap = (int)(LDS_CAP / sizeof(cx<R>));
   int P = (cap - n) / (2 * n);
-  if (P > 16) P = 16;
+  if (P > XMAX_PAIRS) P = XMAX_PAIRS;
   return P < 1 ? 1 : P;
 }
 template <typename R>
@@ -707,17 +757,19 @@ hipError_t fourier_apply(Ctx* c, int ishift, int nrhs, const R* r, R* z, const i
   const cx<R>* tz = twz_of<R>(c);
   const FPlan px = plan_of(g.nx), pz = plan_of(g.nz);
   const int P = x_pairs<R>(g.nx);
+  const unsigned Pm = magic_of(P);
   const int npair = (g.nz * g.N + 1) / 2;
   const dim3 gx((unsigned)((npair + P - 1) / P), (unsigned)nrhs);
   const size_t xlds = (size_t)(g.nx + 2 * P * g.nx) * sizeof(cx<R>);
   const int ub = z_seqs<R>(g.nz);
+  const unsigned ubm = magic_of(ub);
   const dim3 gz((unsigned)(g.mx * ((g.N + ub - 1) / ub)), (unsigned)nrhs);
   const size_t zlds = (size_t)(g.nz + 2 * ub * g.nz) * sizeof(cx<R>);
   // forward: x (into A), then z (A -> B) in 3D
-  fft_x_fwd<R><<<gx, 256, xlds, s>>>(g, px, P, r, sV, tx, A, active, sA);
+  fft_x_fwd<R><<<gx, FFT_THREADS, xlds, s>>>(g, px, P, Pm, r, sV, tx, A, active, sA);
   cx<R>* spec = A;
   if (g.nd == 3) {
-    fft_z<R><<<gz, 256, zlds, s>>>(g, pz, ub, A, tz, 0, B, active, sA);
+    fft_z<R><<<gz, FFT_THREADS, zlds, s>>>(g, pz, ub, ubm, A, tz, 0, B, active, sA);
     spec = B;
   }
   if (c->fp_f64)
@@ -728,10 +780,10 @@ hipError_t fourier_apply(Ctx* c, int ishift, int nrhs, const R* r, R* z, const i
         g, (const cx<float>*)c->fp_L, (const cx<float>*)c->fp_U, c->fp_piv, ishift, shift_step, spec, active, sA);
   cx<R>* xin = spec;
   if (g.nd == 3) {
-    fft_z<R><<<gz, 256, zlds, s>>>(g, pz, ub, B, tz, 1, A, active, sA);
+    fft_z<R><<<gz, FFT_THREADS, zlds, s>>>(g, pz, ub, ubm, B, tz, 1, A, active, sA);
     xin = A;
   }
-  fft_x_inv<R><<<gx, 256, xlds, s>>>(g, px, P, xin, tx, z, sV, active, sA);
+  fft_x_inv<R><<<gx, FFT_THREADS, xlds, s>>>(g, px, P, Pm, xin, tx, z, sV, active, sA);
   const long long per = (long long)g.nv * g.nz * 2 * g.nx;
   zero_walls<R><<<dim3((unsigned)((per + 255) / 256), (unsigned)nrhs), 256, 0, s>>>(g, z, sV, active, sA);
   return hipGetLastError();
@@ -753,9 +805,11 @@ int fourier_setup(Ctx* c, const sa_precond_opts* o, int nshift, const double* sh
   if ((size_t)g.N * sizeof(cx<double>) > LDS_CAP || (size_t)g.nx * 3 * sizeof(cx<double>) > LDS_CAP ||
       (size_t)g.nz * 3 * sizeof(cx<double>) > LDS_CAP)
     return c->fail(SA_EINVAL, "sa_precond_setup: grid too large for the mean-flow preconditioner");
-  // the banded solve keeps the window and a group's entering rows in one
-  // wavefront: KW + BS_GROUP <= 64 (KW = 8 nv - 1), i.e. nv <= 5
-  if (c->nv > 5 || g.KW + BS_GROUP > 64) return c->fail(SA_EINVAL, "sa_precond_setup: at most 5 variables");
+  // the banded solve keeps the window, a group's entering rows and the rows
+  // it finishes in one wavefront: kl + 1 + 2 BS_GROUP <= 64 and
+  // KW + 2 BS_GROUP_BACK <= 64 (kl = 4 nv - 1, KW = 8 nv - 1), i.e. nv <= 5
+  if (c->nv > 5 || g.kl + 1 + 2 * BS_GROUP > 64 || g.KW + 2 * BS_GROUP_BACK > 64)
+    return c->fail(SA_EINVAL, "sa_precond_setup: at most 5 variables");
   hipStream_t s = c->stream;
   const long long n = c->n, np = c->op.npts;
   const int nv = c->nv;
@@ -772,8 +826,10 @@ int fourier_setup(Ctx* c, const sa_precond_opts* o, int nshift, const double* sh
   double* sh = (double*)c->buffer("fp_shifts", sizeof(double) * nshift, false);
   const size_t fs = o->factor_prec == SA_F64 ? sizeof(double) : sizeof(float);
   const size_t nfac = (size_t)nshift * g.nmodes * g.N;
-  void* Uf = c->buffer("fp_U", 2 * fs * nfac * g.KW, false);
-  void* Lf = c->buffer("fp_L", 2 * fs * nfac * g.kl, false);
+  // per (shift, mode): N KW (U) or N kl (L) entries and one zero slot
+  const size_t nfm = (size_t)nshift * g.nmodes;
+  void* Uf = c->buffer("fp_U", 2 * fs * nfm * ((size_t)g.N * g.KW + 1), false);
+  void* Lf = c->buffer("fp_L", 2 * fs * nfm * ((size_t)g.N * g.kl + 1), false);
   int* pv = (int*)c->buffer("fp_piv", sizeof(int) * nfac, false);
   const int cap = nshift > 1 ? nshift : 1;
   void* A64 = c->buffer("fp_specA64", fourier_spec_bytes(c, cap, 8), false);
