@@ -16,10 +16,16 @@ equations).  Readings taken where the printed system is incomplete:
   lambda = c_p mu / Pr.  Non-dimensional: rho_ref = T_ref = u_inf = delta = 1,
   R = 1/(gamma M^2) so that the reference pressure is 1/(gamma M^2) and
   c_ref = 1/M; mu_ref = 1/Re (0 for an inviscid case).
-* The paper's compact staggered scheme is replaced by explicit 6th-order
-  central first/second differences (reduced to 4th and 2nd order on the two
-  rows next to each wall); mixed derivatives are products of first
-  differences; gradients of mu and lambda use the chain rule mu'(T) D T.
+* First derivatives: explicit 6th-order central differences (reduced to 4th
+  and 2nd order on the two rows next to each wall), or, with
+  prob.scheme == 1, the 6th-order compact (tridiagonal) scheme of Lele that
+  the paper uses for its wave terms (Section "Governing equations", last
+  paragraph), on the collocated grid, with Lele's 4th-order compact row and
+  3rd-order one-sided compact row at each wall.  Second derivatives are the
+  explicit 6th-order central ones in both cases (the paper's 5th-order
+  dissipation scheme is not specified).  Mixed derivatives are products of
+  first differences; gradients of mu and lambda use the chain rule
+  mu'(T) D T.
   The viscous terms are expanded:
       d_j tau_ij = mu L u_i + (mu/3) G_i
                    + mu'(T) [ D_j T (D_j u_i + D_i u_j) - 2/3 D_i T D_k u_k ]
@@ -117,6 +123,56 @@ def d1(f, a, h, bc):
     return np.moveaxis(out, 0, ax)
 
 
+# Lele's tridiagonal 6th-order first derivative (J. Comput. Phys. 103, 1992):
+#   alpha f'_{i-1} + f'_i + alpha f'_{i+1}
+#       = a (f_{i+1} - f_{i-1}) / (2h) + b (f_{i+2} - f_{i-2}) / (4h)
+# with alpha = 1/3, a = 14/9, b = 1/9; at a wall the row next to it is the
+# 4th-order Pade scheme (alpha = 1/4, a = 3/2, b = 0) and the wall row the
+# 3rd-order one-sided scheme f'_0 + 2 f'_1 = (-5/2 f_0 + 2 f_1 + 1/2 f_2)/h.
+_C6_ALPHA, _C6_A, _C6_B = 1.0 / 3.0, 14.0 / 9.0, 1.0 / 9.0
+
+
+def compact_matrices(n, periodic):
+    """(A, B) with A f' = B f / h for the compact first derivative on n points."""
+    A = np.zeros((n, n))
+    B = np.zeros((n, n))
+
+    def interior(i, alpha, a, b):
+        for m, c in ((1, a / 2.0), (2, b / 4.0)):
+            if c == 0.0:
+                continue
+            B[i, (i + m) % n] += c
+            B[i, (i - m) % n] -= c
+        A[i, i] = 1.0
+        A[i, (i + 1) % n] += alpha
+        A[i, (i - 1) % n] += alpha
+
+    if periodic:
+        for i in range(n):
+            interior(i, _C6_ALPHA, _C6_A, _C6_B)
+        return A, B
+    for i in range(2, n - 2):
+        interior(i, _C6_ALPHA, _C6_A, _C6_B)
+    for i in (1, n - 2):
+        interior(i, 0.25, 1.5, 0.0)
+    A[0, 0], A[0, 1] = 1.0, 2.0
+    B[0, 0], B[0, 1], B[0, 2] = -2.5, 2.0, 0.5
+    A[n - 1, n - 1], A[n - 1, n - 2] = 1.0, 2.0
+    B[n - 1, n - 1], B[n - 1, n - 2], B[n - 1, n - 3] = 2.5, -2.0, -0.5
+    return A, B
+
+
+def d1_compact(f, a, h, bc):
+    """Compact first derivative along grid axis a: f' = A^-1 B f / h."""
+    ax = _axis_of(a)
+    g = np.moveaxis(np.asarray(f), ax, 0)
+    n = g.shape[0]
+    A, B = compact_matrices(n, bc == BC_PERIODIC)
+    rhs_ = (B @ g.reshape(n, -1)) / h
+    out = np.linalg.solve(A, rhs_).reshape(g.shape)
+    return np.moveaxis(out, 0, ax)
+
+
 def d2(f, a, h, bc):
     """Second derivative along grid axis a."""
     ax = _axis_of(a)
@@ -197,7 +253,8 @@ def rhs(prob, q):
     lam = c.cp * mu / c.pr
     dlam = c.cp * dmu / c.pr
 
-    D = lambda f, a: d1(f, a, h[a], bc[a])
+    first = d1_compact if getattr(prob, "scheme", 0) == 1 else d1
+    D = lambda f, a: first(f, a, h[a], bc[a])
     D2 = lambda f, a: d2(f, a, h[a], bc[a])
 
     Dp = [D(p, a) for a in range(nd)]

@@ -33,6 +33,10 @@ SUTHERLAND = 110.4 / 288.15
 BC_PERIODIC = 0
 BC_WALL = 1
 
+# first-derivative schemes of the discrete operator
+SCHEME_EXPLICIT = 0   # explicit 6th-order central differences
+SCHEME_COMPACT = 1    # 6th-order compact (tridiagonal) differences
+
 
 @dataclass(frozen=True)
 class Problem:
@@ -46,6 +50,7 @@ class Problem:
     gamma: float = GAMMA
     sutherland: float = SUTHERLAND
     bc: Tuple[int, int, int] = (BC_PERIODIC, BC_WALL, BC_PERIODIC)
+    scheme: int = SCHEME_EXPLICIT
 
     @property
     def nv(self) -> int:
@@ -73,18 +78,19 @@ LY_MIXING = 30.0                    # y in [-15, 15]
 
 def mixing_layer_2d(nx: int, ny: int, mach: float, re: float,
                     lx: float = LX_MIXING, ly: float = LY_MIXING,
-                    bc_y: int = BC_WALL) -> Problem:
+                    bc_y: int = BC_WALL, scheme: int = SCHEME_EXPLICIT) -> Problem:
     return Problem(ndim=2, n=(nx, ny, 1), length=(lx, ly, 1.0), mach=mach, re=re,
-                   bc=(BC_PERIODIC, bc_y, BC_PERIODIC))
+                   bc=(BC_PERIODIC, bc_y, BC_PERIODIC), scheme=scheme)
 
 
 def mixing_layer_3d(nx: int, ny: int, nz: int, mach: float, re: float,
                     lx: float = LX_MIXING, ly: float = LY_MIXING,
-                    lz: float | None = None, bc_y: int = BC_WALL) -> Problem:
+                    lz: float | None = None, bc_y: int = BC_WALL,
+                    scheme: int = SCHEME_EXPLICIT) -> Problem:
     if lz is None:
         lz = lx / 2.0
     return Problem(ndim=3, n=(nx, ny, nz), length=(lx, ly, lz), mach=mach, re=re,
-                   bc=(BC_PERIODIC, bc_y, BC_PERIODIC))
+                   bc=(BC_PERIODIC, bc_y, BC_PERIODIC), scheme=scheme)
 
 
 # ---------------------------------------------------------------------------
