@@ -54,6 +54,14 @@ enum {
 
 typedef enum { SA_F64 = 0, SA_F32 = 1, SA_MIXED = 2 } sa_prec;
 typedef enum { SA_BC_PERIODIC = 0, SA_BC_WALL = 1 } sa_bc;
+/* First derivatives of the discrete operator (Section "Governing equations",
+ * last paragraph).  EXPLICIT: 6th-order central differences, 4th and 2nd
+ * order on the two rows next to a wall.  COMPACT: the 6th-order compact
+ * (tridiagonal) scheme of Lele the paper uses for its wave terms, on the
+ * collocated grid, cyclic on periodic axes, with the 4th-order Pade row next
+ * to a wall and the 3rd-order one-sided compact row at it.  Second
+ * derivatives are the explicit ones in both. */
+typedef enum { SA_SCHEME_EXPLICIT = 0, SA_SCHEME_COMPACT = 1 } sa_scheme;
 
 typedef struct sa_ctx sa_ctx;
 
@@ -68,6 +76,12 @@ typedef struct {
   double len[3];       /* Lx, Ly, Lz                                    */
   int bc_y;            /* sa_bc of the y axis                           */
   double mach, re, pr, gamma, sutherland; /* sutherland = S/T_ref      */
+  int scheme;          /* sa_scheme (0, the zero-initialised default:
+                          explicit).  COMPACT computes each product
+                          derivative-first, one system at a time, in a
+                          context workspace of (ndim + 3)(ndim + 1) + 2 ndim
+                          doubles per grid point; its kernels are not
+                          autotuned (sa_get_jv_variant reports -1). */
 } sa_problem;
 
 typedef struct {

@@ -40,7 +40,8 @@ JV_VARIANTS = ["prefetch_z32", "prefetch_z16", "stage_z16", "stage_z32", "prefet
 class Problem(C.Structure):
     _fields_ = [("ndim", C.c_int), ("n", C.c_int * 3), ("len", C.c_double * 3),
                 ("bc_y", C.c_int), ("mach", C.c_double), ("re", C.c_double),
-                ("pr", C.c_double), ("gamma", C.c_double), ("sutherland", C.c_double)]
+                ("pr", C.c_double), ("gamma", C.c_double), ("sutherland", C.c_double),
+                ("scheme", C.c_int)]
 
 
 class GmresOpts(C.Structure):
@@ -147,7 +148,7 @@ def _check_dev(t, dtype=None, numel=None):
 
 def make_problem(prob) -> Problem:
     """From a synth.Problem-like object (ndim, n, length, bc, mach, re, pr,
-    gamma, sutherland)."""
+    gamma, sutherland, optional scheme)."""
     p = Problem()
     p.ndim = prob.ndim
     for a in range(3):
@@ -156,6 +157,7 @@ def make_problem(prob) -> Problem:
     p.bc_y = prob.bc[1]
     p.mach, p.re, p.pr = prob.mach, prob.re, prob.pr
     p.gamma, p.sutherland = prob.gamma, prob.sutherland
+    p.scheme = getattr(prob, "scheme", 0)
     return p
 
 

@@ -865,8 +865,11 @@ int fourier_setup(Ctx* c, const sa_precond_opts* o, int nshift, const double* sh
   if (e != hipSuccess) return c->hip_fail(e, "sa_precond_setup shifts");
   mean_base_kernel<<<(unsigned)(nv * g.ny), 256, 0, s>>>(g, c->base64, qb);
   zero_fill(flag, 16, s);
+  // the explicit-difference operator of q_bar (also for a compact-scheme
+  // context: there the preconditioner is the cheaper explicit operator)
   OpParams op = c->op;
   op.iso[0] = op.iso[1] = nullptr;
+  op.scheme = 0;
   e = launch_base_derive(op, qb, qb32, flag, s);
   if (e == hipSuccess) e = launch_base_data(op, qb, bd, s);
   if (e != hipSuccess) return c->hip_fail(e, "sa_precond_setup mean base");

@@ -104,6 +104,7 @@ template <typename R>
 hipError_t launch_jv_pert(const OpParams& p, const R* base, const R* bdata, const R* x, R* y, int nrhs, R shift,
                           const int* active, hipStream_t s, long long sX, long long sY, const double* shifts,
                           long long sA, int variant) {
+  if (p.scheme == 1) return launch_jv_compact<R>(p, base, bdata, x, y, nrhs, shift, active, s, sX, sY, shifts, sA);
   if (variant < 0 || variant >= JV_NVARIANTS) variant = sizeof(R) == 8 ? 0 : 2;
   // kernel (0 prefetch, 1 stage) and z planes per workgroup of each variant
   // an iso variant on a base state outside that class: the default kernel

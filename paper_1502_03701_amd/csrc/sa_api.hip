@@ -263,6 +263,8 @@ int sa_base_set(sa_ctx* c, const sa_problem* pb, const double* q0_dev) {
   if (pb->ndim == 2 && pb->n[2] != 1) return c->fail(SA_EINVAL, "sa_base_set: 2D needs n[2] == 1");
   if (pb->bc_y != SA_BC_PERIODIC && pb->bc_y != SA_BC_WALL)
     return c->fail(SA_EINVAL, "sa_base_set: bad bc_y");
+  if (pb->scheme != SA_SCHEME_EXPLICIT && pb->scheme != SA_SCHEME_COMPACT)
+    return c->fail(SA_EINVAL, "sa_base_set: bad scheme");
   if (!(pb->mach > 0) || !(pb->gamma > 1) || !(pb->pr > 0) || !(pb->sutherland > 0))
     return c->fail(SA_EINVAL, "sa_base_set: mach, gamma, pr, sutherland must be positive (gamma > 1)");
   for (int a = 0; a < pb->ndim; ++a)
@@ -284,6 +286,10 @@ int sa_base_set(sa_ctx* c, const sa_problem* pb, const double* q0_dev) {
   op.mu_ref = pb->re > 0 ? 1.0 / pb->re : 0.0;
   op.suth = pb->sutherland;
   op.pr = pb->pr;
+  op.scheme = pb->scheme;
+  op.cwork = nullptr;
+  op.ctab64 = nullptr;
+  op.ctab32 = nullptr;
   c->prob = *pb;
   c->nv = pb->ndim + 2;
   c->n = (long long)c->nv * op.npts;
@@ -312,16 +318,39 @@ int sa_base_set(sa_ctx* c, const sa_problem* pb, const double* q0_dev) {
   e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return c->hip_fail(e, "sa_base_set sync");
   if (hflag) return c->fail(SA_ENONFINITE, "sa_base_set: q0 has NaN/Inf or non-positive pressure");
+  if (op.scheme == SA_SCHEME_COMPACT) {
+    // workspace (one system) and Thomas tables of the compact derivatives
+    const size_t nt = compact_table_elems(op);
+    op.cwork = c->buffer("cwork", sizeof(double) * compact_work_elems(op.ndim, op.npts), false);
+    double* t64 = (double*)c->buffer("ctab64", sizeof(double) * nt, false);
+    float* t32 = (float*)c->buffer("ctab32", sizeof(float) * nt, false);
+    if (!op.cwork || !t64 || !t32) return c->fail(SA_ENOMEM, "sa_base_set: out of device memory");
+    std::vector<double> h64;
+    compact_tables(op, h64);
+    std::vector<float> h32(h64.begin(), h64.end());
+    e = hipMemcpy(t64, h64.data(), sizeof(double) * nt, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(t32, h32.data(), sizeof(float) * nt, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return c->hip_fail(e, "sa_base_set tables");
+    op.ctab64 = t64;
+    op.ctab32 = t32;
+  }
   // discrete derivatives of the base state, once per base state
-  e = launch_base_data(op, c->base64, c->bdata64, c->stream);
+  e = op.scheme == SA_SCHEME_COMPACT ? launch_base_data_compact(op, c->base64, c->bdata64, c->stream)
+                                     : launch_base_data(op, c->base64, c->bdata64, c->stream);
   if (e != hipSuccess) return c->hip_fail(e, "sa_base_set base data");
   cast_d2f((long long)nbd, c->bdata64, c->bdata32, nullptr, c->stream);
   e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return c->hip_fail(e, "sa_base_set base data sync");
-  int rc = setup_iso(c);
-  if (rc != SA_OK) return rc;
-  rc = autotune_jv(c);
-  if (rc != SA_OK) return rc;
+  // the uniform-state and autotuned kernels are explicit-difference kernels
+  if (op.scheme == SA_SCHEME_EXPLICIT) {
+    int rc = setup_iso(c);
+    if (rc != SA_OK) return rc;
+    rc = autotune_jv(c);
+    if (rc != SA_OK) return rc;
+  } else {
+    for (int pr = 0; pr < 2; ++pr)
+      for (int v = 0; v < JV_NVARIANTS; ++v) c->jv_tune_us[pr][v] = 0.0f;
+  }
   c->has_base = true;
   return SA_OK;
 }

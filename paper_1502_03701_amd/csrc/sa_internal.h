@@ -26,6 +26,13 @@ struct OpParams {
   // IsoBase<double> / IsoBase<float> (host memory of the context) when the
   // base state has a uniform thermodynamic state, else null
   const void* iso[2];
+  // first derivatives: 0 explicit differences, 1 compact (compact.hip), with
+  // its workspace (compact_work_elems doubles, one system at a time) and
+  // Thomas tables (compact_table_elems, double and float)
+  int scheme;
+  void* cwork;
+  const double* ctab64;
+  const float* ctab32;
 };
 
 // Base states with uniform p0 and s0 (so uniform T0, rho0, mu0, dT/dp,
@@ -96,6 +103,16 @@ hipError_t launch_jv_batch(const OpParams& p, const R* base, const R* bdata, con
                            long long sX, long long sY, const double* shifts_host, const double* shifts_dev,
                            const int* active, long long sA, hipStream_t s, int variant = -1);
 hipError_t launch_base_data(const OpParams& p, const double* base, double* bdata, hipStream_t s);
+// The compact-derivative operator (compact.hip): y = (J - shift I) x one
+// system at a time through the workspace p.cwork, and its base data.
+template <typename R>
+hipError_t launch_jv_compact(const OpParams& p, const R* base, const R* bdata, const R* x, R* y, int nrhs, R shift,
+                             const int* active, hipStream_t s, long long sX, long long sY, const double* shifts,
+                             long long sA);
+hipError_t launch_base_data_compact(const OpParams& p, const double* base, double* bdata, hipStream_t s);
+size_t compact_work_elems(int ndim, long long npts);
+size_t compact_table_elems(const OpParams& p);
+void compact_tables(const OpParams& p, std::vector<double>& t64);
 // Operator y = (J - shift I) x for nrhs vectors with the kernel variant given
 // (-1: the precision's default).
 template <typename R>
