@@ -304,6 +304,19 @@ __global__ void __launch_bounds__(256) lu_kernel(BLayout L, const double* __rest
 // j = l % 16.
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
+// maximum of v over the wavefront (uniform result): prefix maxima within
+// each row of 16 lanes by DPP row shifts (lanes without a source take
+// INT_MIN), then the four row maxima from lanes 15, 31, 47, 63
+__device__ __forceinline__ int wave_max_bits(int v) {
+  v = max(v, __builtin_amdgcn_update_dpp((int)0x80000000, v, 0x111, 0xf, 0xf, false));   // row_shr:1
+  v = max(v, __builtin_amdgcn_update_dpp((int)0x80000000, v, 0x112, 0xf, 0xf, false));   // row_shr:2
+  v = max(v, __builtin_amdgcn_update_dpp((int)0x80000000, v, 0x114, 0xf, 0xf, false));   // row_shr:4
+  v = max(v, __builtin_amdgcn_update_dpp((int)0x80000000, v, 0x118, 0xf, 0xf, false));   // row_shr:8
+  const int r0 = __builtin_amdgcn_readlane(v, 15), r1 = __builtin_amdgcn_readlane(v, 31);
+  const int r2 = __builtin_amdgcn_readlane(v, 47), r3 = __builtin_amdgcn_readlane(v, 63);
+  return max(max(r0, r1), max(r2, r3));
+}
+
 __global__ void __launch_bounds__(64) lu_mfma_kernel(BLayout L, const double* __restrict__ B,
                                                      const double* __restrict__ shifts, double diag_add,
                                                      float* __restrict__ LU, int* __restrict__ perm,
@@ -319,20 +332,29 @@ __global__ void __launch_bounds__(64) lu_mfma_kernel(BLayout L, const double* __
   lu_work_item(L.nblocks, b, s);
   const double dshift = diag_add - shifts[s];
   const double* Bb = B + b * nb * nb;
-  // 20 loads in flight per lane per batch (the block is 51 KB of FP64)
-  for (int t0 = 0; t0 < nb * nb; t0 += 64 * 20) {
-    double v[20];
+  // by columns (lane: rows lane and lane + 64), 10 columns = 20 loads in
+  // flight per lane per batch (the block is 51 KB of FP64); no index division
+  const bool r1 = lane < nb, r2 = lane + 64 < nb;
+  const int l1 = r1 ? lane : nb - 1;   // clamped rows: loads stay inside the block
+  for (int c0l = 0; c0l < nb; c0l += 10) {
+    double v[10][2];
 #pragma unroll
-    for (int q = 0; q < 20; ++q) {
-      const int t = t0 + lane + 64 * q;
-      v[q] = t < nb * nb ? Bb[t] : 0.0;
+    for (int q = 0; q < 10; ++q) {
+      const int col = min(c0l + q, nb - 1);
+      v[q][0] = Bb[(long long)col * nb + l1];
+      v[q][1] = Bb[(long long)col * nb + (r2 ? lane + 64 : l1)];
     }
 #pragma unroll
-    for (int q = 0; q < 20; ++q) {
-      const int t = t0 + lane + 64 * q;
-      if (t < nb * nb) {
-        const bool diag = t / nb == t % nb;
-        A[(t / nb) * ld + t % nb] = (float)(diag ? (local_wall(L, b, t % nb) ? 1.0 : v[q] + dshift) : v[q]);
+    for (int q = 0; q < 10; ++q) {
+      const int col = c0l + q;
+      if (col < nb && r1) {
+        const double d0 = lane == col ? (local_wall(L, b, col) ? 1.0 : v[q][0] + dshift) : v[q][0];
+        A[col * ld + lane] = (float)d0;
+        if (r2) {
+          const int row = lane + 64;
+          const double d1 = row == col ? (local_wall(L, b, col) ? 1.0 : v[q][1] + dshift) : v[q][1];
+          A[col * ld + row] = (float)d1;
+        }
       }
     }
   }
@@ -341,10 +363,14 @@ __global__ void __launch_bounds__(64) lu_mfma_kernel(BLayout L, const double* __
   bool sing = false;
   const int li = lane % 16, lk = lane / 16;
   for (int c0 = 0; c0 < nb; c0 += 16) {
-    // Panel elimination, columns c0 .. c0+15, in registers: lane l holds rows
-    // c0 + l and c0 + 64 + l of the panel.  Pivot search by a wave butterfly,
-    // row exchanges and the pivot row by uniform-lane reads; the exchanges
-    // are applied to the other columns after the panel.
+    // Panel elimination, columns c0 .. c0+15, in registers: lane l holds the
+    // physical rows c0 + l (slot a) and c0 + 64 + l (slot b) of the panel.
+    // Pivoting is implicit: rows are not exchanged inside the panel; each
+    // row carries its current position (the row exchanges of partial
+    // pivoting applied to positions), a chosen pivot row leaves the
+    // candidates, and the rows are stored at their final positions after
+    // the panel.  The exchanges (piv, in positions) are then applied to the
+    // other columns as usual.
     float P[2][16];
     const int ra = c0 + lane, rb = c0 + 64 + lane;
 #pragma unroll
@@ -352,70 +378,71 @@ __global__ void __launch_bounds__(64) lu_mfma_kernel(BLayout L, const double* __
       P[0][c] = ra < nb ? A[(c0 + c) * ld + ra] : 0.0f;
       P[1][c] = rb < nb ? A[(c0 + c) * ld + rb] : 0.0f;
     }
+    int posa = ra, posb = rb;                  // current positions of the lane's rows
+    bool da = ra >= nb, db = rb >= nb;         // chosen as a pivot already (or no row)
     int piv[16];
 #pragma unroll
     for (int kk = 0; kk < 16; ++kk) {
       const int k = c0 + kk;
-      float best = ra >= k && ra < nb ? fabsf(P[0][kk]) : -1.0f;
-      int bi = ra >= k && ra < nb ? ra : nb;
-      if (rb < nb) {
-        const float v1 = fabsf(P[1][kk]);
-        if (v1 > best) {
-          best = v1;
-          bi = rb;
-        }
-      }
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        const float ov = __shfl_xor(best, off, 64);
-        const int oi = __shfl_xor(bi, off, 64);
-        if (ov > best || (ov == best && oi < bi)) {
-          best = ov;
-          bi = oi;
-        }
-      }
-      if (!(best > 0.0f)) sing = true;
-      const int p = __builtin_amdgcn_readfirstlane(bi < nb ? bi : k);
+      // pivot: the largest |a_ik| over the remaining rows, the one at the
+      // smallest position on ties (a wave max of the magnitudes' bit
+      // patterns, -1 marking no candidate)
+      const float va = da ? -1.0f : fabsf(P[0][kk]);
+      const float vb = db ? -1.0f : fabsf(P[1][kk]);
+      const int wbits = wave_max_bits(__float_as_int(va > vb ? va : vb));
+      const float wmax = __int_as_float(wbits);
+      if (!(wmax > 0.0f)) sing = true;
+      // the candidates holding the maximum; the smallest position wins
+      const int ca = __float_as_int(va) == wbits ? posa : 0x7fffffff;
+      const int cb = __float_as_int(vb) == wbits ? posb : 0x7fffffff;
+      const int p = -wave_max_bits(-(ca < cb ? ca : cb));   // position of the pivot row
+      // its lane and slot
+      const unsigned long long ma = __ballot(!da && posa == p);
+      const bool sp = ma == 0ull;
+      const unsigned long long mp = sp ? __ballot(!db && posb == p) : ma;
+      const int lp = __ffsll((long long)mp) - 1;
       piv[kk] = p;
-      const int lk = k - c0;                                // lane of row k (slot 0)
-      const int lp = (p - c0) & 63, sp = (p - c0) >> 6;    // lane and slot of row p
       float urow[16];
 #pragma unroll
-      for (int c = 0; c < 16; ++c) {
-        const float vk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(P[0][c]), lk));
-        const float vp = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sp ? P[1][c] : P[0][c]), lp));
-        urow[c] = vp;   // row k after the exchange
-        if (p != k) {
-          if (lane == lk) P[0][c] = vp;
-          if (lane == lp) {
-            if (sp) P[1][c] = vk;
-            else P[0][c] = vk;
-          }
+      for (int c = kk; c < 16; ++c)
+        urow[c] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sp ? P[1][c] : P[0][c]), lp));
+      // positions: the row at position k moves to p, the pivot row to k
+      if (p != k) {
+        if (posa == k) posa = p;
+        if (posb == k) posb = p;
+        if (lane == lp) {
+          if (sp) posb = k;
+          else posa = k;
+        }
+        if (lane == 0) {
+          const int t2 = s_perm[k];
+          s_perm[k] = s_perm[p];
+          s_perm[p] = t2;
         }
       }
-      if (p != k && lane == 0) {
-        const int t2 = s_perm[k];
-        s_perm[k] = s_perm[p];
-        s_perm[p] = t2;
+      if (lane == lp) {
+        if (sp) db = true;
+        else da = true;
       }
       const float ipiv = urow[kk] != 0.0f ? 1.0f / urow[kk] : 0.0f;
-      if (ra > k && ra < nb) {
+      if (!da) {
         const float l = P[0][kk] * ipiv;
         P[0][kk] = l;
 #pragma unroll
         for (int c = kk + 1; c < 16; ++c) P[0][c] -= l * urow[c];
       }
-      if (rb < nb) {
+      if (!db) {
         const float l = P[1][kk] * ipiv;
         P[1][kk] = l;
 #pragma unroll
         for (int c = kk + 1; c < 16; ++c) P[1][c] -= l * urow[c];
       }
     }
+    // the panel's rows at their final positions (a row position is unique)
 #pragma unroll
     for (int c = 0; c < 16; ++c) {
-      if (ra < nb) A[(c0 + c) * ld + ra] = P[0][c];
-      if (rb < nb) A[(c0 + c) * ld + rb] = P[1][c];
+      if (ra < nb) A[(c0 + c) * ld + posa] = P[0][c];
+      if (rb < nb) A[(c0 + c) * ld + posb] = P[1][c];
     }
     // the panel's row exchanges on the other columns (a lane per column)
     for (int c = lane; c < nb - 16; c += 64) {
@@ -471,7 +498,10 @@ __global__ void __launch_bounds__(64) lu_mfma_kernel(BLayout L, const double* __
   const int gl = (int)(b % 64);
   const long long ngroups = (L.nblocks + 63) / 64;
   float* out = LU + ((long long)s * ngroups + g) * nb * nb * 64 + gl;
-  for (int t = lane; t < nb * nb; t += 64) out[(long long)t * 64] = A[(t / nb) * ld + t % nb];
+  for (int col = 0; col < nb; ++col) {
+    if (r1) out[((long long)col * nb + lane) * 64] = A[col * ld + lane];
+    if (r2) out[((long long)col * nb + lane + 64) * 64] = A[col * ld + lane + 64];
+  }
   int* pout = perm + ((long long)s * ngroups + g) * nb * 64 + gl;
   for (int t = lane; t < nb; t += 64) pout[t * 64] = s_perm[t];
 }
