@@ -302,7 +302,7 @@ struct FPlan {
   int n, ns;
   unsigned nm;
   int rad[FMAX_STAGES], mp[FMAX_STAGES], L[FMAX_STAGES];
-  unsigned mpm[FMAX_STAGES], Lm[FMAX_STAGES];
+  unsigned mpm[FMAX_STAGES], Lm[FMAX_STAGES], bm[FMAX_STAGES];   // bm: magic of n / p
 };
 
 FPlan plan_of(int n) {
@@ -321,6 +321,7 @@ FPlan plan_of(int n) {
     p.Lm[t] = magic_of(L);
     p.mp[t] = n / (L * p.rad[t]);
     p.mpm[t] = magic_of(p.mp[t]);
+    p.bm[t] = magic_of(n / p.rad[t]);
     L *= p.rad[t];
   }
   return p;
@@ -355,12 +356,64 @@ __device__ __forceinline__ cx<R> stage_out(const cx<R>* src, int mp, int p, int 
 //   A'[j', k'] = sum_r e^{-2 pi i r k' / (L p)} A[j' + m' r, k' mod L],  m' = n/(L p).
 // inverse: conjugate twiddles (unscaled).  Every thread of the block calls it.
 template <typename R>
+__device__ __forceinline__ cx<R> cmul(cx<R> x, cx<R> w, bool conj) {
+  const R wi = conj ? -w.im : w.im;
+  return cx<R>{x.re * w.re - x.im * wi, x.re * wi + x.im * w.re};
+}
+
+// Radix-4 and radix-2 stages as butterflies: the p outputs A'[j', kk + L q]
+// (q = 0 .. p-1) share the inputs A[j' + m' r, kk]; each input is twiddled
+// by e^{-2 pi i r kk / (L p)} and a p-point DFT gives the outputs.
+template <typename R, int RP>
+__device__ __forceinline__ void butterflies(const FPlan& pl, int t, const cx<R>* a, cx<R>* b, int P,
+                                            const cx<R>* __restrict__ tw, bool inverse) {
+  const int n = pl.n, mp = pl.mp[t], L = pl.L[t];
+  const int nbf = n / RP;
+  const int m = mp * RP;
+  for (int o = threadIdx.x; o < P * nbf; o += blockDim.x) {
+    const int sq = fdiv(o, pl.bm[t]), bi = o - sq * nbf;
+    const int kk = fdiv(bi, pl.mpm[t]), jp = bi - kk * mp;
+    const cx<R>* src = a + sq * n + jp + m * kk;
+    cx<R> x[RP];
+#pragma unroll
+    for (int r = 0; r < RP; ++r) {
+      x[r] = src[mp * r];
+      if (r > 0) x[r] = cmul(x[r], tw[r * kk * mp], inverse);   // r kk m' < n
+    }
+    cx<R>* dst = b + sq * n + jp + mp * kk;
+    const long long sL = (long long)mp * L;   // output stride of q
+    if (RP == 2) {
+      dst[0] = cx<R>{x[0].re + x[1].re, x[0].im + x[1].im};
+      dst[sL] = cx<R>{x[0].re - x[1].re, x[0].im - x[1].im};
+    } else {
+      // forward W_4 = -i, inverse +i: x1 * (-+i) = (+- x1.im, -+ x1.re)
+      const cx<R> s02{x[0].re + x[2].re, x[0].im + x[2].im}, d02{x[0].re - x[2].re, x[0].im - x[2].im};
+      const cx<R> s13{x[1].re + x[3].re, x[1].im + x[3].im}, d13{x[1].re - x[3].re, x[1].im - x[3].im};
+      const cx<R> jd13 = inverse ? cx<R>{-d13.im, d13.re} : cx<R>{d13.im, -d13.re};   // W_4 (x1 - x3)
+      dst[0] = cx<R>{s02.re + s13.re, s02.im + s13.im};
+      dst[sL] = cx<R>{d02.re + jd13.re, d02.im + jd13.im};
+      dst[2 * sL] = cx<R>{s02.re - s13.re, s02.im - s13.im};
+      dst[3 * sL] = cx<R>{d02.re - jd13.re, d02.im - jd13.im};
+    }
+  }
+}
+
+template <typename R>
 __device__ cx<R>* stockham(const FPlan& pl, cx<R>* a, cx<R>* b, int P, const cx<R>* __restrict__ tw, bool inverse) {
   const int n = pl.n;
   for (int t = 0; t < pl.ns; ++t) {
     const int p = pl.rad[t], mp = pl.mp[t], L = pl.L[t];
     const unsigned mpm = pl.mpm[t], Lm = pl.Lm[t];
     const int m = mp * p;
+    if (p == 4 || p == 2) {
+      if (p == 4) butterflies<R, 4>(pl, t, a, b, P, tw, inverse);
+      else butterflies<R, 2>(pl, t, a, b, P, tw, inverse);
+      __syncthreads();
+      cx<R>* t2 = a;
+      a = b;
+      b = t2;
+      continue;
+    }
     for (int o = threadIdx.x; o < P * n; o += blockDim.x) {
       const int sq = fdiv(o, pl.nm), idx = o - sq * n;
       const int kp = fdiv(idx, mpm), jp = idx - kp * mp;
