@@ -19,11 +19,16 @@
 // three derivatives and the three viscous fields); for 2D parallel flows
 // none is.
 //
-// Organisation as in jv_prefetch.hip: TX x TY column tiles marching over NZC
-// planes with a register z-queue of the own column, the centre plane with
-// its xy halo staged in LDS, mixed derivatives as first differences of
-// staged first derivatives, all loads of plane k+1 issued before the
-// pointwise algebra of plane k, XCD-aware tile numbering.
+// Organisation: TX x TY column tiles marching over NZC planes with a
+// register z-queue of the own column, the centre plane with its xy halo
+// staged in LDS, XCD-aware tile numbering.  The in-plane mixed derivatives
+// D_x D_y v and D_y D_x u are first differences of staged first derivatives.
+// The mixed derivatives with z are taken in the other order, as z
+// derivatives of in-plane ones (the x, y and z stencils act on different
+// indices, so they commute exactly): D_z of E = (D_x w, D_y w, D_x u + D_y v)
+// of the own column.  E of plane k+3 is formed from that plane's u, v, w
+// staged with their xy halo, and E of planes k-3 .. k+3 lives in an LDS ring
+// of the own thread, so no halo column is ever read along z.
 #include "jv_common.h"
 
 namespace sa {
@@ -35,15 +40,16 @@ constexpr int PW = TX + 6;
 constexpr int PH = TY + 6;
 constexpr int NT = TX * TY;
 constexpr int NHALO = PW * PH - NT;   // staged halo positions of a plane
-constexpr int NXH = 6 * TY;           // x-strip positions needing D_z
-constexpr int NYH = 6 * TX;           // y-strip positions needing D_z
+constexpr int NXH = 6 * TY;           // x-strip positions needing D_y v
+constexpr int NYH = 6 * TX;           // y-strip positions needing D_x u
+constexpr int NRING = 6;              // E of planes k-3 .. k+3 (E[k-3] is read before E[k+3] is written)
 static_assert(NHALO <= NT && NXH + NYH <= NT, "one halo position per thread");
 constexpr int NXCD = 8;
 
 __device__ __forceinline__ int wrapc(int a, int n) { return a < 0 ? a + n : (a >= n ? min(a - n, n - 1) : a); }
 
 template <typename R, int ND, int NZC, bool FULL>
-__global__ void __launch_bounds__(NT, 2) jv_iso_kernel(OpParams op, IsoBase<R> ib, const R* __restrict__ x,
+__global__ void __launch_bounds__(NT, sizeof(R) == 4 && FULL ? 3 : 2) jv_iso_kernel(OpParams op, IsoBase<R> ib, const R* __restrict__ x,
                                                     R* __restrict__ y, R shift, const int* __restrict__ active,
                                                     long long strideX, long long strideY,
                                                     const double* __restrict__ shifts, long long sA, int zchunks,
@@ -66,9 +72,12 @@ __global__ void __launch_bounds__(NT, 2) jv_iso_kernel(OpParams op, IsoBase<R> i
   if (shifts) shift = R(shifts[sys]);
   constexpr int NF = ND + 2;   // p, u_i, s (T' = T_p p' + T_s s' is formed from their derivatives)
   constexpr int NB = iso_fields(ND);
+  constexpr int N3 = ND == 3 ? 1 : 0;
   __shared__ R sP[NF][PH][PW];
-  __shared__ R sX[2][TY][PW];  // D_y v + D_z w, D_z u  (x halo)
-  __shared__ R sY[2][PH][TX];  // D_x u + D_z w, D_z v  (y halo)
+  __shared__ R sX[TY][PW];                         // D_y v (x halo)
+  __shared__ R sY[PH][TX];                         // D_x u (y halo)
+  __shared__ R sN[N3 ? 3 : 1][N3 ? PH : 1][PW];    // u, v, w of plane k+3
+  __shared__ R sE[N3 ? NRING : 1][3][NT];          // ring of E (own thread's slots)
 
   const int tid = threadIdx.x;
   const int ti = tid % TX, tj = tid / TX;
@@ -135,9 +144,6 @@ __global__ void __launch_bounds__(NT, 2) jv_iso_kernel(OpParams op, IsoBase<R> i
     dr = r < 3 ? r : TY + r;
   }
   const int gj_d = dxs ? grow(dr + 3) : grow(dr);
-  const int col_d = gj_d * nx + wrapc(dxs ? i0 - 3 + dc : i0 + dc, nx);
-  const bool wall_d = is_wall(gj_d);
-  const int fb = dxs ? 1 : 2;   // u on x strips, v on y strips (w on both)
   const Axis<R> ayd = axis_coefs<R>(wall_row_order(gj_d, ny, op.bcy));
 
   const int kbeg = ND == 3 ? zc * NZC : 0;
@@ -155,31 +161,83 @@ __global__ void __launch_bounds__(NT, 2) jv_iso_kernel(OpParams op, IsoBase<R> i
     }
   }
 
-  R hv[NF], dzw[6], dzb[6], qn[NF], bq[NB];
+  R hv[NF], hn[3], qn[NF], bq[NB];
+  // u, v, w at the own thread's halo position of plane k (wrapped in z)
+  auto load_halo_uvw = [&](int k) {
+    const int p = wrapc(k, nz) * plane + col_h;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) hn[c] = x[(1 + c) * npts + p];
+  };
+  auto finish_halo_uvw = [&]() {
+    if (wall_h) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) hn[c] = R(0);
+    }
+  };
   auto load_plane = [&](int k) {
     load_raw(k * plane + col_h, hv);
-    if (ND == 3) {
-#pragma unroll
-      for (int m = 0; m < 6; ++m) {
-        const int p = wrapc(k - 3 + m + (m >= 3 ? 1 : 0), nz) * plane + col_d;
-        dzw[m] = x[3 * npts + p];
-        dzb[m] = x[fb * npts + p];
-      }
-    }
+    if (ND == 3) load_halo_uvw(k + 3);
     load_raw((ND == 3 ? wrapc(k + 3, nz) * plane : 0) + col_own, qn);
   };
+  const int cx = ti + 3, cy = tj + 3;
+  // u, v, w of a plane into sN (own point from own[], halo from hn)
+  auto stage_uvw = [&](const R own[3]) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) sN[c][cy][cx] = own[c];
+    if (has_h) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) sN[c][hjj][hii] = hn[c];
+    }
+  };
+  // E = (D_x w, D_y w, D_x u + D_y v) at the own point of the plane in sN
+  auto form_E = [&](R e[3]) {
+    R wx = R(0), wy = R(0), ux = R(0), vy = R(0);
+#pragma unroll
+    for (int m = 1; m <= 3; ++m) {
+      wx += ax.c1[m - 1] * (sN[2][cy][cx + m] - sN[2][cy][cx - m]);
+      wy += ayc.c1[m - 1] * (sN[2][cy + m][cx] - sN[2][cy - m][cx]);
+      ux += ax.c1[m - 1] * (sN[0][cy][cx + m] - sN[0][cy][cx - m]);
+      vy += ayc.c1[m - 1] * (sN[1][cy + m][cx] - sN[1][cy - m][cx]);
+    }
+    e[0] = wx * ihx;
+    e[1] = wy * ihy;
+    e[2] = ux * ihx + vy * ihy;
+  };
+  if (ND == 3) {
+    // E of planes kbeg-3 .. kbeg+2 into ring slots 0 .. 5
+    for (int m = 0; m < 6; ++m) {
+      load_halo_uvw(kbeg - 3 + m);
+      finish_halo_uvw();
+      R own[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) own[c] = zq[1 + c][m];
+      __syncthreads();
+      stage_uvw(own);
+      __syncthreads();
+      R e[3];
+      form_E(e);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) sE[m][c][tid] = e[c];
+    }
+  }
   // base data of the own point: zero fields are not loaded, profiles come
   // from the (x = 0, z = 0) column, general fields stream once (nontemporal)
+  // The masks and the field stride pass through an empty asm each plane so
+  // that the per-field offsets are recomputed there (a few scalar
+  // instructions) instead of being hoisted into 2 NB live scalar registers.
   auto load_base = [&](int k) {
+    unsigned gm = ib.gmask, pm = ib.pmask;
+    int np = npts;
+    asm volatile("" : "+s"(gm), "+s"(pm), "+s"(np));
     const int pg = k * plane + col_own;
     const int pp = jrow * nx;
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
-      const int kind = ib.kind[q];
-      if (kind == ISO_GENERAL)
-        bq[q] = __builtin_nontemporal_load(ib.f[q] + pg);
-      else if (kind == ISO_PROFILE)
-        bq[q] = ib.f[q][pp];
+      const int off = iso_fidx(ND, q) * np;
+      if (gm >> q & 1u)
+        bq[q] = __builtin_nontemporal_load(ib.bd + (off + pg));
+      else if (pm >> q & 1u)
+        bq[q] = ib.bd[off + pp];
       else
         bq[q] = R(0);
     }
@@ -189,38 +247,28 @@ __global__ void __launch_bounds__(NT, 2) jv_iso_kernel(OpParams op, IsoBase<R> i
     load_plane(k);
     load_base(k);
     finish_raw(wall_h, hv);
+    if (ND == 3) finish_halo_uvw();
     finish_raw(wall_own, qn);
     __syncthreads();
 #pragma unroll
-    for (int f = 0; f < NF; ++f) sP[f][tj + 3][ti + 3] = ND == 3 ? zq[f][3] : qn[f];
+    for (int f = 0; f < NF; ++f) sP[f][cy][cx] = ND == 3 ? zq[f][3] : qn[f];
     if (has_h) {
 #pragma unroll
       for (int f = 0; f < NF; ++f) sP[f][hjj][hii] = hv[f];
     }
+    if (ND == 3) stage_uvw(&qn[1]);
     __syncthreads();
     if (has_d) {
-      R dzwv = R(0), dzbv = R(0);
-      if (ND == 3 && !wall_d) {
-#pragma unroll
-        for (int m = 1; m <= 3; ++m) {
-          dzwv += az.c1[m - 1] * (dzw[2 + m] - dzw[3 - m]);
-          dzbv += az.c1[m - 1] * (dzb[2 + m] - dzb[3 - m]);
-        }
-        dzwv *= ihz;
-        dzbv *= ihz;
-      }
       if (dxs) {
         R dyv = R(0);
 #pragma unroll
         for (int m = 1; m <= 3; ++m) dyv += ayd.c1[m - 1] * (sP[2][dr + 3 + m][dc] - sP[2][dr + 3 - m][dc]);
-        sX[0][dr][dc] = dyv * ihy + dzwv;
-        sX[1][dr][dc] = dzbv;
+        sX[dr][dc] = dyv * ihy;
       } else {
         R dxu = R(0);
 #pragma unroll
         for (int m = 1; m <= 3; ++m) dxu += ax.c1[m - 1] * (sP[1][dr][dc + 3 + m] - sP[1][dr][dc + 3 - m]);
-        sY[0][dr][dc] = dxu * ihx + dzwv;
-        sY[1][dr][dc] = dzbv;
+        sY[dr][dc] = dxu * ihx;
       }
     }
     // ---- base data of the point, and the quantities derived from it ----
@@ -248,7 +296,6 @@ __global__ void __launch_bounds__(NT, 2) jv_iso_kernel(OpParams op, IsoBase<R> i
 
     // ---- derivatives of the own point's fields: x, y from LDS, z from the
     // queue; the tangent-linear is accumulated as each field is done ----
-    const int cx = ti + 3, cy = tj + 3;
     auto stencil = [&](int f, R& c0, R D[ND], R& L, R& d2own, int own) {
       c0 = sP[f][cy][cx];
       R a1x = R(0), a2x = R(0), a1y = R(0), a2y = R(0), a1z = R(0), a2z = R(0);
@@ -309,7 +356,7 @@ __global__ void __launch_bounds__(NT, 2) jv_iso_kernel(OpParams op, IsoBase<R> i
     }
     // velocities: divergence, strain products, advection, viscous terms
     R thp = R(0), S0p = R(0);
-    R dyv = R(0), dxu = R(0), dzu = R(0), dzv = R(0), dzw_own = R(0);
+    R dyv = R(0), dxu = R(0);
 #pragma unroll
     for (int c = 0; c < ND; ++c) {
       R uc, Du[ND], Lu, d2c;
@@ -324,44 +371,43 @@ __global__ void __launch_bounds__(NT, 2) jv_iso_kernel(OpParams op, IsoBase<R> i
 #pragma unroll
       for (int i2 = 0; i2 < ND; ++i2) accU[i2] -= uc * Du0[i2][c];
       accU[c] += -advu + ib.mu0 * ib.irho * (Lu + d2c * R(1.0 / 3.0)) - shift * uc;
-      // first derivatives the mixed terms of G' need at the own point
-      if (c == 0) {
-        dxu = Du[0];
-        dzu = Du[ND - 1];
-      }
-      if (c == 1) {
-        dyv = Du[1];
-        dzv = Du[ND - 1];
-      }
-      if constexpr (ND == 3) {
-        if (c == 2) dzw_own = Du[2];
-      }
+      // first derivatives the in-plane mixed terms of G' need at the own point
+      if (c == 0) dxu = Du[0];
+      if (c == 1) dyv = Du[1];
     }
     Hp += ib.mu0 * (R(4) * S0p - R(4.0 / 3.0) * th0 * thp);
     acc0 += -gam * ib.p0 * thp;
-    sX[0][tj][cx] = dyv + dzw_own;
-    sY[0][cy][ti] = dxu + dzw_own;
-    if constexpr (ND == 3) {
-      sX[1][tj][cx] = dzu;
-      sY[1][cy][ti] = dzv;
+    // D_z E at plane k; E[k+m] sits in ring slot (k - kbeg + 3 + m) mod 6
+    R dzE[3] = {R(0), R(0), R(0)};
+    if (ND == 3) {
+      const int r0 = k - kbeg;
+      const int sm3 = r0 % NRING, sp1 = (r0 + 4) % NRING, sm1 = (r0 + 2) % NRING;
+      const int sp2 = (r0 + 5) % NRING, sm2 = (r0 + 1) % NRING;
+      R e3[3];
+      form_E(e3);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const R em3 = sE[sm3][c][tid];
+        sE[sm3][c][tid] = e3[c];
+        dzE[c] = (az.c1[0] * (sE[sp1][c][tid] - sE[sm1][c][tid]) + az.c1[1] * (sE[sp2][c][tid] - sE[sm2][c][tid]) +
+                  az.c1[2] * (e3[c] - em3)) * ihz;
+      }
     }
+    sX[tj][cx] = dyv;
+    sY[cy][ti] = dxu;
     __syncthreads();
     {
-      // mixed parts of G'_i: D_x(D_y v + D_z w), D_y(D_x u + D_z w), D_x(D_z u) + D_y(D_z v)
-      R gxs = R(0), gys = R(0), gz1 = R(0), gz2 = R(0);
+      // mixed parts of G'_i: D_x D_y v + D_z D_x w, D_y D_x u + D_z D_y w, D_z (D_x u + D_y v)
+      R gxs = R(0), gys = R(0);
 #pragma unroll
       for (int m = 1; m <= 3; ++m) {
-        gxs += ax.c1[m - 1] * (sX[0][tj][cx + m] - sX[0][tj][cx - m]);
-        gys += ayc.c1[m - 1] * (sY[0][cy + m][ti] - sY[0][cy - m][ti]);
-        if (ND == 3) {
-          gz1 += ax.c1[m - 1] * (sX[1][tj][cx + m] - sX[1][tj][cx - m]);
-          gz2 += ayc.c1[m - 1] * (sY[1][cy + m][ti] - sY[1][cy - m][ti]);
-        }
+        gxs += ax.c1[m - 1] * (sX[tj][cx + m] - sX[tj][cx - m]);
+        gys += ayc.c1[m - 1] * (sY[cy + m][ti] - sY[cy - m][ti]);
       }
       const R cg = ib.mu0 * ib.irho * R(1.0 / 3.0);
-      accU[0] += cg * (gxs * ihx);
-      accU[1] += cg * (gys * ihy);
-      if constexpr (ND == 3) accU[2] += cg * (gz1 * ihx + gz2 * ihy);
+      accU[0] += cg * (gxs * ihx + dzE[0]);
+      accU[1] += cg * (gys * ihy + dzE[1]);
+      if constexpr (ND == 3) accU[2] += cg * dzE[2];
     }
     if (ND == 3) {
 #pragma unroll

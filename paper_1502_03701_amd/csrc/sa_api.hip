@@ -72,11 +72,10 @@ static int setup_iso(Ctx* c) {
   c->iso = false;
   const int nd = op.ndim, nv = c->nv;
   const int nf = iso_fields(nd);
+  // the iso kernels index the base data with 32-bit offsets
+  if ((long long)(iso_fidx(nd, nf - 1) + 1) * op.npts >= (1LL << 31)) return SA_OK;
   int fidx[ISO_MAXF];
-  for (int i = 0; i < nd; ++i) fidx[i] = 1 + i;                                   // u0_i
-  for (int i = 0; i < nd; ++i)
-    for (int a = 0; a < nd; ++a) fidx[nd + i * nd + a] = 2 + 2 * nd + i * nd + a;   // D_a u0_i
-  for (int i = 0; i < nd; ++i) fidx[nd + nd * nd + i] = 2 + 4 * nd + nd * nd + i;   // L u0_i + G0_i/3
+  for (int q = 0; q < nf; ++q) fidx[q] = iso_fidx(nd, q);
   int* flags = (int*)c->buffer("iso_flags", 3 * sizeof(int), false);
   if (!flags) return c->fail(SA_ENOMEM, "sa_base_set: out of device memory");
   hipError_t e = hipMemsetAsync(flags, 0, 3 * sizeof(int), c->stream);
@@ -99,13 +98,14 @@ static int setup_iso(Ctx* c) {
   const double muT = mu0 * (1.5 / T0 - 1.0 / (T0 + S));
   auto fill = [&](auto& ib, auto* bd) {
     using R = std::remove_reference_t<decltype(ib.Tp)>;
-    for (int q = 0; q < ISO_MAXF; ++q) {
-      ib.f[q] = nullptr;
-      ib.kind[q] = ISO_ZERO;
-    }
+    ib.bd = bd;
+    ib.gmask = ib.pmask = 0;
     for (int q = 0; q < nf; ++q) {
-      ib.f[q] = bd + (long long)fidx[q] * np;
-      ib.kind[q] = !(hf[1] >> q & 1) ? ISO_ZERO : (!(hf[2] >> q & 1) ? ISO_PROFILE : ISO_GENERAL);
+      if (!(hf[1] >> q & 1)) continue;           // identically zero
+      if (hf[2] >> q & 1)
+        ib.gmask |= 1u << q;
+      else
+        ib.pmask |= 1u << q;
     }
     ib.Tp = R(h[3]);
     ib.Ts = R(h[4]);

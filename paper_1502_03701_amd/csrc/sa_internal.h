@@ -40,13 +40,17 @@ struct OpParams {
 // L u0_i + G0_i/3 (iso_fields(ND) fields, in that order, D_a u0_i at
 // ND + i ND + a), each classified exactly as identically zero, a y profile
 // (equal along x and z; read at x = 0, z = 0) or general.
-constexpr int ISO_ZERO = 0, ISO_PROFILE = 1, ISO_GENERAL = 2;
 constexpr int ISO_MAXF = 15;
 __host__ __device__ constexpr int iso_fields(int nd) { return nd + nd * nd + nd; }
+// base-data field holding iso field q: u0_i at 1 + i, D_a u0_i at
+// 2 + 2 nd + i nd + a, L u0_i + G0_i/3 at 2 + 4 nd + nd^2 + i
+__host__ __device__ constexpr int iso_fidx(int nd, int q) {
+  return q < nd ? 1 + q : (q < nd + nd * nd ? 2 + 2 * nd + (q - nd) : 2 + 4 * nd + nd * nd + (q - nd - nd * nd));
+}
 template <typename R>
 struct IsoBase {
-  const R* f[ISO_MAXF];    // field q: start of its base-data field (general: [point], profile: [j nx])
-  int kind[ISO_MAXF];      // ISO_ZERO / ISO_PROFILE / ISO_GENERAL
+  const R* bd;             // base data: field f at bd + f npts (general: [point], profile: [j nx])
+  unsigned gmask, pmask;   // bit q: iso field q general / a y profile (neither: zero)
   R Tp, Ts;                // dT/dp, dT/ds
   R p0, ip0, T0, rho, irho, irT;   // irT = 1/(rho T0)
   R mu0, muT, lam0;        // mu(T0), mu'(T0), c_p mu(T0)/Pr
