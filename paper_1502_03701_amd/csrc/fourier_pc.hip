@@ -50,6 +50,7 @@ struct FGeom {
   int nd, nv, nx, ny, nz;
   int mx, mz, nmodes;   // modes: kx = 0 .. mx-1 (real DFT), kz = 0 .. mz-1
   int N, kl, ku, KW;    // unknowns per mode, bandwidths, window width
+  int KU;               // column length of the packed U (set up: <= KW)
   long long npts, n;
 };
 
@@ -66,6 +67,7 @@ FGeom geom_of(const Ctx* c) {
   g.N = (g.ny - 2) * g.nv;
   g.kl = g.ku = REACH * g.nv + g.nv - 1;
   g.KW = g.kl + g.ku + 1;
+  g.KU = c->fp_ku > 0 ? c->fp_ku : g.KW;
   g.npts = c->op.npts;
   g.n = c->n;
   return g;
@@ -141,7 +143,8 @@ __global__ void gather_kernel(FGeom g, int c, const double* __restrict__ Y, doub
 // (r0 + i) % KH, logical column jj (matrix column col + jj) at physical
 // column (c0 + jj) % KW.  Factor layout per (shift, mode), each row of it
 // what one substitution step reads: Ut[c][0] = 1 / U(c, c) and Ut[c][d] =
-// U(c - d, c) for d = 1 .. KW-1 (column c of U upwards from the diagonal);
+// U(c - d, c) for d = 1 .. KW-1 (column c of U upwards from the diagonal;
+// u_pack_kernel turns it into the layout the back substitution reads);
 // L[u][0 .. kl), the multiplier of row u + 1 + d at step u; piv[u] in
 // [0, kl], row u exchanged with row u + piv[u].
 template <typename F>
@@ -285,6 +288,57 @@ __global__ void __launch_bounds__(64) band_lu_kernel(FGeom g, const double* __re
     __syncthreads();
   }
   if (sing && lane == 0) atomicOr(singular, 1);
+}
+
+// Row exchanges reach only a few rows, so U's columns stay far inside the
+// kl + ku band the factorisation allows (at C2 about 22 of 39 entries): the
+// back substitution reads columns of the exact common length KU.
+// ext = max over every (shift, mode) block and column of the largest d with
+// U(c - d, c) != 0.  Grid: x over a block's N KW entries, y strides blocks
+// (a few y rows: one atomic per wavefront, not per entry).
+template <typename F>
+__global__ void __launch_bounds__(256) u_extent_kernel(FGeom g, long long nblk, const cx<F>* __restrict__ U,
+                                                       int* __restrict__ ext) {
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  const int nU = g.N * g.KW;
+  int e = 0;
+  if (r < nU) {
+    const int d = r % g.KW;
+    for (long long b = blockIdx.y; b < nblk; b += gridDim.y) {
+      const cx<F> u = U[b * ((long long)nU + 1) + r];
+      if (d > e && (u.re != F(0) || u.im != F(0))) e = d;
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) e = max(e, __shfl_xor(e, off, 64));
+  if ((threadIdx.x & 63) == 0 && e > 0) atomicMax(ext, e);
+}
+
+// The layout the back substitution reads, KU entries per column: Uc[c][d] =
+// U(c - d, c) / U(c, c) for d = 1 .. KU-1 and Uc[c][0] = 1 - 1 / U(c, c), so
+// one multiply-add form serves every lane of a step (lane 0 turns r_0 into
+// r_0 / U(c, c)); a zero slot after each block.
+template <typename F>
+__global__ void __launch_bounds__(256) u_pack_kernel(FGeom g, long long nblk, int KU, const cx<F>* __restrict__ U,
+                                                     cx<F>* __restrict__ Uc) {
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  const int nc = g.N * KU;
+  if (r > nc) return;
+  const int c = r / KU, d = r - c * KU;
+  for (long long b = blockIdx.y; b < nblk; b += gridDim.y) {
+    cx<F> out{F(0), F(0)};
+    if (r < nc) {
+      const cx<F>* col = U + b * ((long long)g.N * g.KW + 1) + (long long)c * g.KW;
+      const cx<F> iv = col[0];
+      if (d == 0) {
+        out = cx<F>{F(1) - iv.re, -iv.im};
+      } else {
+        const cx<F> u = col[d];
+        out = cx<F>{u.re * iv.re - u.im * iv.im, u.re * iv.im + u.im * iv.re};
+      }
+    }
+    Uc[b * ((long long)nc + 1) + r] = out;
+  }
 }
 
 // ---------------------------------------------------------------- apply ----
@@ -612,26 +666,38 @@ __device__ __forceinline__ cx<R> rdlane(cx<R> v, int l) {
   return cx<R>{rdlane(v.re, l), rdlane(v.im, l)};
 }
 
-// whole-wavefront rotation: lane i receives lane (i + 1) mod 64 (DPP wave_rol:1)
+// whole-wavefront rotation: lane i receives lane (i + 1) mod 64 (DPP
+// wave_rol:1; every lane has a source, so no old value is needed)
 __device__ __forceinline__ float rol1(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x134, 0xf, 0xf, false));
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x134, 0xf, 0xf, false));
 }
 __device__ __forceinline__ double rol1(double v) {
   const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), 0x134, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x134, 0xf, 0xf, false);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffLL), 0x134, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x134, 0xf, 0xf, false);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 template <typename R>
 __device__ __forceinline__ cx<R> rol1(cx<R> v) {
   return cx<R>{rol1(v.re), rol1(v.im)};
 }
+// z - l b in four fused multiply-adds (b wave-uniform)
+template <typename R>
+__device__ __forceinline__ cx<R> cfms(cx<R> z, R lr, R li, cx<R> b) {
+  R re = fma(-lr, b.re, z.re);
+  re = fma(li, b.im, re);
+  R im = fma(-lr, b.im, z.im);
+  im = fma(-li, b.re, im);
+  return cx<R>{re, im};
+}
 
 // Banded forward and back substitution of one (mode, system) per wavefront,
 // in place on the mode's vector.  The moving window sits in registers with
 // lane k holding row col + k (forward) or col - k (back), so a step's factor
 // row is lane-aligned (one load at a uniform address), the finished row is
-// read from lane 0 with readlane, every window lane updates its own row, and
+// read from lane 0 with readlane, every window lane updates its own row with
+// four fused multiply-adds (in the back substitution lane 0 too: the packed
+// U makes its update the division by the pivot), and
 // the wavefront then rotates by one lane: the next rows move down and the
 // finished row moves to lane 63, where the rows a group finishes collect
 // for one store at the group's end.  The G rows a group brings into the
@@ -648,10 +714,11 @@ __global__ void __launch_bounds__(64) band_solve_kernel(FGeom g, const cx<F>* __
   const int m = blockIdx.x, sys = blockIdx.y;
   if (active && !active[sys * sA]) return;
   const int lane = threadIdx.x;
-  const int N = g.N, kl = g.kl, KW = g.KW;
+  const int N = g.N, kl = g.kl;
   const long long fo = (long long)(shift0 + sys * shift_step) * g.nmodes + m;
   const cx<F>* L = Lo + fo * ((long long)N * kl + 1);
-  const cx<F>* Ut = Uo + fo * ((long long)N * KW + 1);
+  const int KU = g.KU;
+  const cx<F>* Ut = Uo + fo * ((long long)N * KU + 1);
   const int* piv = pivo + fo * (long long)N;
   cx<R>* vec = spec + ((long long)sys * g.nmodes + m) * N;   // mode m = kz mx + kx
   // loads are unconditional and need no select after them (idle lanes read
@@ -669,32 +736,36 @@ __global__ void __launch_bounds__(64) band_solve_kernel(FGeom g, const cx<F>* __
   struct FwdSet {
     cx<F> l[GF];
     cx<R> ent;
-    int pv;   // lane s < GF: the pivot offset of column c0 + s
+    int pv[GF];   // pivot offsets of columns c0 .. c0 + GF - 1 (uniform: scalar loads)
   };
+  // a factor row at a uniform base address plus a per-lane 32-bit byte
+  // offset (one select per load): lane - 1 for the multiplier lanes, the
+  // zero slot for the others
+  const unsigned lmoff = (unsigned)(lane - 1) * (unsigned)sizeof(cx<F>);
   auto load_fwd = [&](int c0, FwdSet& f) {
 #pragma unroll
     for (int s = 0; s < GF; ++s) {
       const int col = min(c0 + s, N - 1);   // steps past the end run on row N-1's multipliers
-      f.l[s] = L[lmul ? (long long)col * kl + lane - 1 : lzero];
+      const long long rb = (long long)col * kl;
+      const unsigned off = lmul ? lmoff : (unsigned)((lzero - rb) * (long long)sizeof(cx<F>));
+      f.l[s] = *reinterpret_cast<const cx<F>*>(reinterpret_cast<const char*>(L + rb) + off);
     }
     f.ent = vec[min(c0 + lane, N - 1)];
-    f.pv = piv[min(c0 + (lane & (GF - 1)), N - 1)];
+#pragma unroll
+    for (int s = 0; s < GF; ++s) f.pv[s] = piv[min(c0 + s, N - 1)];
   };
   auto fwd_group = [&](int c0, const FwdSet& f) {
     if (fent) z = f.ent;
 #pragma unroll
     for (int s = 0; s < GF; ++s) {
-      const int p = __builtin_amdgcn_readlane(f.pv, s);
+      const int p = f.pv[s];
       const cx<R> b = rdlane(z, p);
       if (p != 0) {   // uniform: exchange rows col and col + p
         const cx<R> a = rdlane(z, 0);
         z.re = lane == p ? a.re : (lane == 0 ? b.re : z.re);
         z.im = lane == p ? a.im : (lane == 0 ? b.im : z.im);
       }
-      const R lr = (R)f.l[s].re, li = (R)f.l[s].im;
-      z.re -= lr * b.re - li * b.im;
-      z.im -= lr * b.im + li * b.re;
-      z = rol1(z);
+      z = rol1(cfms(z, (R)f.l[s].re, (R)f.l[s].im, b));
     }
     const int o = lane - (64 - GF);   // lane 64 - GF + s holds row c0 + s
     if (o >= 0 && c0 + o < N) vec[c0 + o] = z;
@@ -708,20 +779,23 @@ __global__ void __launch_bounds__(64) band_solve_kernel(FGeom g, const cx<F>* __
     fwd_group(c0 + GF, fb);
   }
   __syncthreads();   // the back substitution reads rows other lanes stored
-  // ---- back: U by columns; lanes 0 .. KW-1 hold rows col .. col - KW + 1
-  const bool umul = lane < KW;
-  const bool bent = lane >= KW && lane < KW + GB;
-  const long long uzero = (long long)N * KW;
+  // ---- back: U by columns; lanes 0 .. KU-1 hold rows col .. col - KU + 1
+  const bool umul = lane < KU;
+  const bool bent = lane >= KU && lane < KU + GB;
+  const long long uzero = (long long)N * KU;
   cx<R> r = ldv(umul && N - 1 - lane >= 0, (long long)N - 1 - lane);
   struct BwdSet {
     cx<F> u[GB];
     cx<R> ent;
   };
+  const unsigned umoff = (unsigned)lane * (unsigned)sizeof(cx<F>);
   auto load_bwd = [&](int c0, BwdSet& b) {
 #pragma unroll
     for (int s = 0; s < GB; ++s) {
       const int col = max(c0 - s, 0);   // steps past the start run on row 0's column
-      b.u[s] = Ut[umul ? (long long)col * KW + lane : uzero];
+      const long long cb = (long long)col * KU;
+      const unsigned off = umul ? umoff : (unsigned)((uzero - cb) * (long long)sizeof(cx<F>));
+      b.u[s] = *reinterpret_cast<const cx<F>*>(reinterpret_cast<const char*>(Ut + cb) + off);
     }
     b.ent = vec[max(c0 - lane, 0)];
   };
@@ -729,12 +803,9 @@ __global__ void __launch_bounds__(64) band_solve_kernel(FGeom g, const cx<F>* __
     if (bent) r = b.ent;
 #pragma unroll
     for (int s = 0; s < GB; ++s) {
-      const R ur = (R)b.u[s].re, ui = (R)b.u[s].im;
-      const cx<R> t{r.re * ur - r.im * ui, r.re * ui + r.im * ur};   // lane 0: r / U(col, col)
-      const cx<R> zc = rdlane(t, 0);
-      r.re = lane == 0 ? t.re : r.re - (ur * zc.re - ui * zc.im);
-      r.im = lane == 0 ? t.im : r.im - (ur * zc.im + ui * zc.re);
-      r = rol1(r);
+      // lane d >= 1: r_d - (U(col-d, col) / U(col, col)) r_0; lane 0:
+      // r_0 - (1 - 1/U(col, col)) r_0 = r_0 / U(col, col), the unknown
+      r = rol1(cfms(r, (R)b.u[s].re, (R)b.u[s].im, rdlane(r, 0)));
     }
     const int o = lane - (64 - GB);   // lane 64 - GB + s holds row c0 - s
     if (o >= 0 && c0 - o >= 0) vec[c0 - o] = r;
@@ -948,7 +1019,33 @@ int fourier_setup(Ctx* c, const sa_precond_opts* o, int nshift, const double* sh
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return c->hip_fail(e, "sa_precond_setup sync");
   if (hflag) return c->fail(SA_ESINGULAR, "sa_precond_setup: zero pivot in a mode of the mean-flow operator");
-  c->fp_U = Uf;
+  // the common extent of U's columns, then the packed layout the solve reads
+  c->fp_ku = 0;
+  zero_fill(flag, 16, s);
+  const long long nfb = (long long)nshift * g.nmodes;
+  const unsigned ny_grid = (unsigned)std::min<long long>(nfb, 4096);
+  const dim3 gext((unsigned)((g.N * g.KW + 255) / 256), (unsigned)std::min<long long>(nfb, 64));
+  if (o->factor_prec == SA_F64)
+    u_extent_kernel<double><<<gext, 256, 0, s>>>(g, nfb, (const cx<double>*)Uf, flag);
+  else
+    u_extent_kernel<float><<<gext, 256, 0, s>>>(g, nfb, (const cx<float>*)Uf, flag);
+  int hext = 0;
+  e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(&hext, flag, sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return c->hip_fail(e, "sa_precond_setup extent");
+  const int KU = std::min(hext + 1, g.KW);
+  void* Uc = c->buffer("fp_Uc", 2 * fs * nfm * ((size_t)g.N * KU + 1), false);
+  if (!Uc) return c->fail(SA_ENOMEM, "sa_precond_setup: out of device memory");
+  const dim3 gpk((unsigned)((g.N * KU + 1 + 255) / 256), ny_grid);
+  if (o->factor_prec == SA_F64)
+    u_pack_kernel<double><<<gpk, 256, 0, s>>>(g, nfb, KU, (const cx<double>*)Uf, (cx<double>*)Uc);
+  else
+    u_pack_kernel<float><<<gpk, 256, 0, s>>>(g, nfb, KU, (const cx<float>*)Uf, (cx<float>*)Uc);
+  e = hipGetLastError();
+  if (e != hipSuccess) return c->hip_fail(e, "sa_precond_setup pack");
+  c->fp_ku = KU;
+  c->fp_U = Uc;
   c->fp_L = Lf;
   c->fp_piv = pv;
   c->fp_f64 = o->factor_prec == SA_F64;

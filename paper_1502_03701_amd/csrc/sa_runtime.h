@@ -69,7 +69,8 @@ struct Ctx {
   int pc_kind = 0;         // SA_PC_BLOCK_JACOBI or SA_PC_MEAN_FLOW
   // mean-flow preconditioner (fourier_pc.hip): per (shift, mode) banded
   // factors, the apply's spectrum buffers and twiddle tables
-  void* fp_U = nullptr;
+  void* fp_U = nullptr;     // packed U (column length fp_ku)
+  int fp_ku = 0;
   void* fp_L = nullptr;
   int* fp_piv = nullptr;
   bool fp_f64 = false;
