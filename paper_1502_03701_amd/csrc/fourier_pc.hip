@@ -43,7 +43,8 @@ constexpr int NOFF = 2 * REACH + 1;   // offsets -3 .. 3
 constexpr int NCOL = 7;               // y colours of the probes (> 2 REACH)
 constexpr size_t LDS_CAP = 65536;     // dynamic LDS a launch of this file may take
 constexpr int BS_GROUP = 16;          // forward steps per prefetch group of the banded solve
-constexpr int BS_GROUP_BACK = 8;      // back-substitution steps per group
+constexpr int BS_GROUP_BACK = 8;      // back-substitution steps per group (KU + 16 <= 64)
+constexpr int BS_GROUP_BACK_WIDE = 16;   // the same when the packed U leaves room: KU + 32 <= 64
 constexpr int FFT_THREADS = 512;      // threads per FFT workgroup (8 waves: LDS-bound occupancy)
 
 struct FGeom {
@@ -705,12 +706,12 @@ __device__ __forceinline__ cx<R> cfms(cx<R> z, R lr, R li, cx<R> b) {
 // group runs (two register sets used in turn) and placed above the window
 // at the group's start (window + entering + finished rows fit in 64 lanes).
 // System sys uses the factors of shift shift0 + sys * shift_step.
-template <typename F, typename R>
+template <typename F, typename R, int GB>
 __global__ void __launch_bounds__(64) band_solve_kernel(FGeom g, const cx<F>* __restrict__ Lo,
                                                         const cx<F>* __restrict__ Uo, const int* __restrict__ pivo,
                                                         int shift0, int shift_step, cx<R>* __restrict__ spec,
                                                         const int* __restrict__ active, long long sA) {
-  constexpr int GF = BS_GROUP, GB = BS_GROUP_BACK;
+  constexpr int GF = BS_GROUP;
   const int m = blockIdx.x, sys = blockIdx.y;
   if (active && !active[sys * sA]) return;
   const int lane = threadIdx.x;
@@ -896,12 +897,26 @@ hipError_t fourier_apply(Ctx* c, int ishift, int nrhs, const R* r, R* z, const i
     fft_z<R><<<gz, FFT_THREADS, zlds, s>>>(g, pz, ub, ubm, A, tz, 0, B, active, sA);
     spec = B;
   }
-  if (c->fp_f64)
-    band_solve_kernel<double, R><<<dim3((unsigned)g.nmodes, (unsigned)nrhs), 64, 0, s>>>(
-        g, (const cx<double>*)c->fp_L, (const cx<double>*)c->fp_U, c->fp_piv, ishift, shift_step, spec, active, sA);
+  // longer back-substitution groups (more factor bytes in flight per
+  // wavefront) when the packed U leaves the lanes for them
+  const bool wide = g.KU + 2 * BS_GROUP_BACK_WIDE <= 64;
+  const dim3 gb((unsigned)g.nmodes, (unsigned)nrhs);
+  const cx<double>* L64 = (const cx<double>*)c->fp_L;
+  const cx<double>* U64 = (const cx<double>*)c->fp_U;
+  const cx<float>* L32 = (const cx<float>*)c->fp_L;
+  const cx<float>* U32 = (const cx<float>*)c->fp_U;
+  if (c->fp_f64 && wide)
+    band_solve_kernel<double, R, BS_GROUP_BACK_WIDE><<<gb, 64, 0, s>>>(g, L64, U64, c->fp_piv, ishift, shift_step, spec,
+                                                                       active, sA);
+  else if (c->fp_f64)
+    band_solve_kernel<double, R, BS_GROUP_BACK><<<gb, 64, 0, s>>>(g, L64, U64, c->fp_piv, ishift, shift_step, spec,
+                                                                  active, sA);
+  else if (wide)
+    band_solve_kernel<float, R, BS_GROUP_BACK_WIDE><<<gb, 64, 0, s>>>(g, L32, U32, c->fp_piv, ishift, shift_step, spec,
+                                                                      active, sA);
   else
-    band_solve_kernel<float, R><<<dim3((unsigned)g.nmodes, (unsigned)nrhs), 64, 0, s>>>(
-        g, (const cx<float>*)c->fp_L, (const cx<float>*)c->fp_U, c->fp_piv, ishift, shift_step, spec, active, sA);
+    band_solve_kernel<float, R, BS_GROUP_BACK><<<gb, 64, 0, s>>>(g, L32, U32, c->fp_piv, ishift, shift_step, spec,
+                                                                 active, sA);
   cx<R>* xin = spec;
   if (g.nd == 3) {
     fft_z<R><<<gz, FFT_THREADS, zlds, s>>>(g, pz, ub, ubm, B, tz, 1, A, active, sA);
