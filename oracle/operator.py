@@ -34,6 +34,13 @@ equations).  Readings taken where the printed system is incomplete:
       Phi = mu [2 s_ij s_ij - 2/3 s_kk^2]             (= tau_ij s_ij)
 * Wall rows (y = +-Ly/2) carry zero perturbation: the operator is P J P with
   P zeroing the wall rows.
+* Grid stretching in y (Section "Model problem": points clustered where the
+  velocity gradients are largest), prob.stretch = beta > 0: the rows sit at
+  y(eta) = (Ly/2) sinh(beta eta)/sinh(beta) of a uniform eta grid on [-1, 1],
+  the stencils above act along eta, and the chain rule with the analytic
+  metric gives D_y f = D_eta f / y' and
+  D_yy f = D_etaeta f / y'^2 - (y''/y'^2) D_y f
+  (D_y the scheme's first derivative, explicit or compact).
 
 Everything is written so that it is complex-analytic (no abs, no branches on
 values), which lets ``jv_cstep`` obtain the exact derivative of the discrete
@@ -68,18 +75,39 @@ class Constants:
 
 def spacings(prob):
     """Grid spacings (dx, dy, dz): periodic axes x_i = i L / N, wall axis with
-    N points including both walls."""
+    N points including both walls; with y stretching, dy is the spacing of
+    the computational coordinate eta in [-1, 1]."""
     out = []
     for a in range(3):
         n = prob.n[a]
         L = prob.length[a]
         if a >= prob.ndim:
             out.append(1.0)
+        elif a == 1 and stretched(prob):
+            out.append(2.0 / (n - 1))
         elif prob.bc[a] == BC_WALL:
             out.append(L / (n - 1))
         else:
             out.append(L / n)
     return tuple(out)
+
+
+def stretched(prob):
+    return float(getattr(prob, "stretch", 0.0)) > 0.0
+
+
+def y_metrics(prob):
+    """(1/y'(eta_j), -y''(eta_j)/y'(eta_j)^2) of the mapping
+    y = (Ly/2) sinh(beta eta)/sinh(beta), as (Ny, 1) columns."""
+    beta = float(prob.stretch)
+    ny = prob.n[1]
+    if prob.bc[1] != BC_WALL:
+        raise ValueError("grid stretching needs walls in y")
+    eta = -1.0 + np.arange(ny) * (2.0 / (ny - 1))
+    half = 0.5 * prob.length[1] / math.sinh(beta)
+    yp = half * beta * np.cosh(beta * eta)
+    ypp = half * beta * beta * np.sinh(beta * eta)
+    return (1.0 / yp)[:, None], (-ypp / (yp * yp))[:, None]
 
 
 # ---------------------------------------------------------------------------
@@ -199,6 +227,29 @@ def d2(f, a, h, bc):
 # ---------------------------------------------------------------------------
 # Thermodynamics (ideal gas, entropy zero at the reference state).
 # ---------------------------------------------------------------------------
+def deriv(prob, f, a):
+    """First derivative along physical axis a of the problem's discrete
+    operator: the scheme's stencil along the grid index, over the spacing,
+    and with y stretching divided by y'(eta)."""
+    h = spacings(prob)[a]
+    bc = prob.bc[a]
+    first = d1_compact if getattr(prob, "scheme", 0) == 1 else d1
+    d = first(f, a, h, bc)
+    if a == 1 and stretched(prob):
+        d = d * y_metrics(prob)[0]
+    return d
+
+
+def deriv2(prob, f, a):
+    """Second derivative along physical axis a: the explicit stencil, and
+    with y stretching D_etaeta f / y'^2 - (y''/y'^2) D_y f."""
+    d = d2(f, a, spacings(prob)[a], prob.bc[a])
+    if a == 1 and stretched(prob):
+        iyp, mq = y_metrics(prob)
+        d = d * (iyp * iyp) + mq * deriv(prob, f, 1)
+    return d
+
+
 def density(c, p, s):
     """rho(p, s) = (p/p_ref)^(1/gamma) exp(-s/c_p)."""
     return (p / c.p_ref) ** (1.0 / c.gamma) * np.exp(-s / c.cp)
@@ -238,8 +289,6 @@ def rhs(prob, q):
     leading axes are a batch.  Works for real and complex q."""
     c = Constants(prob)
     nd = prob.ndim
-    h = spacings(prob)
-    bc = prob.bc
     vax = -(nd + 1)
     q = np.asarray(q)
     p = np.take(q, 0, axis=vax)
@@ -253,9 +302,8 @@ def rhs(prob, q):
     lam = c.cp * mu / c.pr
     dlam = c.cp * dmu / c.pr
 
-    first = d1_compact if getattr(prob, "scheme", 0) == 1 else d1
-    D = lambda f, a: first(f, a, h[a], bc[a])
-    D2 = lambda f, a: d2(f, a, h[a], bc[a])
+    D = lambda f, a: deriv(prob, f, a)      # noqa: E731
+    D2 = lambda f, a: deriv2(prob, f, a)    # noqa: E731
 
     Dp = [D(p, a) for a in range(nd)]
     Ds = [D(s, a) for a in range(nd)]

@@ -51,6 +51,7 @@ class Problem:
     sutherland: float = SUTHERLAND
     bc: Tuple[int, int, int] = (BC_PERIODIC, BC_WALL, BC_PERIODIC)
     scheme: int = SCHEME_EXPLICIT
+    stretch: float = 0.0            # y-grid stretching beta (0: uniform; walls in y only)
 
     @property
     def nv(self) -> int:
@@ -78,19 +79,19 @@ LY_MIXING = 30.0                    # y in [-15, 15]
 
 def mixing_layer_2d(nx: int, ny: int, mach: float, re: float,
                     lx: float = LX_MIXING, ly: float = LY_MIXING,
-                    bc_y: int = BC_WALL, scheme: int = SCHEME_EXPLICIT) -> Problem:
+                    bc_y: int = BC_WALL, scheme: int = SCHEME_EXPLICIT, stretch: float = 0.0) -> Problem:
     return Problem(ndim=2, n=(nx, ny, 1), length=(lx, ly, 1.0), mach=mach, re=re,
-                   bc=(BC_PERIODIC, bc_y, BC_PERIODIC), scheme=scheme)
+                   bc=(BC_PERIODIC, bc_y, BC_PERIODIC), scheme=scheme, stretch=stretch)
 
 
 def mixing_layer_3d(nx: int, ny: int, nz: int, mach: float, re: float,
                     lx: float = LX_MIXING, ly: float = LY_MIXING,
                     lz: float | None = None, bc_y: int = BC_WALL,
-                    scheme: int = SCHEME_EXPLICIT) -> Problem:
+                    scheme: int = SCHEME_EXPLICIT, stretch: float = 0.0) -> Problem:
     if lz is None:
         lz = lx / 2.0
     return Problem(ndim=3, n=(nx, ny, nz), length=(lx, ly, lz), mach=mach, re=re,
-                   bc=(BC_PERIODIC, bc_y, BC_PERIODIC), scheme=scheme)
+                   bc=(BC_PERIODIC, bc_y, BC_PERIODIC), scheme=scheme, stretch=stretch)
 
 
 # ---------------------------------------------------------------------------
@@ -162,9 +163,15 @@ def config4_reduced(seed: int = 4, count: int = 8, sides=(24, 32, 40, 48)) -> Li
 # Grids and base flows.
 # ---------------------------------------------------------------------------
 def grid_y(prob: Problem) -> np.ndarray:
-    """y coordinates: Ny points including both walls, uniform."""
+    """y coordinates: Ny points including both walls; uniform, or with
+    stretch = beta > 0 the points y = (Ly/2) sinh(beta eta) / sinh(beta) of a
+    uniform eta grid on [-1, 1] (clustered around the layer's centre y = 0,
+    as the paper's grid is around the largest velocity gradients)."""
     ny = prob.n[1]
     ly = prob.length[1]
+    if prob.stretch > 0.0:
+        eta = -1.0 + np.arange(ny) * (2.0 / (ny - 1))
+        return 0.5 * ly * np.sinh(prob.stretch * eta) / np.sinh(prob.stretch)
     return -0.5 * ly + np.arange(ny) * (ly / (ny - 1))
 
 
