@@ -82,6 +82,16 @@ typedef struct {
                           context workspace of (ndim + 3)(ndim + 1) + 2 ndim
                           doubles per grid point; its kernels are not
                           autotuned (sa_get_jv_variant reports -1). */
+  double stretch;      /* y-grid stretching beta >= 0 (Section "Model
+                          problem": rows clustered where the velocity
+                          gradients are largest).  0 (the zero-initialised
+                          default): uniform rows.  beta > 0 needs walls in
+                          y: the rows sit at y = (Ly/2) sinh(beta eta) /
+                          sinh(beta), eta uniform on [-1, 1], and y
+                          derivatives take the analytic metric (D_y =
+                          D_eta / y', D_yy = D_etaeta / y'^2 - (y''/y'^2) D_y,
+                          D_y the scheme's first derivative).  The
+                          uniform-state kernels are not used then. */
 } sa_problem;
 
 typedef struct {

@@ -41,7 +41,7 @@ class Problem(C.Structure):
     _fields_ = [("ndim", C.c_int), ("n", C.c_int * 3), ("len", C.c_double * 3),
                 ("bc_y", C.c_int), ("mach", C.c_double), ("re", C.c_double),
                 ("pr", C.c_double), ("gamma", C.c_double), ("sutherland", C.c_double),
-                ("scheme", C.c_int)]
+                ("scheme", C.c_int), ("stretch", C.c_double)]
 
 
 class GmresOpts(C.Structure):
@@ -158,6 +158,7 @@ def make_problem(prob) -> Problem:
     p.mach, p.re, p.pr = prob.mach, prob.re, prob.pr
     p.gamma, p.sutherland = prob.gamma, prob.sutherland
     p.scheme = getattr(prob, "scheme", 0)
+    p.stretch = float(getattr(prob, "stretch", 0.0))
     return p
 
 

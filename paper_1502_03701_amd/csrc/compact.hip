@@ -56,11 +56,14 @@ CAxis axis_of(const OpParams& p, int a) {
 }
 
 // compact derivative along one axis of nf fields: dst_f = D src_f, field f
-// at src + f fs (dst + f fd); fields of one system
+// at src + f fs (dst + f fd); fields of one system.  rs (stretched rows,
+// else null): the solution is scaled by rs[i] (the line's metric) after the
+// solve, with ih = 1
 template <typename R>
-__global__ void __launch_bounds__(256) cd1_kernel(CAxis ax, const R* __restrict__ tab, R ih, const R* __restrict__ src,
-                                                  long long fs, R* __restrict__ dst, long long fd, int nf,
-                                                  const int* __restrict__ active, long long sA, int sys) {
+__global__ void __launch_bounds__(256) cd1_kernel(CAxis ax, const R* __restrict__ tab, R ih, const R* __restrict__ rs,
+                                                  const R* __restrict__ src, long long fs, R* __restrict__ dst,
+                                                  long long fd, int nf, const int* __restrict__ active, long long sA,
+                                                  int sys) {
   if (active && !active[sys * sA]) return;
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (long long)ax.lines * nf) return;
@@ -104,9 +107,10 @@ __global__ void __launch_bounds__(256) cd1_kernel(CAxis ax, const R* __restrict_
   }
   // back substitution
   R x = o[(long long)(n - 1) * st];
+  if (rs) o[(long long)(n - 1) * st] = x * rs[n - 1];
   for (int i = n - 2; i >= 0; --i) {
     x = o[(long long)i * st] - tc[i] * x;
-    o[(long long)i * st] = x;
+    o[(long long)i * st] = rs ? x * rs[i] : x;
   }
   if (ax.periodic) {   // Sherman-Morrison correction of the cyclic system
     const R* tq = tc + n;
@@ -186,7 +190,8 @@ __device__ __forceinline__ R d2_at(const OpParams& op, const R* __restrict__ F, 
   R acc = A.c0 * at(c);
 #pragma unroll
   for (int m = 1; m <= 3; ++m) acc += A.c2[m - 1] * (at(c + m) + at(c - m));
-  const R ih = R(a == 0 ? op.ihx : (a == 1 ? op.ihy : op.ihz));
+  if (a == 1) return acc * ymet<R>(op)[op.ny + j];   // m2 of the row; fill_pt adds m4 D_y f
+  const R ih = R(a == 0 ? op.ihx : op.ihz);
   return acc * ih * ih;
 }
 
@@ -203,13 +208,15 @@ __device__ __forceinline__ void fill_pt(const OpParams& op, const R* __restrict_
 #pragma unroll
     for (int a = 0; a < ND; ++a) P.D[f][a] = D[(long long)(a * NF + f) * np + id];
   }
+  const R m4 = ymet<R>(op)[2 * op.ny + j];   // -y''/y'^2 of the row (0 on uniform rows)
 #pragma unroll
   for (int c = 0; c < ND; ++c) {
     const R* F = W + (long long)(1 + c) * np;
     R L = R(0), own = R(0);
 #pragma unroll
     for (int a = 0; a < ND; ++a) {
-      const R d2 = d2_at<R>(op, F, a, i, j, k);
+      R d2 = d2_at<R>(op, F, a, i, j, k);
+      if (a == 1) d2 += m4 * P.D[1 + c][1];
       L += d2;
       if (a == c) own = d2;
     }
@@ -219,7 +226,7 @@ __device__ __forceinline__ void fill_pt(const OpParams& op, const R* __restrict_
   R LT = R(0);
 #pragma unroll
   for (int a = 0; a < ND; ++a) LT += d2_at<R>(op, W + (long long)(ND + 2) * np, a, i, j, k);
-  P.LT = LT;
+  P.LT = LT + m4 * P.D[ND + 2][1];
 }
 
 // y = (J - shift I) x at every point of system sys
@@ -296,6 +303,12 @@ __global__ void cbase_kernel(OpParams op, const double* __restrict__ W, const do
 }
 
 template <typename R>
+const R* ymet_host(const OpParams& p) {
+  if constexpr (sizeof(R) == 8) return p.ym64;
+  else return p.ym32;
+}
+
+template <typename R>
 const R* ctab(const OpParams& p);
 template <>
 const double* ctab<double>(const OpParams& p) {
@@ -316,16 +329,21 @@ hipError_t derivatives(const OpParams& p, const R* W, R* D, R* M, R* GM, const i
   constexpr int NF = ND + 3;
   const long long np = p.npts;
   const R* tab = ctab<R>(p);
-  const R ih[3] = {R(p.ihx), R(p.ihy), R(p.ihz)};
+  // stretched rows: the y solve runs with ih = 1 and scales its solution by
+  // the row metric m1 (a row-dependent factor does not commute with A^-1)
+  const bool st = p.stretch > 0.0;
+  const R ih[3] = {R(p.ihx), st ? R(1) : R(p.ihy), R(p.ihz)};
+  const R* rs[3] = {nullptr, st ? ymet_host<R>(p) : nullptr, nullptr};
   for (int a = 0; a < ND; ++a) {
     const CAxis ax = axis_of(p, a);
-    cd1_kernel<R><<<blocks((long long)ax.lines * NF, 256), 256, 0, s>>>(ax, tab, ih[a], W, np, D + (long long)a * NF * np,
-                                                                          np, NF, active, sA, sys);
+    cd1_kernel<R><<<blocks((long long)ax.lines * NF, 256), 256, 0, s>>>(ax, tab, ih[a], rs[a], W, np,
+                                                                          D + (long long)a * NF * np, np, NF, active,
+                                                                          sA, sys);
   }
   cmix_kernel<R, ND><<<blocks(np, 256), 256, 0, s>>>(p, D, M, active, sA, sys);
   for (int a = 0; a < ND; ++a) {
     const CAxis ax = axis_of(p, a);
-    cd1_kernel<R><<<blocks(ax.lines, 256), 256, 0, s>>>(ax, tab, ih[a], M + (long long)a * np, np,
+    cd1_kernel<R><<<blocks(ax.lines, 256), 256, 0, s>>>(ax, tab, ih[a], rs[a], M + (long long)a * np, np,
                                                         GM + (long long)a * np, np, 1, active, sA, sys);
   }
   return hipGetLastError();

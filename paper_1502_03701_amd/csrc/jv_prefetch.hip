@@ -91,7 +91,11 @@ __global__ void __launch_bounds__(NT) jv_prefetch_kernel(OpParams op, const R* _
   const int npts = (int)op.npts;
   const bool inside = FULL || (i < nx && j < ny);
   const bool wallbc = op.bcy == 1;
-  const R ihx = R(op.ihx), ihy = R(op.ihy), ihz = R(op.ihz);
+  const R ihx = R(op.ihx), ihz = R(op.ihz);
+  // y metric of the own row (uniform or stretched rows)
+  const R* ymt = ymet<R>(op);
+  const int jm = j < ny ? j : ny - 1;
+  const R my1 = ymt[jm], my2 = ymt[ny + jm], my4 = ymt[2 * ny + jm];
   const Axis<R> ax = axis_coefs<R>(6);
   const Axis<R> ayc = axis_coefs<R>(wall_row_order(j < ny ? j : ny - 1, ny, op.bcy));
   const Axis<R> az = axis_coefs<R>(6);
@@ -242,7 +246,7 @@ __global__ void __launch_bounds__(NT) jv_prefetch_kernel(OpParams op, const R* _
         R dyv = R(0);
 #pragma unroll
         for (int m = 1; m <= 3; ++m) dyv += ayd.c1[m - 1] * (sP[2][dr + 3 + m][dc] - sP[2][dr + 3 - m][dc]);
-        sX[0][dr][dc] = dyv * ihy + dzwv;
+        sX[0][dr][dc] = dyv * ymt[gj_d] + dzwv;
         sX[1][dr][dc] = dzbv;
       } else {
         R dxu = R(0);
@@ -275,11 +279,11 @@ __global__ void __launch_bounds__(NT) jv_prefetch_kernel(OpParams op, const R* _
       }
       P.q[f] = c0;
       P.D[f][0] = a1x * ihx;
-      P.D[f][1] = a1y * ihy;
+      P.D[f][1] = a1y * my1;
       if (ND == 3) P.D[f][2] = a1z * ihz;
       if ((f >= 1 && f <= ND) || f == ND + 2) {
         const R d2x = (ax.c0 * c0 + a2x) * (ihx * ihx);
-        const R d2y = (ayc.c0 * c0 + a2y) * (ihy * ihy);
+        const R d2y = (ayc.c0 * c0 + a2y) * my2 + P.D[f][1] * my4;
         const R d2z = ND == 3 ? (az.c0 * c0 + a2z) * (ihz * ihz) : R(0);
         const R L = d2x + d2y + d2z;
         if (f == ND + 2) {
@@ -309,8 +313,8 @@ __global__ void __launch_bounds__(NT) jv_prefetch_kernel(OpParams op, const R* _
         }
       }
       P.G[0] += gxs * ihx;
-      P.G[1] += gys * ihy;
-      if (ND == 3) P.G[2] += gz1 * ihx + gz2 * ihy;
+      P.G[1] += gys * my1;
+      if (ND == 3) P.G[2] += gz1 * ihx + gz2 * my1;
     }
     // the queue takes plane k+3; then the next plane's loads fly during the algebra
     if (ND == 3) {

@@ -77,7 +77,11 @@ __global__ void __launch_bounds__(NT) jv_stage_kernel(OpParams op, const R* __re
   const long long npts = op.npts;
   const bool inside = i < nx && j < ny;
   const bool wallbc = op.bcy == 1;
-  const R ihx = R(op.ihx), ihy = R(op.ihy), ihz = R(op.ihz);
+  const R ihx = R(op.ihx), ihz = R(op.ihz);
+  // y metric of the own row (uniform or stretched rows)
+  const R* ymt = ymet<R>(op);
+  const int jm = j < ny ? j : ny - 1;
+  const R my1 = ymt[jm], my2 = ymt[ny + jm], my4 = ymt[2 * ny + jm];
   const Axis<R> ax = axis_coefs<R>(6);
   const Axis<R> ayc = axis_coefs<R>(wall_row_order(j < ny ? j : ny - 1, ny, op.bcy));
   const Axis<R> az = axis_coefs<R>(6);
@@ -166,7 +170,7 @@ __global__ void __launch_bounds__(NT) jv_stage_kernel(OpParams op, const R* __re
             dzw = dzcol(3, colp, k, wall);
             dzu = dzcol(1, colp, k, wall);
           }
-          sX[0][r][ii] = dyv * ihy + dzw;
+          sX[0][r][ii] = dyv * ymt[gj] + dzw;
           sX[1][r][ii] = dzu;
         } else {
           const int t2 = t - NXH;
@@ -211,11 +215,11 @@ __global__ void __launch_bounds__(NT) jv_stage_kernel(OpParams op, const R* __re
       }
       P.q[f] = c0;
       P.D[f][0] = a1x * ihx;
-      P.D[f][1] = a1y * ihy;
+      P.D[f][1] = a1y * my1;
       if (ND == 3) P.D[f][2] = a1z * ihz;
       if ((f >= 1 && f <= ND) || f == ND + 2) {
         const R d2x = (ax.c0 * c0 + a2x) * (ihx * ihx);
-        const R d2y = (ayc.c0 * c0 + a2y) * (ihy * ihy);
+        const R d2y = (ayc.c0 * c0 + a2y) * my2 + P.D[f][1] * my4;
         const R d2z = ND == 3 ? (az.c0 * c0 + a2z) * (ihz * ihz) : R(0);
         const R L = d2x + d2y + d2z;
         if (f == ND + 2) {
@@ -245,8 +249,8 @@ __global__ void __launch_bounds__(NT) jv_stage_kernel(OpParams op, const R* __re
         }
       }
       P.G[0] += gx * ihx;
-      P.G[1] += gy * ihy;
-      if (ND == 3) P.G[2] += gz1 * ihx + gz2 * ihy;
+      P.G[1] += gy * my1;
+      if (ND == 3) P.G[2] += gz1 * ihx + gz2 * my1;
     }
     if (inside) {
       const int id = k * plane + j * nx + i;

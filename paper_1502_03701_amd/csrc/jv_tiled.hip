@@ -59,7 +59,11 @@ __global__ void __launch_bounds__(NT) base_data_kernel(OpParams op, const R* __r
   const int nx = op.nx, ny = op.ny, nz = op.nz;
   const long long npts = op.npts;
   const bool inside = i < nx && j < ny;
-  const R ihx = R(op.ihx), ihy = R(op.ihy), ihz = R(op.ihz);
+  const R ihx = R(op.ihx), ihz = R(op.ihz);
+  // y metric of the own row (uniform or stretched rows)
+  const R* ymt = ymet<R>(op);
+  const int jm = j < ny ? j : ny - 1;
+  const R my1 = ymt[jm], my2 = ymt[ny + jm], my4 = ymt[2 * ny + jm];
 
   const Axis<R> ax = axis_coefs<R>(6);
   const Axis<R> ayc = axis_coefs<R>(wall_row_order(j < ny ? j : ny - 1, ny, op.bcy));
@@ -151,7 +155,7 @@ __global__ void __launch_bounds__(NT) base_data_kernel(OpParams op, const R* __r
 #pragma unroll
             for (int m = 1; m <= 3; ++m)
               dyv += ay2.c1[m - 1] * (sP[F0 + 2][tj2 + 3 + m][ii] - sP[F0 + 2][tj2 + 3 - m][ii]);
-            dyv *= ihy;
+            dyv *= ymt[gj];
             const R dzw = dz1(is_pert(s), 3, gi, gj, k, wall);
             const R dzu = dz1(is_pert(s), 1, gi, gj, k, wall);
             sX[s][0][tj2][ii] = dyv + dzw;
@@ -195,7 +199,7 @@ __global__ void __launch_bounds__(NT) base_data_kernel(OpParams op, const R* __r
 #pragma unroll
             for (int m = 1; m <= 3; ++m)
               dyv += ay2.c1[m - 1] * (sP[F0 + 2][tj2 + 3 + m][ii] - sP[F0 + 2][tj2 + 3 - m][ii]);
-            sX[s][0][tj2][ii] = dyv * ihy;
+            sX[s][0][tj2][ii] = dyv * ymt[gj];
           }
         } else {
           const int t2 = t - nxh;
@@ -234,12 +238,12 @@ __global__ void __launch_bounds__(NT) base_data_kernel(OpParams op, const R* __r
         }
         P[s].q[f] = c0;
         P[s].D[f][0] = a1x * ihx;
-        P[s].D[f][1] = a1y * ihy;
+        P[s].D[f][1] = a1y * my1;
         if (ND == 3) P[s].D[f][ND - 1] = dz[s][f];
         // second derivatives: velocity components and T
         if ((f >= 1 && f <= ND) || f == ND + 2) {
           const R d2x = (ax.c0 * c0 + a2x) * (ihx * ihx);
-          const R d2y = (ayc.c0 * c0 + a2y) * (ihy * ihy);
+          const R d2y = (ayc.c0 * c0 + a2y) * my2 + P[s].D[f][1] * my4;
           R d2zz = R(0);
           if (ND == 3) d2zz = (az.c0 * c0 + d2z[s][f == ND + 2 ? ND : f - 1]) * (ihz * ihz);
           const R L = d2x + d2y + d2zz;
@@ -283,8 +287,8 @@ __global__ void __launch_bounds__(NT) base_data_kernel(OpParams op, const R* __r
         }
       }
       P[s].G[0] += gx * ihx;
-      P[s].G[1] += gy * ihy;
-      if (ND == 3) P[s].G[2] += gz1 * ihx + gz2 * ihy;
+      P[s].G[1] += gy * my1;
+      if (ND == 3) P[s].G[2] += gz1 * ihx + gz2 * my1;
     }
     // 5. the base data of the point
     const long long id = ((long long)k * ny + j) * nx + i;

@@ -269,6 +269,10 @@ int sa_base_set(sa_ctx* c, const sa_problem* pb, const double* q0_dev) {
     return c->fail(SA_EINVAL, "sa_base_set: mach, gamma, pr, sutherland must be positive (gamma > 1)");
   for (int a = 0; a < pb->ndim; ++a)
     if (!(pb->len[a] > 0)) return c->fail(SA_EINVAL, "sa_base_set: lengths must be positive");
+  if (!(pb->stretch >= 0.0 && pb->stretch <= 20.0))
+    return c->fail(SA_EINVAL, "sa_base_set: stretch must be in [0, 20]");
+  if (pb->stretch > 0.0 && pb->bc_y != SA_BC_WALL)
+    return c->fail(SA_EINVAL, "sa_base_set: grid stretching needs walls in y");
   OpParams& op = c->op;
   op.ndim = pb->ndim;
   op.nx = pb->n[0];
@@ -287,6 +291,7 @@ int sa_base_set(sa_ctx* c, const sa_problem* pb, const double* q0_dev) {
   op.suth = pb->sutherland;
   op.pr = pb->pr;
   op.scheme = pb->scheme;
+  op.stretch = pb->stretch;
   op.cwork = nullptr;
   op.ctab64 = nullptr;
   op.ctab32 = nullptr;
@@ -318,6 +323,35 @@ int sa_base_set(sa_ctx* c, const sa_problem* pb, const double* q0_dev) {
   e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return c->hip_fail(e, "sa_base_set sync");
   if (hflag) return c->fail(SA_ENONFINITE, "sa_base_set: q0 has NaN/Inf or non-positive pressure");
+  {
+    // per-row y metric [m1 | m2 | m4] (see OpParams), double and float
+    double* y64 = (double*)c->buffer("ymet64", sizeof(double) * 3 * op.ny, false);
+    float* y32 = (float*)c->buffer("ymet32", sizeof(float) * 3 * op.ny, false);
+    if (!y64 || !y32) return c->fail(SA_ENOMEM, "sa_base_set: out of device memory");
+    std::vector<double> h(3 * (size_t)op.ny);
+    const int ny = op.ny;
+    for (int j = 0; j < ny; ++j) {
+      if (op.stretch > 0.0) {
+        // y(eta) = (Ly/2) sinh(beta eta)/sinh(beta), eta_j = -1 + 2 j/(ny-1)
+        const double b = op.stretch, eta = -1.0 + 2.0 * j / (ny - 1), heta = 2.0 / (ny - 1);
+        const double half = 0.5 * pb->len[1] / std::sinh(b);
+        const double yp = half * b * std::cosh(b * eta), ypp = half * b * b * std::sinh(b * eta);
+        h[j] = 1.0 / (heta * yp);
+        h[ny + j] = h[j] * h[j];
+        h[2 * ny + j] = -ypp / (yp * yp);
+      } else {
+        h[j] = op.ihy;
+        h[ny + j] = op.ihy * op.ihy;
+        h[2 * ny + j] = 0.0;
+      }
+    }
+    std::vector<float> h32(h.begin(), h.end());
+    e = hipMemcpy(y64, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(y32, h32.data(), sizeof(float) * h32.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return c->hip_fail(e, "sa_base_set y metric");
+    op.ym64 = y64;
+    op.ym32 = y32;
+  }
   if (op.scheme == SA_SCHEME_COMPACT) {
     // workspace (one system) and Thomas tables of the compact derivatives
     const size_t nt = compact_table_elems(op);
@@ -343,7 +377,7 @@ int sa_base_set(sa_ctx* c, const sa_problem* pb, const double* q0_dev) {
   if (e != hipSuccess) return c->hip_fail(e, "sa_base_set base data sync");
   // the uniform-state and autotuned kernels are explicit-difference kernels
   if (op.scheme == SA_SCHEME_EXPLICIT) {
-    int rc = setup_iso(c);
+    int rc = op.stretch > 0.0 ? SA_OK : setup_iso(c);   // the uniform-state kernels take uniform rows
     if (rc != SA_OK) return rc;
     rc = autotune_jv(c);
     if (rc != SA_OK) return rc;

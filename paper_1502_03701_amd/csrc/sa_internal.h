@@ -33,7 +33,24 @@ struct OpParams {
   void* cwork;
   const double* ctab64;
   const float* ctab32;
+  // y metric per row j (device, [3][ny]): m1 = 1/h_y, m2 = 1/h_y^2 and
+  // m4 = 0 on a uniform grid; with the stretched rows y(eta) the scales
+  // 1/(h_eta y'), 1/(h_eta y')^2 and -y''/y'^2, so that D_y f = m1 d1 f and
+  // D_yy f = m2 d2 f + m4 D_y f (d1, d2: the stencil sums along the rows)
+  const double* ym64;
+  const float* ym32;
+  double stretch;          // beta (0: uniform rows)
 };
+template <typename R>
+__device__ __forceinline__ const R* ymet(const OpParams& op);
+template <>
+__device__ __forceinline__ const double* ymet<double>(const OpParams& op) {
+  return op.ym64;
+}
+template <>
+__device__ __forceinline__ const float* ymet<float>(const OpParams& op) {
+  return op.ym32;
+}
 
 // Base states with uniform p0 and s0 (so uniform T0, rho0, mu0, dT/dp,
 // dT/ds): the operator needs per point only u0_i, D_a u0_i and
