@@ -187,6 +187,9 @@ def main():
                     help="only the achievable HBM bandwidth of plain torch sum / add / copy on 4 GiB")
     ap.add_argument("--c2-cap", type=int, default=30000,
                     help="product budget of each --c2-solve solve (a small cap for profiling)")
+    ap.add_argument("--discretisations", action="store_true",
+                    help="only the operator on 256x128x128 with explicit / compact first derivatives on "
+                         "uniform / stretched rows, FP64 and FP32")
     ap.add_argument("--gmres-only", action="store_true",
                     help="only capped GMRES runs: 512x512 FP64 (1 and 8 shifts), one FP32 cycle of "
                          "8 shifts on the 3D grid (for profiling)")
@@ -202,6 +205,9 @@ def main():
     from paper_1502_03701_amd import Context
 
     dev = torch.device("cuda:0")
+    if args.discretisations:
+        print(json.dumps(discretisations(torch, dev, args.steps, args.warmup)))
+        return
     if args.hbm_probe:
         print(json.dumps(hbm_probe(torch, dev)))
         return
@@ -446,6 +452,32 @@ def extras(torch, dev, ctx3, prob3):
     res.update(eigs_3d(torch, dev, nev=4, ncv=20, max_restarts=40, augment=3, log=log))
     res.update(eigs_3d(torch, dev, side=64, max_restarts=20, augment=3, log=log))
     return res
+
+
+def discretisations(torch, dev, steps, warmup):
+    """The operator y = (J - 0.2 I) x on the 256 x 128 x 128 workload grid
+    (tanh + 1e-3 spanwise noise, M 0.5, Re 1000) with explicit or compact
+    first derivatives, on uniform rows or rows stretched with beta = 3:
+    ms per product and Gpt/s in FP64 and FP32 (HIP events, steps products
+    after warmup)."""
+    import synth
+    from paper_1502_03701_amd import SA_F32, SA_F64, Context
+    out = {}
+    for scheme, sname in ((synth.SCHEME_EXPLICIT, "explicit"), (synth.SCHEME_COMPACT, "compact")):
+        for beta in (0.0, 3.0):
+            p = synth.mixing_layer_3d(256, 128, 128, 0.5, 1000.0, scheme=scheme, stretch=beta)
+            ctx = Context()
+            ctx.base_set(p, torch.from_numpy(synth.base_flow(p, seed=2, w_noise=1e-3).ravel()).to(dev))
+            x = torch.from_numpy(synth.random_vector(p, 2).ravel()).to(dev)
+            rec = {"variant_f64": ctx.jv_variant(SA_F64)[0], "variant_f32": ctx.jv_variant(SA_F32)[0]}
+            for dt, tag in ((torch.float64, "f64"), (torch.float32, "f32")):
+                xx = x.to(dt)
+                y = torch.empty_like(xx)
+                sec = timed(lambda: ctx.op_apply(xx, y, shift=0.2), steps, warmup, torch) / steps
+                rec[tag] = {"ms": sec * 1e3, "gpts": p.npts / sec / 1e9}
+            ctx.close()
+            out["%s_%s" % (sname, "stretched" if beta > 0 else "uniform")] = rec
+    return {"discretisations_256x128x128": out}
 
 
 def eigs_c2(torch, dev, log=None, max_restarts=60):

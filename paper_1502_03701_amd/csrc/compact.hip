@@ -121,7 +121,7 @@ __global__ void __launch_bounds__(256) cd1_kernel(CAxis ax, const R* __restrict_
 
 // W = (p', u', s', T') of system sys with zero wall rows
 template <typename R, int ND>
-__global__ void cstage_kernel(OpParams op, const R* __restrict__ base, const R* __restrict__ x, long long sX,
+__global__ void __launch_bounds__(256) cstage_kernel(OpParams op, const R* __restrict__ base, const R* __restrict__ x, long long sX,
                               R* __restrict__ W, const int* __restrict__ active, long long sA, int sys) {
   if (active && !active[sys * sA]) return;
   const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -145,7 +145,7 @@ __global__ void cstage_kernel(OpParams op, const R* __restrict__ base, const R* 
 // M_x = D_y v + D_z w, M_y = D_x u + D_z w, M_z = D_x u + D_y v (2D: D_y v, D_x u)
 // from D (D[a][f] at D + (a NF + f) np, NF = ND + 3)
 template <typename R, int ND>
-__global__ void cmix_kernel(OpParams op, const R* __restrict__ D, R* __restrict__ M, const int* __restrict__ active,
+__global__ void __launch_bounds__(256) cmix_kernel(OpParams op, const R* __restrict__ D, R* __restrict__ M, const int* __restrict__ active,
                             long long sA, int sys) {
   if (active && !active[sys * sA]) return;
   const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -231,7 +231,7 @@ __device__ __forceinline__ void fill_pt(const OpParams& op, const R* __restrict_
 
 // y = (J - shift I) x at every point of system sys
 template <typename R, int ND>
-__global__ void cpoint_kernel(OpParams op, const R* __restrict__ bdata, const R* __restrict__ W,
+__global__ void __launch_bounds__(256) cpoint_kernel(OpParams op, const R* __restrict__ bdata, const R* __restrict__ W,
                               const R* __restrict__ D, const R* __restrict__ GM, const R* __restrict__ x, R* __restrict__ y,
                               long long sX, long long sY, R shift, const double* __restrict__ shifts,
                               const int* __restrict__ active, long long sA, int sys) {
@@ -280,7 +280,7 @@ __global__ void cpoint_kernel(OpParams op, const R* __restrict__ bdata, const R*
 
 // base data of the compact operator from W = (p0, u0_i, s0, T0)
 template <int ND>
-__global__ void cbase_kernel(OpParams op, const double* __restrict__ W, const double* __restrict__ D,
+__global__ void __launch_bounds__(256) cbase_kernel(OpParams op, const double* __restrict__ W, const double* __restrict__ D,
                              const double* __restrict__ GM, double* __restrict__ bdata) {
   const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long np = op.npts;
