@@ -46,6 +46,13 @@ constexpr int BS_GROUP = 16;          // forward steps per prefetch group of the
 constexpr int BS_GROUP_BACK = 8;      // back-substitution steps per group (KU + 16 <= 64)
 constexpr int BS_GROUP_BACK_WIDE = 16;   // the same when the packed U leaves room: KU + 32 <= 64
 constexpr int FFT_THREADS = 512;      // threads per FFT workgroup (8 waves: LDS-bound occupancy)
+// LDS a workgroup of the x and z FFTs batches its lines in. The x lines are
+// contiguous in memory, so a 32 KB batch (four workgroups per CU to hide LDS
+// latency) still reads whole rows; a z workgroup gathers its ub lines as runs
+// of ub consecutive complex values per plane, and in FP64 the longer runs of
+// a 64 KB batch pay more than the extra occupancy.
+template <typename R> constexpr size_t fft_x_lds() { return 32768; }
+template <typename R> constexpr size_t fft_z_lds() { return sizeof(R) == 8 ? 65536 : 32768; }
 
 struct FGeom {
   int nd, nv, nx, ny, nz;
@@ -852,18 +859,18 @@ size_t fourier_spec_bytes(const Ctx* c, int nrhs, size_t es) {
 }
 
 // line pairs per workgroup of the x transforms (two LDS buffers of P n
-// complex values and the twiddles within LDS_CAP), and sequences per
-// workgroup of the z transforms
+// complex values and the twiddles within the x budget), and sequences per
+// workgroup of the z transforms (within the z budget)
 template <typename R>
 int x_pairs(int n) {
-  const int cap = (int)(LDS_CAP / sizeof(cx<R>));
+  const int cap = (int)(fft_x_lds<R>() / sizeof(cx<R>));
   int P = (cap - n) / (2 * n);
   if (P > XMAX_PAIRS) P = XMAX_PAIRS;
   return P < 1 ? 1 : P;
 }
 template <typename R>
 int z_seqs(int n) {
-  const int cap = (int)(LDS_CAP / sizeof(cx<R>));
+  const int cap = (int)(fft_z_lds<R>() / sizeof(cx<R>));
   int ub = (cap - n) / (2 * n);
   if (ub > 32) ub = 32;
   return ub < 1 ? 1 : ub;
