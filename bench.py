@@ -662,11 +662,12 @@ def sweep_c4(torch, dev, log=None, nev=2, modes=("sequential", "concurrent"), re
     steps, and the rest of a captured GMRES(m) cycle is launches that return
     at once; these small problems are launch-bound, so the inner solver is
     GMRES(4) (the same products and eigenvalues as GMRES(30), 1.6x faster).
-    Run twice: in turn on one stream, and concurrently, 16 problems at a
-    time on one stream each (one host thread per problem; torch hands out
-    at most 32 distinct streams per device).  The timed region covers each
-    problem's preconditioner setup and its eigen solve; p50/p99 are over the
-    library's per-problem wall times."""
+    Run twice: in turn on one stream, and concurrently: every problem on a
+    stream of its own (created here: torch's pool hands out at most 32
+    distinct streams per device), handed to the library largest first, whose
+    16 host threads take the next problem as they finish one.  The timed
+    region covers each problem's preconditioner setup and its eigen solve;
+    p50/p99 are over the library's per-problem wall times."""
     import numpy as np
     import synth
     from paper_1502_03701_amd import SA_F32, SA_MIXED, SA_PC_MEAN_FLOW, Context, arnoldi_eigs
@@ -675,10 +676,12 @@ def sweep_c4(torch, dev, log=None, nev=2, modes=("sequential", "concurrent"), re
               prec=SA_MIXED, inner_tol=1e-4, use_precond=True)
     out = {}
     for mode in modes:
-        conc = 16
-        pool = [torch.cuda.Stream() for _ in range(conc)]
-        streams = ([torch.cuda.current_stream()] * len(items) if mode == "sequential"
-                   else [pool[i % conc] for i in range(len(items))])
+        own = []
+        if mode == "sequential":
+            streams = [torch.cuda.current_stream()] * len(items)
+        else:
+            own = [_hip_stream() for _ in items]
+            streams = [torch.cuda.ExternalStream(h, device=dev) for h in own]
         ctxs, v0s = [], []
         for it, st in zip(items, streams):
             c = Context(stream=st)
@@ -693,11 +696,13 @@ def sweep_c4(torch, dev, log=None, nev=2, modes=("sequential", "concurrent"), re
                 c.precond_setup([0.2], factor_prec=SA_F32, kind=SA_PC_MEAN_FLOW)
                 r += arnoldi_eigs([c], [v], **kw)[1]
         else:
-            r = []
-            for b in range(0, len(items), conc):
-                for c in ctxs[b:b + conc]:
-                    c.precond_setup([0.2], factor_prec=SA_F32, kind=SA_PC_MEAN_FLOW)
-                r += arnoldi_eigs(ctxs[b:b + conc], v0s[b:b + conc], **kw)[1]
+            order = sorted(range(len(items)), key=lambda i: -items[i].problem.ndof)
+            for c in ctxs:
+                c.precond_setup([0.2], factor_prec=SA_F32, kind=SA_PC_MEAN_FLOW)
+            ro = arnoldi_eigs([ctxs[i] for i in order], [v0s[i] for i in order], **kw)[1]
+            r = [None] * len(items)
+            for i, x in zip(order, ro):
+                r[i] = x
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         secs = np.array([x["seconds"] for x in r])
@@ -713,7 +718,37 @@ def sweep_c4(torch, dev, log=None, nev=2, modes=("sequential", "concurrent"), re
             log("sweep c4 %s: %.2f s, %d eigenpairs" % (mode, el, pairs))
         for c in ctxs:
             c.close()
+        for h in own:
+            _hip_stream_destroy(h)
     return out
+
+
+def _hip():
+    """The HIP runtime this process already runs on (torch and libsa share
+    it); opening the library by name could map a second copy."""
+    import ctypes
+    paths = sorted({ln.split()[-1] for ln in open("/proc/self/maps") if "libamdhip64.so" in ln})
+    if len(paths) != 1:
+        raise RuntimeError("expected one mapped HIP runtime, found %s" % paths)
+    lib = ctypes.CDLL(paths[0])
+    lib.hipStreamCreateWithFlags.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_uint]
+    lib.hipStreamDestroy.argtypes = [ctypes.c_void_p]
+    return lib
+
+
+def _hip_stream():
+    """A new non-blocking HIP stream of the default priority (its handle)."""
+    import ctypes
+    h = ctypes.c_void_p()
+    rc = _hip().hipStreamCreateWithFlags(ctypes.byref(h), 1)
+    if rc != 0:
+        raise RuntimeError("hipStreamCreateWithFlags failed: %d" % rc)
+    return h.value
+
+
+def _hip_stream_destroy(h):
+    import ctypes
+    _hip().hipStreamDestroy(ctypes.c_void_p(h))
 
 
 if __name__ == "__main__":
