@@ -35,7 +35,7 @@ void iram_column(IState* st, int j, hipStream_t s);
 // Restart step: Ritz values/vectors of H_m, Ritz estimates, convergence test;
 // if not converged, the exact-shift QR steps, Q, H_k and the coefficients of
 // the k-step update (done = 1 when converged or out of restarts).
-void iram_restart(IState* st, hipStream_t s);
+void iram_restart(IState* st, int m, hipStream_t s);   // m: the Arnoldi dimension given to iram_init
 // After V_k and f_k are formed: H(k, k-1) = ||f_k|| from wn2, inv = 1/||f_k||.
 void iram_set_fk(IState* st, hipStream_t s);
 void iram_init(IState* st, int m, int nev, double tol, double sigma, double mu, int max_restarts,

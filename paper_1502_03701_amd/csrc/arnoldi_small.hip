@@ -13,24 +13,26 @@ namespace {
 
 constexpr double EPS = 2.220446049250313e-16;   // 2^-52
 constexpr int LD = MMAX;
+// Largest m whose four m x m working matrices of the restart (T and Z, then
+// H_m, M, HQ and Q) fit in 64 KB of LDS with leading dimension m; larger
+// Arnoldi dimensions work in the state's global arrays.
+constexpr int RESTART_LDS_M = 44;
 
 __device__ __forceinline__ double cabs2(double r, double i) { return hypot(r, i); }
 
-// complex Schur form T = Z^H H Z of the real m x m matrix in st->Hm.
-// All 64 lanes take part; lane 0 decides, every lane applies rotations to
-// the row/column it owns.  Returns 0 on success.
-__device__ int complex_schur(IState* st, int m) {
+// complex Schur form T = Z^H H Z of the real m x m matrix in st->Hm, into
+// (Tr, Ti) and (Zr, Zi), column-major with leading dimension LDT (LDS or the
+// state's arrays).  All 64 lanes take part; lane 0 decides, every lane
+// applies rotations to the row/column it owns.  Returns 0 on success.
+template <int LDT>
+__device__ int complex_schur(IState* st, int m, double* Tr, double* Ti, double* Zr, double* Zi) {
   const int lane = threadIdx.x;
-  double* Tr = st->Tr;
-  double* Ti = st->Ti;
-  double* Zr = st->Zr;
-  double* Zi = st->Zi;
   for (int j = 0; j < m; ++j) {
     if (lane < m) {
-      Tr[j * LD + lane] = st->Hm[j * LD + lane];
-      Ti[j * LD + lane] = 0.0;
-      Zr[j * LD + lane] = lane == j ? 1.0 : 0.0;
-      Zi[j * LD + lane] = 0.0;
+      Tr[j * LDT + lane] = st->Hm[j * MMAX + lane];
+      Ti[j * LDT + lane] = 0.0;
+      Zr[j * LDT + lane] = lane == j ? 1.0 : 0.0;
+      Zi[j * LDT + lane] = 0.0;
     }
   }
   __shared__ int s_hi, s_l, s_stop, s_iter;
@@ -47,13 +49,13 @@ __device__ int complex_schur(IState* st, int m) {
       const int hi = s_hi;
       int l = hi;
       while (l > 0) {
-        const double sub = cabs2(Tr[(l - 1) * LD + l], Ti[(l - 1) * LD + l]);
-        double d = cabs2(Tr[(l - 1) * LD + l - 1], Ti[(l - 1) * LD + l - 1]) +
-                   cabs2(Tr[l * LD + l], Ti[l * LD + l]);
+        const double sub = cabs2(Tr[(l - 1) * LDT + l], Ti[(l - 1) * LDT + l]);
+        double d = cabs2(Tr[(l - 1) * LDT + l - 1], Ti[(l - 1) * LDT + l - 1]) +
+                   cabs2(Tr[l * LDT + l], Ti[l * LDT + l]);
         if (d == 0.0) d = st->hnorm;
         if (sub <= EPS * d) {
-          Tr[(l - 1) * LD + l] = 0.0;
-          Ti[(l - 1) * LD + l] = 0.0;
+          Tr[(l - 1) * LDT + l] = 0.0;
+          Ti[(l - 1) * LDT + l] = 0.0;
           break;
         }
         --l;
@@ -68,10 +70,10 @@ __device__ int complex_schur(IState* st, int m) {
       } else {
         s_stop = 0;
         // Wilkinson shift from the trailing 2x2 block
-        const double ar = Tr[(hi - 1) * LD + hi - 1], ai = Ti[(hi - 1) * LD + hi - 1];
-        const double br = Tr[hi * LD + hi - 1], bi = Ti[hi * LD + hi - 1];
-        const double cr = Tr[(hi - 1) * LD + hi], ci = Ti[(hi - 1) * LD + hi];
-        const double dr = Tr[hi * LD + hi], di = Ti[hi * LD + hi];
+        const double ar = Tr[(hi - 1) * LDT + hi - 1], ai = Ti[(hi - 1) * LDT + hi - 1];
+        const double br = Tr[hi * LDT + hi - 1], bi = Ti[hi * LDT + hi - 1];
+        const double cr = Tr[(hi - 1) * LDT + hi], ci = Ti[(hi - 1) * LDT + hi];
+        const double dr = Tr[hi * LDT + hi], di = Ti[hi * LDT + hi];
         // eigenvalues of [[a b][c d]]: t/2 +- sqrt((a-d)^2/4 + b c)
         const double hr = 0.5 * (ar - dr), hi_ = 0.5 * (ai - di);
         const double qr = hr * hr - hi_ * hi_ + (br * cr - bi * ci);
@@ -87,7 +89,7 @@ __device__ int complex_schur(IState* st, int m) {
         double mr = d1 < d2 ? m1r : m2r, mi = d1 < d2 ? m1i : m2i;
         ++s_iter;
         if (s_iter % 11 == 10) {   // exceptional shift
-          const double sub = cabs2(Tr[(hi - 1) * LD + hi], Ti[(hi - 1) * LD + hi]);
+          const double sub = cabs2(Tr[(hi - 1) * LDT + hi], Ti[(hi - 1) * LDT + hi]);
           mr = dr + 0.75 * sub;
           mi = di;
         }
@@ -108,15 +110,15 @@ __device__ int complex_schur(IState* st, int m) {
       if (lane == 0) {
         double xr, xi, yr, yi;
         if (k == l) {
-          xr = Tr[l * LD + l] - s_mr;
-          xi = Ti[l * LD + l] - s_mi;
-          yr = Tr[l * LD + l + 1];
-          yi = Ti[l * LD + l + 1];
+          xr = Tr[l * LDT + l] - s_mr;
+          xi = Ti[l * LDT + l] - s_mi;
+          yr = Tr[l * LDT + l + 1];
+          yi = Ti[l * LDT + l + 1];
         } else {
-          xr = Tr[(k - 1) * LD + k];
-          xi = Ti[(k - 1) * LD + k];
-          yr = Tr[(k - 1) * LD + k + 1];
-          yi = Ti[(k - 1) * LD + k + 1];
+          xr = Tr[(k - 1) * LDT + k];
+          xi = Ti[(k - 1) * LDT + k];
+          yr = Tr[(k - 1) * LDT + k + 1];
+          yi = Ti[(k - 1) * LDT + k + 1];
         }
         const double ax = hypot(xr, xi), ay = hypot(yr, yi);
         const double nrm = hypot(ax, ay);
@@ -142,13 +144,13 @@ __device__ int complex_schur(IState* st, int m) {
       {
         const int j = lane;
         if (j < m && j >= (k > 0 ? k - 1 : 0)) {
-          const double t1r = Tr[j * LD + k], t1i = Ti[j * LD + k];
-          const double t2r = Tr[j * LD + k + 1], t2i = Ti[j * LD + k + 1];
-          Tr[j * LD + k] = c * t1r + (sr * t2r - si * t2i);
-          Ti[j * LD + k] = c * t1i + (sr * t2i + si * t2r);
+          const double t1r = Tr[j * LDT + k], t1i = Ti[j * LDT + k];
+          const double t2r = Tr[j * LDT + k + 1], t2i = Ti[j * LDT + k + 1];
+          Tr[j * LDT + k] = c * t1r + (sr * t2r - si * t2i);
+          Ti[j * LDT + k] = c * t1i + (sr * t2i + si * t2r);
           // -conj(s) t1 + c t2
-          Tr[j * LD + k + 1] = -(sr * t1r + si * t1i) + c * t2r;
-          Ti[j * LD + k + 1] = -(sr * t1i - si * t1r) + c * t2i;
+          Tr[j * LDT + k + 1] = -(sr * t1r + si * t1i) + c * t2r;
+          Ti[j * LDT + k + 1] = -(sr * t1i - si * t1r) + c * t2i;
         }
       }
       __syncthreads();
@@ -157,21 +159,21 @@ __device__ int complex_schur(IState* st, int m) {
         const int i = lane;
         const int imax = k + 2 < hi ? k + 2 : hi;
         if (i <= imax) {
-          const double t1r = Tr[k * LD + i], t1i = Ti[k * LD + i];
-          const double t2r = Tr[(k + 1) * LD + i], t2i = Ti[(k + 1) * LD + i];
+          const double t1r = Tr[k * LDT + i], t1i = Ti[k * LDT + i];
+          const double t2r = Tr[(k + 1) * LDT + i], t2i = Ti[(k + 1) * LDT + i];
           // t1 c + t2 conj(s) ; -t1 s + t2 c
-          Tr[k * LD + i] = t1r * c + (t2r * sr + t2i * si);
-          Ti[k * LD + i] = t1i * c + (t2i * sr - t2r * si);
-          Tr[(k + 1) * LD + i] = -(t1r * sr - t1i * si) + t2r * c;
-          Ti[(k + 1) * LD + i] = -(t1r * si + t1i * sr) + t2i * c;
+          Tr[k * LDT + i] = t1r * c + (t2r * sr + t2i * si);
+          Ti[k * LDT + i] = t1i * c + (t2i * sr - t2r * si);
+          Tr[(k + 1) * LDT + i] = -(t1r * sr - t1i * si) + t2r * c;
+          Ti[(k + 1) * LDT + i] = -(t1r * si + t1i * sr) + t2i * c;
         }
         if (i < m) {
-          const double z1r = Zr[k * LD + i], z1i = Zi[k * LD + i];
-          const double z2r = Zr[(k + 1) * LD + i], z2i = Zi[(k + 1) * LD + i];
-          Zr[k * LD + i] = z1r * c + (z2r * sr + z2i * si);
-          Zi[k * LD + i] = z1i * c + (z2i * sr - z2r * si);
-          Zr[(k + 1) * LD + i] = -(z1r * sr - z1i * si) + z2r * c;
-          Zi[(k + 1) * LD + i] = -(z1r * si + z1i * sr) + z2i * c;
+          const double z1r = Zr[k * LDT + i], z1i = Zi[k * LDT + i];
+          const double z2r = Zr[(k + 1) * LDT + i], z2i = Zi[(k + 1) * LDT + i];
+          Zr[k * LDT + i] = z1r * c + (z2r * sr + z2i * si);
+          Zi[k * LDT + i] = z1i * c + (z2i * sr - z2r * si);
+          Zr[(k + 1) * LDT + i] = -(z1r * sr - z1i * si) + z2r * c;
+          Zi[(k + 1) * LDT + i] = -(z1r * si + z1i * sr) + z2i * c;
         }
       }
       __syncthreads();
@@ -182,10 +184,10 @@ __device__ int complex_schur(IState* st, int m) {
 
 // Unit eigenvector of T for eigenvalue p (lane p), mapped by Z: stored in
 // (Yr, Yi) column p (unsorted order, later permuted).
-__device__ void schur_eigvec(IState* st, int m, int p, double* xr, double* xi) {
-  const double* Tr = st->Tr;
-  const double* Ti = st->Ti;
-  const double lr = Tr[p * LD + p], li = Ti[p * LD + p];
+template <int LDT>
+__device__ void schur_eigvec(IState* st, int m, int p, const double* Tr, const double* Ti, double* xr,
+                             double* xi) {
+  const double lr = Tr[p * LDT + p], li = Ti[p * LDT + p];
   const double smin = fmax(EPS * st->hnorm, DBL_MIN * 1e10);
   for (int i = 0; i < m; ++i) {
     xr[i] = 0.0;
@@ -195,11 +197,11 @@ __device__ void schur_eigvec(IState* st, int m, int p, double* xr, double* xi) {
   for (int i = p - 1; i >= 0; --i) {
     double sr = 0.0, si = 0.0;
     for (int j = i + 1; j <= p; ++j) {
-      const double ar = Tr[j * LD + i], ai = Ti[j * LD + i];
+      const double ar = Tr[j * LDT + i], ai = Ti[j * LDT + i];
       sr += ar * xr[j] - ai * xi[j];
       si += ar * xi[j] + ai * xr[j];
     }
-    double dr = Tr[i * LD + i] - lr, di = Ti[i * LD + i] - li;
+    double dr = Tr[i * LDT + i] - lr, di = Ti[i * LDT + i] - li;
     if (hypot(dr, di) < smin) {
       dr = smin;
       di = 0.0;
@@ -211,9 +213,27 @@ __device__ void schur_eigvec(IState* st, int m, int p, double* xr, double* xi) {
   }
 }
 
+// USE_LDS: the working matrices live in LDS with leading dimension
+// RESTART_LDS_M (dynamic LDS of 4 RESTART_LDS_M m doubles); else in the
+// state's arrays.
+template <bool USE_LDS>
 __global__ void restart_kernel(IState* st) {
+  constexpr int L = USE_LDS ? RESTART_LDS_M : LD;
+  extern __shared__ double lds[];
   const int lane = threadIdx.x;
   const int m = st->m;
+  if (USE_LDS && m > RESTART_LDS_M) {   // launched for a smaller m: refuse
+    if (lane == 0) {
+      st->fail = 1;
+      st->done = 1;
+    }
+    return;
+  }
+  const int ms = USE_LDS ? L * m : 0;   // LDS words per matrix
+  double* Tr = USE_LDS ? lds : st->Tr;
+  double* Ti = USE_LDS ? lds + ms : st->Ti;
+  double* Zr = USE_LDS ? lds + 2 * ms : st->Zr;
+  double* Zi = USE_LDS ? lds + 3 * ms : st->Zi;
   // H_m and the norms
   for (int j = 0; j < m; ++j)
     if (lane < m) st->Hm[j * LD + lane] = st->H[j * (MMAX + 1) + lane];
@@ -227,7 +247,7 @@ __global__ void restart_kernel(IState* st) {
     st->fail = 0;
   }
   __syncthreads();
-  if (complex_schur(st, m)) {
+  if (complex_schur<L>(st, m, Tr, Ti, Zr, Zi)) {
     if (lane == 0) {
       st->fail = 1;
       st->done = 1;
@@ -238,11 +258,11 @@ __global__ void restart_kernel(IState* st) {
   // eigenvalues and unit eigenvectors (lane p -> eigenvalue p), into M/HQ
   // as temporaries (x in M/HQ columns, y = Z x into er/ei later)
   if (lane < m) {
-    st->er[lane] = st->Tr[lane * LD + lane];
-    st->ei[lane] = st->Ti[lane * LD + lane];
+    st->er[lane] = Tr[lane * L + lane];
+    st->ei[lane] = Ti[lane * L + lane];
     double* xr = st->M + lane * LD;
     double* xi = st->HQ + lane * LD;
-    schur_eigvec(st, m, lane, xr, xi);
+    schur_eigvec<L>(st, m, lane, Tr, Ti, xr, xi);
   }
   __syncthreads();
   // y_p = Z x_p, normalised; store unsorted into Yr/Yi
@@ -254,7 +274,7 @@ __global__ void restart_kernel(IState* st) {
     for (int i = 0; i < m; ++i) {
       double yr = 0.0, yi = 0.0;
       for (int j = 0; j <= p; ++j) {
-        const double zr = st->Zr[j * LD + i], zi = st->Zi[j * LD + i];
+        const double zr = Zr[j * L + i], zi = Zi[j * L + i];
         yr += zr * xr[j] - zi * xi[j];
         yi += zr * xi[j] + zi * xr[j];
       }
@@ -386,9 +406,17 @@ __global__ void restart_kernel(IState* st) {
   __syncthreads();
   if (s_done) return;
   const int k = s_k;
+  // the shift steps work on H_m, M, HQ and Q (in LDS: where T and Z were)
+  double* Hm = USE_LDS ? lds : st->Hm;
+  double* Mw = USE_LDS ? lds + ms : st->M;
+  double* HQ = USE_LDS ? lds + 2 * ms : st->HQ;
+  double* Q = USE_LDS ? lds + 3 * ms : st->Q;
   // Q = I
   for (int j = 0; j < m; ++j)
-    if (lane < m) st->Q[j * LD + lane] = lane == j ? 1.0 : 0.0;
+    if (lane < m) {
+      Q[j * L + lane] = lane == j ? 1.0 : 0.0;
+      if (USE_LDS) Hm[j * L + lane] = st->Hm[j * LD + lane];
+    }
   __syncthreads();
   __shared__ double s_v[MMAX];
   __shared__ double s_mu[2];
@@ -409,28 +437,28 @@ __global__ void restart_kernel(IState* st) {
         double v;
         if (pair) {
           double hh = 0.0;
-          for (int r = 0; r < m; ++r) hh += st->Hm[r * LD + i] * st->Hm[j * LD + r];
-          v = hh - 2.0 * mr * st->Hm[j * LD + i] + (i == j ? mr * mr + mi * mi : 0.0);
+          for (int r = 0; r < m; ++r) hh += Hm[r * L + i] * Hm[j * L + r];
+          v = hh - 2.0 * mr * Hm[j * L + i] + (i == j ? mr * mr + mi * mi : 0.0);
         } else {
-          v = st->Hm[j * LD + i] - (i == j ? mr : 0.0);
+          v = Hm[j * L + i] - (i == j ? mr : 0.0);
         }
-        st->M[j * LD + i] = v;
+        Mw[j * L + i] = v;
       }
-      for (int i = 0; i < m; ++i) st->HQ[j * LD + i] = i == j ? 1.0 : 0.0;   // Qj = I
+      for (int i = 0; i < m; ++i) HQ[j * L + i] = i == j ? 1.0 : 0.0;   // Qj = I
     }
     __syncthreads();
     // Householder QR of M; Qj accumulated in HQ (Qj <- Qj P)
     for (int c = 0; c < m - 1; ++c) {
       if (lane == 0) {
         double nrm = 0.0;
-        for (int i = c; i < m; ++i) nrm += st->M[c * LD + i] * st->M[c * LD + i];
+        for (int i = c; i < m; ++i) nrm += Mw[c * L + i] * Mw[c * L + i];
         nrm = sqrt(nrm);
-        const double x0 = st->M[c * LD + c];
+        const double x0 = Mw[c * L + c];
         const double alpha = x0 >= 0 ? -nrm : nrm;
         for (int i = 0; i < m; ++i) s_v[i] = 0.0;
         if (nrm > 0.0) {
           s_v[c] = x0 - alpha;
-          for (int i = c + 1; i < m; ++i) s_v[i] = st->M[c * LD + i];
+          for (int i = c + 1; i < m; ++i) s_v[i] = Mw[c * L + i];
           double vn = 0.0;
           for (int i = c; i < m; ++i) vn += s_v[i] * s_v[i];
           vn = sqrt(vn);
@@ -446,14 +474,14 @@ __global__ void restart_kernel(IState* st) {
         const int j = lane;
         if (j >= c) {
           double d = 0.0;
-          for (int i = c; i < m; ++i) d += s_v[i] * st->M[j * LD + i];
-          for (int i = c; i < m; ++i) st->M[j * LD + i] -= 2.0 * d * s_v[i];
+          for (int i = c; i < m; ++i) d += s_v[i] * Mw[j * L + i];
+          for (int i = c; i < m; ++i) Mw[j * L + i] -= 2.0 * d * s_v[i];
         }
         // Qj <- Qj P on row lane
         const int i = lane;
         double d = 0.0;
-        for (int r = c; r < m; ++r) d += st->HQ[r * LD + i] * s_v[r];
-        for (int r = c; r < m; ++r) st->HQ[r * LD + i] -= 2.0 * d * s_v[r];
+        for (int r = c; r < m; ++r) d += HQ[r * L + i] * s_v[r];
+        for (int r = c; r < m; ++r) HQ[r * L + i] -= 2.0 * d * s_v[r];
       }
       __syncthreads();
     }
@@ -462,8 +490,8 @@ __global__ void restart_kernel(IState* st) {
       const int i = lane;
       for (int j = 0; j < m; ++j) {
         double s = 0.0;
-        for (int r = 0; r < m; ++r) s += st->Hm[r * LD + i] * st->HQ[j * LD + r];
-        st->M[j * LD + i] = s;
+        for (int r = 0; r < m; ++r) s += Hm[r * L + i] * HQ[j * L + r];
+        Mw[j * L + i] = s;
       }
     }
     __syncthreads();
@@ -471,8 +499,8 @@ __global__ void restart_kernel(IState* st) {
       const int j = lane;
       for (int i = 0; i < m; ++i) {
         double s = 0.0;
-        for (int r = 0; r < m; ++r) s += st->HQ[i * LD + r] * st->M[j * LD + r];
-        st->Hm[j * LD + i] = (i > j + 1) ? 0.0 : s;   // Hessenberg up to rounding
+        for (int r = 0; r < m; ++r) s += HQ[i * L + r] * Mw[j * L + r];
+        Hm[j * L + i] = (i > j + 1) ? 0.0 : s;   // Hessenberg up to rounding
       }
     }
     __syncthreads();
@@ -481,28 +509,29 @@ __global__ void restart_kernel(IState* st) {
       const int i = lane;
       for (int j = 0; j < m; ++j) {
         double s = 0.0;
-        for (int r = 0; r < m; ++r) s += st->Q[r * LD + i] * st->HQ[j * LD + r];
-        st->M[j * LD + i] = s;
+        for (int r = 0; r < m; ++r) s += Q[r * L + i] * HQ[j * L + r];
+        Mw[j * L + i] = s;
       }
     }
     __syncthreads();
     if (lane < m)
-      for (int j = 0; j < m; ++j) st->Q[j * LD + lane] = st->M[j * LD + lane];
+      for (int j = 0; j < m; ++j) Q[j * L + lane] = Mw[j * L + lane];
     __syncthreads();
     o += pair ? 2 : 1;
   }
   // k-step update data; H <- [H_k 0; 0 0]
   if (lane == 0) {
-    st->coef[0] = st->Hm[(k - 1) * LD + k];                       // beta_hat = H(k+1, k)
-    st->coef[1] = st->Q[(k - 1) * LD + m - 1] * st->H[(m - 1) * (MMAX + 1) + m];   // Q(m,k) ||f_m||
+    st->coef[0] = Hm[(k - 1) * L + k];                       // beta_hat = H(k+1, k)
+    st->coef[1] = Q[(k - 1) * L + m - 1] * st->H[(m - 1) * (MMAX + 1) + m];   // Q(m,k) ||f_m||
     st->restarts += 1;
   }
   __syncthreads();
   for (int j = 0; j < m; ++j) {
     for (int i = lane; i <= m; i += blockDim.x) {
-      const double v = (j < k && i < k) ? st->Hm[j * LD + i] : 0.0;
+      const double v = (j < k && i < k) ? Hm[j * L + i] : 0.0;
       st->H[j * (MMAX + 1) + i] = v;
     }
+    if (USE_LDS && lane < m) st->Q[j * LD + lane] = Q[j * L + lane];   // read by the k-step update
   }
 }
 
@@ -637,7 +666,12 @@ inline unsigned grid_for(long long n) {
 }  // namespace
 
 void iram_column(IState* st, int j, hipStream_t s) { column_kernel<<<1, 64, 0, s>>>(st, j); }
-void iram_restart(IState* st, hipStream_t s) { restart_kernel<<<1, 64, 0, s>>>(st); }
+void iram_restart(IState* st, int m, hipStream_t s) {
+  if (m <= RESTART_LDS_M)
+    restart_kernel<true><<<1, 64, sizeof(double) * 4 * RESTART_LDS_M * m, s>>>(st);
+  else
+    restart_kernel<false><<<1, 64, 0, s>>>(st);
+}
 void iram_set_fk(IState* st, hipStream_t s) { set_fk_kernel<<<1, 64, 0, s>>>(st); }
 void iram_inv_norm(IState* st, hipStream_t s) { inv_norm_kernel<<<1, 64, 0, s>>>(st); }
 void iram_init(IState* st, int m, int nev, double tol, double sigma, double mu, int max_restarts,

@@ -109,7 +109,7 @@ int run_one(Ctx* c, const sa_eig_opts& o, const double* v0, sa_eig_result* res) 
     int done, fail, k, nconv, restarts;
   } h{};
   for (;;) {
-    iram_restart(w.st, s);
+    iram_restart(w.st, m, s);
     hipError_t e = hipMemcpyAsync(&h.done, &w.st->done, sizeof(int), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipMemcpyAsync(&h.fail, &w.st->fail, sizeof(int), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipMemcpyAsync(&h.k, &w.st->k, sizeof(int), hipMemcpyDeviceToHost, s);

@@ -98,6 +98,20 @@ def test_kh_pair_fp64():
     assert all(x < 1e-8 for x in res)
 
 
+@pytest.mark.parametrize("ncv", [44, 48], ids=["m44-lds", "m48-global"])
+def test_kh_pair_large_arnoldi_dimension(ncv):
+    """The restart's dense steps keep their matrices in LDS up to m = 44 and
+    in the state's global arrays above: both against the dense spectrum and
+    the oracle's operator."""
+    need_gpu()
+    prob = synth.mixing_layer_2d(24, 24, 0.3, 500.0)
+    rc, r, ev = run(prob, nev=2, ncv=ncv, evecs=True)
+    assert rc == 0 and r["nconv"] >= 2
+    check(r["lam"], golden("kh_24x24_M0.3_Re500"), 1)
+    res = oracle_residuals(prob, synth.base_flow(prob), r["lam"], *ev)
+    assert all(x < 1e-8 for x in res), res
+
+
 @pytest.mark.parametrize("precname", ["fp64", "mixed"])
 def test_reduced_3d_spectrum(precname):
     """3D 16x16x8 (M = 0.5, Re = 1000, the workload's tanh base with 1e-3
