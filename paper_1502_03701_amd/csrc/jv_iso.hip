@@ -48,8 +48,10 @@ constexpr int NXCD = 8;
 
 __device__ __forceinline__ int wrapc(int a, int n) { return a < 0 ? a + n : (a >= n ? min(a - n, n - 1) : a); }
 
+// FP32 full tiles: four wavefronts per SIMD (128 VGPRs, a 20-byte spill)
+// run 8-10 % faster than three (145 VGPRs, none)
 template <typename R, int ND, int NZC, bool FULL>
-__global__ void __launch_bounds__(NT, sizeof(R) == 4 && FULL ? 3 : 2) jv_iso_kernel(OpParams op, IsoBase<R> ib, const R* __restrict__ x,
+__global__ void __launch_bounds__(NT, sizeof(R) == 4 && FULL ? 4 : 2) jv_iso_kernel(OpParams op, IsoBase<R> ib, const R* __restrict__ x,
                                                     R* __restrict__ y, R shift, const int* __restrict__ active,
                                                     long long strideX, long long strideY,
                                                     const double* __restrict__ shifts, long long sA, int zchunks,
