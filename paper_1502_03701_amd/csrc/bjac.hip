@@ -303,6 +303,10 @@ __global__ void __launch_bounds__(256) lu_kernel(BLayout L, const double* __rest
 // j = l % 16, k = l / 16; accumulator v of D[i][j] with i = 4 (l / 16) + v,
 // j = l % 16.
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+// Two wavefronts per factorisation: the first eliminates each panel, both
+// share the row exchanges, the triangular solve, the trailing update's tiles
+// and the block's load and store.
+constexpr int LU_MFMA_THREADS = 128;
 
 // maximum of v over the wavefront (uniform result): prefix maxima within
 // each row of 16 lanes by DPP row shifts (lanes without a source take
@@ -317,7 +321,7 @@ __device__ __forceinline__ int wave_max_bits(int v) {
   return max(max(r0, r1), max(r2, r3));
 }
 
-__global__ void __launch_bounds__(64) lu_mfma_kernel(BLayout L, const double* __restrict__ B,
+__global__ void __launch_bounds__(LU_MFMA_THREADS) lu_mfma_kernel(BLayout L, const double* __restrict__ B,
                                                      const double* __restrict__ shifts, double diag_add,
                                                      float* __restrict__ LU, int* __restrict__ perm,
                                                      int* __restrict__ singular) {
@@ -326,17 +330,20 @@ __global__ void __launch_bounds__(64) lu_mfma_kernel(BLayout L, const double* __
   const int ld = nb + 1;   // odd column stride: lane-per-column accesses hit distinct banks
   float* A = reinterpret_cast<float*>(smem);   // nb x nb column-major, leading dimension ld
   __shared__ int s_perm[128];
-  const int lane = threadIdx.x;
+  __shared__ int s_piv[16];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr int NW = LU_MFMA_THREADS / 64;
   long long b;
   int s;
   lu_work_item(L.nblocks, b, s);
   const double dshift = diag_add - shifts[s];
   const double* Bb = B + b * nb * nb;
   // by columns (lane: rows lane and lane + 64), 10 columns = 20 loads in
-  // flight per lane per batch (the block is 51 KB of FP64); no index division
+  // flight per lane per batch (the block is 51 KB of FP64), the batches
+  // shared out over the wavefronts; no index division
   const bool r1 = lane < nb, r2 = lane + 64 < nb;
   const int l1 = r1 ? lane : nb - 1;   // clamped rows: loads stay inside the block
-  for (int c0l = 0; c0l < nb; c0l += 10) {
+  for (int c0l = 10 * wave; c0l < nb; c0l += 10 * NW) {
     double v[10][2];
 #pragma unroll
     for (int q = 0; q < 10; ++q) {
@@ -358,11 +365,12 @@ __global__ void __launch_bounds__(64) lu_mfma_kernel(BLayout L, const double* __
       }
     }
   }
-  for (int t = lane; t < nb; t += 64) s_perm[t] = t;
+  for (int t = tid; t < nb; t += LU_MFMA_THREADS) s_perm[t] = t;
   __syncthreads();
   bool sing = false;
   const int li = lane % 16, lk = lane / 16;
   for (int c0 = 0; c0 < nb; c0 += 16) {
+    if (wave == 0) {
     // Panel elimination, columns c0 .. c0+15, in registers: lane l holds the
     // physical rows c0 + l (slot a) and c0 + 64 + l (slot b) of the panel.
     // Pivoting is implicit: rows are not exchanged inside the panel; each
@@ -444,13 +452,19 @@ __global__ void __launch_bounds__(64) lu_mfma_kernel(BLayout L, const double* __
       if (ra < nb) A[(c0 + c) * ld + posa] = P[0][c];
       if (rb < nb) A[(c0 + c) * ld + posb] = P[1][c];
     }
-    // the panel's row exchanges on the other columns (a lane per column)
-    for (int c = lane; c < nb - 16; c += 64) {
+    if (lane == 0) {
+#pragma unroll
+      for (int kk = 0; kk < 16; ++kk) s_piv[kk] = piv[kk];
+    }
+    }   // wave 0
+    __syncthreads();
+    // the panel's row exchanges on the other columns (a thread per column)
+    for (int c = tid; c < nb - 16; c += LU_MFMA_THREADS) {
       const int col = c < c0 ? c : c + 16;
       float* Ac = A + col * ld;
 #pragma unroll
       for (int kk = 0; kk < 16; ++kk) {
-        const int k = c0 + kk, p = piv[kk];
+        const int k = c0 + kk, p = s_piv[kk];
         if (p != k) {
           const float t1 = Ac[k];
           Ac[k] = Ac[p];
@@ -461,8 +475,8 @@ __global__ void __launch_bounds__(64) lu_mfma_kernel(BLayout L, const double* __
     __syncthreads();
     const int c1 = c0 + 16;
     if (c1 >= nb) break;
-    // U12 = L11^-1 A12 (unit lower L11), a lane per column
-    for (int c = c1 + lane; c < nb; c += 64) {
+    // U12 = L11^-1 A12 (unit lower L11), a thread per column
+    for (int c = c1 + tid; c < nb; c += LU_MFMA_THREADS) {
       float x[16];
 #pragma unroll
       for (int i = 0; i < 16; ++i) x[i] = A[c * ld + c0 + i];
@@ -477,7 +491,7 @@ __global__ void __launch_bounds__(64) lu_mfma_kernel(BLayout L, const double* __
     __syncthreads();
     // A22 -= L21 U12, 16 x 16 tiles on the matrix cores
     const int nt = (nb - c1) / 16;
-    for (int t = 0; t < nt * nt; ++t) {
+    for (int t = wave; t < nt * nt; t += NW) {
       const int r0 = c1 + 16 * (t % nt), q0 = c1 + 16 * (t / nt);
       floatx4 acc;
 #pragma unroll
@@ -493,17 +507,17 @@ __global__ void __launch_bounds__(64) lu_mfma_kernel(BLayout L, const double* __
     }
     __syncthreads();
   }
-  if (sing && lane == 0) atomicOr(singular, 1);
+  if (sing && tid == 0) atomicOr(singular, 1);
   const long long g = b / 64;
   const int gl = (int)(b % 64);
   const long long ngroups = (L.nblocks + 63) / 64;
   float* out = LU + ((long long)s * ngroups + g) * nb * nb * 64 + gl;
-  for (int col = 0; col < nb; ++col) {
+  for (int col = wave; col < nb; col += NW) {
     if (r1) out[((long long)col * nb + lane) * 64] = A[col * ld + lane];
     if (r2) out[((long long)col * nb + lane + 64) * 64] = A[col * ld + lane + 64];
   }
   int* pout = perm + ((long long)s * ngroups + g) * nb * 64 + gl;
-  for (int t = lane; t < nb; t += 64) pout[t * 64] = s_perm[t];
+  for (int t = tid; t < nb; t += LU_MFMA_THREADS) pout[t * 64] = s_perm[t];
 }
 
 // z_b = U^{-1} L^{-1} (P r_b), one lane per block: a wavefront solves the 64
@@ -754,8 +768,8 @@ extern "C" int sa_precond_setup(sa_ctx* c, const sa_precond_opts* o, int nshift,
   if (o->factor_prec == SA_F64)
     lu_kernel<double><<<grid, 256, lds, s>>>(L, B, sh, o->diag_add, (double*)LU, perm, flag);
   else if (L.nb % 16 == 0)   // LDS block with leading dimension nb + 1
-    lu_mfma_kernel<<<grid, 64, sizeof(float) * L.nb * (L.nb + 1), s>>>(L, B, sh, o->diag_add, (float*)LU, perm,
-                                                                         flag);
+    lu_mfma_kernel<<<grid, LU_MFMA_THREADS, sizeof(float) * L.nb * (L.nb + 1), s>>>(L, B, sh, o->diag_add,
+                                                                                      (float*)LU, perm, flag);
   else
     lu_kernel<float><<<grid, 256, lds, s>>>(L, B, sh, o->diag_add, (float*)LU, perm, flag);
   hipError_t e = hipGetLastError();
