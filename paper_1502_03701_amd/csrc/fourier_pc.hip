@@ -349,6 +349,32 @@ __global__ void __launch_bounds__(256) u_pack_kernel(FGeom g, long long nblk, in
   }
 }
 
+// FP32 factors in step pairs: the rows a sweep uses at two consecutive steps
+// side by side (16 bytes a lane, one load serves two steps): Out[q][w] =
+// (In[a][w], In[b][w]) with rows (a, b) = (2q, 2q + 1) for the forward sweep,
+// (N-1-2q, N-2-2q) for the back substitution (rev), zero where a row is
+// outside 0 .. N-1; a zero pair after each block.  In: rows of width W with
+// a zero slot after each block of N rows.
+__global__ void __launch_bounds__(256) pair_rows_kernel(int N, int W, int rev, long long nblk,
+                                                        const cx<float>* __restrict__ In, cx<float>* __restrict__ Out) {
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  const int NP = (N + 1) / 2, np = NP * W;
+  if (r > np) return;
+  const int q = r / W, w = r - q * W;
+  const int ra = rev ? N - 1 - 2 * q : 2 * q, rb = rev ? N - 2 - 2 * q : 2 * q + 1;
+  for (long long b = blockIdx.y; b < nblk; b += gridDim.y) {
+    cx<float> o0{0.0f, 0.0f}, o1{0.0f, 0.0f};
+    if (r < np) {
+      const cx<float>* in = In + b * ((long long)N * W + 1);
+      if (ra >= 0 && ra < N) o0 = in[(long long)ra * W + w];
+      if (rb >= 0 && rb < N) o1 = in[(long long)rb * W + w];
+    }
+    cx<float>* out = Out + 2 * (b * ((long long)np + 1) + r);
+    out[0] = o0;
+    out[1] = o1;
+  }
+}
+
 // ---------------------------------------------------------------- apply ----
 
 // Division by a small runtime divisor d with a multiply-high: for a d < 2^32,
@@ -713,7 +739,8 @@ __device__ __forceinline__ cx<R> cfms(cx<R> z, R lr, R li, cx<R> b) {
 // group runs (two register sets used in turn) and placed above the window
 // at the group's start (window + entering + finished rows fit in 64 lanes).
 // System sys uses the factors of shift shift0 + sys * shift_step.
-template <typename F, typename R, int GB>
+// PAIR (FP32 factors): L and U in the step-pair layout of pair_rows_kernel.
+template <typename F, typename R, int GB, bool PAIR>
 __global__ void __launch_bounds__(64) band_solve_kernel(FGeom g, const cx<F>* __restrict__ Lo,
                                                         const cx<F>* __restrict__ Uo, const int* __restrict__ pivo,
                                                         int shift0, int shift_step, cx<R>* __restrict__ spec,
@@ -724,9 +751,10 @@ __global__ void __launch_bounds__(64) band_solve_kernel(FGeom g, const cx<F>* __
   const int lane = threadIdx.x;
   const int N = g.N, kl = g.kl;
   const long long fo = (long long)(shift0 + sys * shift_step) * g.nmodes + m;
-  const cx<F>* L = Lo + fo * ((long long)N * kl + 1);
   const int KU = g.KU;
-  const cx<F>* Ut = Uo + fo * ((long long)N * KU + 1);
+  const int NP = (N + 1) / 2;   // step pairs (PAIR)
+  const cx<F>* L = Lo + (PAIR ? 2 * fo * ((long long)NP * kl + 1) : fo * ((long long)N * kl + 1));
+  const cx<F>* Ut = Uo + (PAIR ? 2 * fo * ((long long)NP * KU + 1) : fo * ((long long)N * KU + 1));
   const int* piv = pivo + fo * (long long)N;
   cx<R>* vec = spec + ((long long)sys * g.nmodes + m) * N;   // mode m = kz mx + kx
   // loads are unconditional and need no select after them (idle lanes read
@@ -751,12 +779,26 @@ __global__ void __launch_bounds__(64) band_solve_kernel(FGeom g, const cx<F>* __
   // zero slot for the others
   const unsigned lmoff = (unsigned)(lane - 1) * (unsigned)sizeof(cx<F>);
   auto load_fwd = [&](int c0, FwdSet& f) {
+    if constexpr (PAIR) {
+      // c0 is even: steps c0 + s and c0 + s + 1 are pair (c0 + s) / 2
+      const long long pzero = (long long)NP * kl;
 #pragma unroll
-    for (int s = 0; s < GF; ++s) {
-      const int col = min(c0 + s, N - 1);   // steps past the end run on row N-1's multipliers
-      const long long rb = (long long)col * kl;
-      const unsigned off = lmul ? lmoff : (unsigned)((lzero - rb) * (long long)sizeof(cx<F>));
-      f.l[s] = *reinterpret_cast<const cx<F>*>(reinterpret_cast<const char*>(L + rb) + off);
+      for (int s = 0; s < GF; s += 2) {
+        const int q = min((c0 + s) >> 1, NP - 1);   // pairs past the end: the last pair
+        const long long rb = (long long)q * kl;
+        const unsigned off = lmul ? (unsigned)(lane - 1) * 16u : (unsigned)((pzero - rb) * 16);
+        const float4 v = *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(L) + rb * 16 + off);
+        f.l[s] = cx<F>{v.x, v.y};
+        f.l[s + 1] = cx<F>{v.z, v.w};
+      }
+    } else {
+#pragma unroll
+      for (int s = 0; s < GF; ++s) {
+        const int col = min(c0 + s, N - 1);   // steps past the end run on row N-1's multipliers
+        const long long rb = (long long)col * kl;
+        const unsigned off = lmul ? lmoff : (unsigned)((lzero - rb) * (long long)sizeof(cx<F>));
+        f.l[s] = *reinterpret_cast<const cx<F>*>(reinterpret_cast<const char*>(L + rb) + off);
+      }
     }
     f.ent = vec[min(c0 + lane, N - 1)];
 #pragma unroll
@@ -798,12 +840,27 @@ __global__ void __launch_bounds__(64) band_solve_kernel(FGeom g, const cx<F>* __
   };
   const unsigned umoff = (unsigned)lane * (unsigned)sizeof(cx<F>);
   auto load_bwd = [&](int c0, BwdSet& b) {
+    if constexpr (PAIR) {
+      // N - 1 - c0 is a multiple of the (even) group: steps c0 - s and
+      // c0 - s - 1 are pair (N - 1 - c0 + s) / 2
+      const long long pzero = (long long)NP * KU;
 #pragma unroll
-    for (int s = 0; s < GB; ++s) {
-      const int col = max(c0 - s, 0);   // steps past the start run on row 0's column
-      const long long cb = (long long)col * KU;
-      const unsigned off = umul ? umoff : (unsigned)((uzero - cb) * (long long)sizeof(cx<F>));
-      b.u[s] = *reinterpret_cast<const cx<F>*>(reinterpret_cast<const char*>(Ut + cb) + off);
+      for (int s = 0; s < GB; s += 2) {
+        const int q = min((N - 1 - c0 + s) >> 1, NP - 1);   // pairs past the start: the last pair
+        const long long cb = (long long)q * KU;
+        const unsigned off = umul ? (unsigned)lane * 16u : (unsigned)((pzero - cb) * 16);
+        const float4 v = *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(Ut) + cb * 16 + off);
+        b.u[s] = cx<F>{v.x, v.y};
+        b.u[s + 1] = cx<F>{v.z, v.w};
+      }
+    } else {
+#pragma unroll
+      for (int s = 0; s < GB; ++s) {
+        const int col = max(c0 - s, 0);   // steps past the start run on row 0's column
+        const long long cb = (long long)col * KU;
+        const unsigned off = umul ? umoff : (unsigned)((uzero - cb) * (long long)sizeof(cx<F>));
+        b.u[s] = *reinterpret_cast<const cx<F>*>(reinterpret_cast<const char*>(Ut + cb) + off);
+      }
     }
     b.ent = vec[max(c0 - lane, 0)];
   };
@@ -913,17 +970,17 @@ hipError_t fourier_apply(Ctx* c, int ishift, int nrhs, const R* r, R* z, const i
   const cx<float>* L32 = (const cx<float>*)c->fp_L;
   const cx<float>* U32 = (const cx<float>*)c->fp_U;
   if (c->fp_f64 && wide)
-    band_solve_kernel<double, R, BS_GROUP_BACK_WIDE><<<gb, 64, 0, s>>>(g, L64, U64, c->fp_piv, ishift, shift_step, spec,
-                                                                       active, sA);
+    band_solve_kernel<double, R, BS_GROUP_BACK_WIDE, false><<<gb, 64, 0, s>>>(g, L64, U64, c->fp_piv, ishift,
+                                                                              shift_step, spec, active, sA);
   else if (c->fp_f64)
-    band_solve_kernel<double, R, BS_GROUP_BACK><<<gb, 64, 0, s>>>(g, L64, U64, c->fp_piv, ishift, shift_step, spec,
-                                                                  active, sA);
+    band_solve_kernel<double, R, BS_GROUP_BACK, false><<<gb, 64, 0, s>>>(g, L64, U64, c->fp_piv, ishift, shift_step,
+                                                                         spec, active, sA);
   else if (wide)
-    band_solve_kernel<float, R, BS_GROUP_BACK_WIDE><<<gb, 64, 0, s>>>(g, L32, U32, c->fp_piv, ishift, shift_step, spec,
-                                                                      active, sA);
+    band_solve_kernel<float, R, BS_GROUP_BACK_WIDE, true><<<gb, 64, 0, s>>>(g, L32, U32, c->fp_piv, ishift,
+                                                                            shift_step, spec, active, sA);
   else
-    band_solve_kernel<float, R, BS_GROUP_BACK><<<gb, 64, 0, s>>>(g, L32, U32, c->fp_piv, ishift, shift_step, spec,
-                                                                 active, sA);
+    band_solve_kernel<float, R, BS_GROUP_BACK, true><<<gb, 64, 0, s>>>(g, L32, U32, c->fp_piv, ishift, shift_step,
+                                                                       spec, active, sA);
   cx<R>* xin = spec;
   if (g.nd == 3) {
     fft_z<R><<<gz, FFT_THREADS, zlds, s>>>(g, pz, ub, ubm, B, tz, 1, A, active, sA);
@@ -1066,9 +1123,26 @@ int fourier_setup(Ctx* c, const sa_precond_opts* o, int nshift, const double* sh
     u_pack_kernel<float><<<gpk, 256, 0, s>>>(g, nfb, KU, (const cx<float>*)Uf, (cx<float>*)Uc);
   e = hipGetLastError();
   if (e != hipSuccess) return c->hip_fail(e, "sa_precond_setup pack");
+  void* Lsolve = Lf;
+  void* Usolve = Uc;
+  if (o->factor_prec != SA_F64) {
+    // FP32 factors: the step-pair layout (16-byte loads, one per two steps)
+    const size_t NP = (size_t)(g.N + 1) / 2;
+    void* Lp = c->buffer("fp_Lp", 16 * nfm * (NP * g.kl + 1), false);
+    void* Up = c->buffer("fp_Up", 16 * nfm * (NP * KU + 1), false);
+    if (!Lp || !Up) return c->fail(SA_ENOMEM, "sa_precond_setup: out of device memory");
+    const dim3 gpl((unsigned)((NP * g.kl + 1 + 255) / 256), ny_grid);
+    const dim3 gpu((unsigned)((NP * KU + 1 + 255) / 256), ny_grid);
+    pair_rows_kernel<<<gpl, 256, 0, s>>>(g.N, g.kl, 0, nfb, (const cx<float>*)Lf, (cx<float>*)Lp);
+    pair_rows_kernel<<<gpu, 256, 0, s>>>(g.N, KU, 1, nfb, (const cx<float>*)Uc, (cx<float>*)Up);
+    e = hipGetLastError();
+    if (e != hipSuccess) return c->hip_fail(e, "sa_precond_setup pairs");
+    Lsolve = Lp;
+    Usolve = Up;
+  }
   c->fp_ku = KU;
-  c->fp_U = Uc;
-  c->fp_L = Lf;
+  c->fp_U = Usolve;
+  c->fp_L = Lsolve;
   c->fp_piv = pv;
   c->fp_f64 = o->factor_prec == SA_F64;
   c->fp_specA64 = A64;
