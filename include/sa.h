@@ -244,7 +244,10 @@ int sa_op_apply(sa_ctx *ctx, sa_prec prec, int nrhs, const void *x_dev, void *y_
  * periodic axes the mode's banded matrix (bandwidths 4 nv - 1, order
  * (Ny-2) nv) is factored by LU with partial pivoting in factor_prec, one
  * wavefront per (mode, shift), all in one launch.  The y axis must have
- * walls.  Memory: nshift (Nx/2+1) Nz (Ny-2) nv (12 nv - 2) complex entries.
+ * walls.  Memory, in complex entries of factor_prec per unknown of the
+ * nshift (Nx/2+1) Nz (Ny-2) nv: 12 nv - 2 for the factorisation (L and U),
+ * KU <= 8 nv - 1 for U packed to its common column extent, and with FP32
+ * factors 4 nv - 1 + KU more for the step-pair copies the solve reads.
  *
  * SA_PC_BLOCK_JACOBI (Section "Preconditioning": blocks of the operator
  * assembled from operator calls).  Block b of shift s is
