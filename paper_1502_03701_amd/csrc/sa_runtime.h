@@ -118,7 +118,7 @@ void scratch_init(int device);
 
 template <typename R>
 int solve_gmres(Ctx* c, const sa_gmres_opts& o, int nsys, const double* sigma_host, const R* b, R* x, int pc_shift0,
-                sa_gmres_info* info, const std::string& tag = "g");
+                sa_gmres_info* info, const std::string& tag = "g", bool io_stable = false);
 int solve_ir(Ctx* c, const sa_gmres_opts& o, double sigma, const double* b, double* x, int pc_shift,
              sa_gmres_info* info);
 

@@ -72,7 +72,7 @@ constexpr size_t MAX_GRAPHS = 16;
 
 template <typename R>
 int solve_gmres(Ctx* c, const sa_gmres_opts& o, int nsys, const double* sigma, const R* b, R* x, int pc_shift0,
-                sa_gmres_info* info, const std::string& tag) {
+                sa_gmres_info* info, const std::string& tag, bool io_stable) {
   hipStream_t s = c->stream;
   const long long n = c->n;
   const int m = o.restart;
@@ -96,9 +96,12 @@ int solve_gmres(Ctx* c, const sa_gmres_opts& o, int nsys, const double* sigma, c
   bl.partial = (double*)c->buffer(tag + "partial", sizeof(double) * RED_BLOCKS * PARTIAL_LD * nsys);
   bl.ticket = (int*)c->buffer(tag + "ticket", sizeof(int) * nsys);
   // a captured cycle works on context-owned copies of b and x, so that one
-  // graph serves every caller buffer
-  R* X = graph ? (R*)c->buffer(tag + "X", sizeof(R) * n * nsys, false) : x;
-  R* B = graph ? (R*)c->buffer(tag + "B", sizeof(R) * n * nsys, false) : const_cast<R*>(b);
+  // graph serves every caller buffer; io_stable: b and x are themselves
+  // context-owned buffers that every call passes again (the refinement
+  // loop's), and the cycle works on them directly
+  const bool copy_io = graph && !io_stable;
+  R* X = copy_io ? (R*)c->buffer(tag + "X", sizeof(R) * n * nsys, false) : x;
+  R* B = copy_io ? (R*)c->buffer(tag + "B", sizeof(R) * n * nsys, false) : const_cast<R*>(b);
   if (!V || !Z || !T || !st || !sig || !bl.partial || !bl.ticket || !X || !B ||
       (k && (!AUG || !AUGA || !RPREV || !XOLD)))
     return c->fail(SA_ENOMEM, "gmres: out of device memory");
@@ -107,8 +110,8 @@ int solve_gmres(Ctx* c, const sa_gmres_opts& o, int nsys, const double* sigma, c
     if (e != hipSuccess) return c->hip_fail(e, "gmres capture stream");
   }
   hipError_t e = hipMemcpyAsync(sig, sigma, sizeof(double) * nsys, hipMemcpyHostToDevice, s);
-  if (e == hipSuccess && graph) e = hipMemcpyAsync(X, x, sizeof(R) * n * nsys, hipMemcpyDeviceToDevice, s);
-  if (e == hipSuccess && graph) e = hipMemcpyAsync(B, b, sizeof(R) * n * nsys, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess && copy_io) e = hipMemcpyAsync(X, x, sizeof(R) * n * nsys, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess && copy_io) e = hipMemcpyAsync(B, b, sizeof(R) * n * nsys, hipMemcpyDeviceToDevice, s);
   if (e != hipSuccess) return c->hip_fail(e, "gmres inputs");
   const R* base = base_of<R>(c);
   const R* bdata = bdata_of<R>(c);
@@ -290,7 +293,7 @@ int solve_gmres(Ctx* c, const sa_gmres_opts& o, int nsys, const double* sigma, c
     }
     ++cycles;
   }
-  if (graph) {
+  if (copy_io) {
     e = hipMemcpyAsync(x, X, sizeof(R) * n * nsys, hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess) return c->hip_fail(e, "gmres solution");
   }
@@ -300,9 +303,9 @@ int solve_gmres(Ctx* c, const sa_gmres_opts& o, int nsys, const double* sigma, c
 }
 
 template int solve_gmres<double>(Ctx*, const sa_gmres_opts&, int, const double*, const double*, double*, int,
-                                 sa_gmres_info*, const std::string&);
+                                 sa_gmres_info*, const std::string&, bool);
 template int solve_gmres<float>(Ctx*, const sa_gmres_opts&, int, const double*, const float*, float*, int,
-                                sa_gmres_info*, const std::string&);
+                                sa_gmres_info*, const std::string&, bool);
 
 size_t gmres_workspace_bytes(const Ctx* c, const sa_gmres_opts& o, int nshift) {
   auto r = [](size_t b) -> size_t { return (b + 255) / 256 * 256; };
@@ -392,7 +395,7 @@ int solve_ir(Ctx* c, const sa_gmres_opts& o, double sigma, const double* b, doub
     // the last sweeps need only close the remaining gap: ask the inner solve
     // for max(inner_tol, tol ||b|| / (2 ||r||)), never looser than 1/2
     in.tol = std::min(0.5, std::max(o.inner_tol, 0.5 * o.tol / h[0].relres));
-    int rc = solve_gmres<float>(c, in, 1, &sigma, r32, d32, pc_shift, &ii, "ir32");
+    int rc = solve_gmres<float>(c, in, 1, &sigma, r32, d32, pc_shift, &ii, "ir32", true);
     if (rc < 0) return rc;
     inner_mv += ii.matvecs;
     inner_it += ii.iters;
