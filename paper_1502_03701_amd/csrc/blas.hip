@@ -354,7 +354,7 @@ __global__ void __launch_bounds__(RED_THREADS) nrm2_kernel(long long n, const R*
   finish_reduction(partial, gridDim.x, gridDim.x, ldp, 1, e);
 }
 
-// r = b - y, partial ||r||^2 (b uses its own stride sB)
+// r = b - y, partial ||r||^2 (b uses its own stride sB; y null: y = 0)
 template <typename R>
 __global__ void __launch_bounds__(RED_THREADS) residual_kernel(long long n, const R* __restrict__ b,
                                                                const R* __restrict__ y, R* __restrict__ r,
@@ -363,14 +363,15 @@ __global__ void __launch_bounds__(RED_THREADS) residual_kernel(long long n, cons
                                                                long long sB, long long sP, long long sA,
                                                                long long sY, RedEnd e) {
   if (inactive(active, sA)) return;
+  const bool hy = y != nullptr;
   b += blockIdx.z * sB;
-  y += blockIdx.z * sY;
+  if (hy) y += blockIdx.z * sY;
   r += blockIdx.z * sV;
   partial += blockIdx.z * sP;
   double acc[1] = {0.0};
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    const R v = b[i] - y[i];
+    const R v = hy ? b[i] - y[i] : b[i];
     r[i] = v;
     acc[0] += (double)v * (double)v;
   }

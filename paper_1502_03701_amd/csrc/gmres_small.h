@@ -100,7 +100,8 @@ void gstate_set_bnorm(GState* st, int nsys, hipStream_t s);
 // beta = ||r||, convergence / budget tests; the cycle runs `restart` Krylov
 // steps (fewer if the operator budget is short) and then naug augmentation
 // steps
-void gstate_cycle_start(GState* st, int nsys, hipStream_t s, int naug = 0);
+// products: operator products behind this cycle's residual (0 when x was zero)
+void gstate_cycle_start(GState* st, int nsys, hipStream_t s, int naug = 0, int products = 1);
 void gstate_step(GState* st, int nsys, int j, hipStream_t s);
 void gstate_finish(GState* st, int nsys, hipStream_t s);
 

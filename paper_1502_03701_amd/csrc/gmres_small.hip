@@ -36,7 +36,7 @@ __global__ void set_bnorm_kernel(GState* base) {
   st->t.bnorm = sqrt(st->t.bnorm2);
 }
 
-__global__ void cycle_start_kernel(GState* base, int naug) {
+__global__ void cycle_start_kernel(GState* base, int naug, int products) {
   if (threadIdx.x != 0) return;
   GState* st = base + blockIdx.x;
   st->t.jdone = 0;
@@ -48,7 +48,7 @@ __global__ void cycle_start_kernel(GState* base, int naug) {
   const double beta = sqrt(st->t.rnorm2);
   st->t.beta = beta;
   st->t.relres = st->t.bnorm > 0.0 ? beta / st->t.bnorm : 0.0;
-  st->t.matvecs += 1;   // the residual product of this cycle
+  st->t.matvecs += products;   // the residual product of this cycle (0: x was zero)
   st->t.active = 0;
   if (!isfinite(beta)) {
     st->t.nonfinite = 1;
@@ -131,8 +131,8 @@ void gstate_init(GState* st, int nsys, double tol, int restart, long long max_ma
   init_kernel<<<nsys, 64, 0, s>>>(st, tol, restart, max_matvec);
 }
 void gstate_set_bnorm(GState* st, int nsys, hipStream_t s) { set_bnorm_kernel<<<nsys, 64, 0, s>>>(st); }
-void gstate_cycle_start(GState* st, int nsys, hipStream_t s, int naug) {
-  cycle_start_kernel<<<nsys, 64, 0, s>>>(st, naug);
+void gstate_cycle_start(GState* st, int nsys, hipStream_t s, int naug, int products) {
+  cycle_start_kernel<<<nsys, 64, 0, s>>>(st, naug, products);
 }
 void gstate_step(GState* st, int nsys, int j, hipStream_t s) { step_kernel<<<nsys, 64, 0, s>>>(st, j); }
 void gstate_finish(GState* st, int nsys, hipStream_t s) { finish_kernel<<<nsys, 64, 0, s>>>(st); }

@@ -44,10 +44,11 @@ int cayley_apply(Iram& w, const double* v, double* out) {
   sa_gmres_info info{};
   int rc;
   const int pci = o.lin.use_precond ? 0 : -1;
+  // out is zero: the solves start from x0 = 0 without an operator product
   if (o.lin.prec == SA_MIXED)
-    rc = solve_ir(c, o.lin, o.sigma, w.tb, out, pci, &info);
+    rc = solve_ir(c, o.lin, o.sigma, w.tb, out, pci, &info, true);
   else
-    rc = solve_gmres<double>(c, o.lin, 1, &o.sigma, w.tb, out, pci, &info);
+    rc = solve_gmres<double>(c, o.lin, 1, &o.sigma, w.tb, out, pci, &info, "g", false, true);
   if (rc < 0) return rc;
   w.res->n_cayley += 1;
   w.res->n_matvec += info.matvecs + 1;

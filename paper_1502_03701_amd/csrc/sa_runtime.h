@@ -118,9 +118,12 @@ void scratch_init(int device);
 
 template <typename R>
 int solve_gmres(Ctx* c, const sa_gmres_opts& o, int nsys, const double* sigma_host, const R* b, R* x, int pc_shift0,
-                sa_gmres_info* info, const std::string& tag = "g", bool io_stable = false);
+                sa_gmres_info* info, const std::string& tag = "g", bool io_stable = false,
+                bool x0_zero = false);
+// x0_zero (here and in solve_gmres): x holds zeros on entry, so the first
+// residual is b (no operator product, none counted)
 int solve_ir(Ctx* c, const sa_gmres_opts& o, double sigma, const double* b, double* x, int pc_shift,
-             sa_gmres_info* info);
+             sa_gmres_info* info, bool x0_zero = false);
 
 // mean-flow preconditioner (fourier_pc.hip): setup, and z = M^{-1} r for
 // nrhs systems (at most the setup's shift count)

@@ -72,7 +72,7 @@ constexpr size_t MAX_GRAPHS = 16;
 
 template <typename R>
 int solve_gmres(Ctx* c, const sa_gmres_opts& o, int nsys, const double* sigma, const R* b, R* x, int pc_shift0,
-                sa_gmres_info* info, const std::string& tag, bool io_stable) {
+                sa_gmres_info* info, const std::string& tag, bool io_stable, bool x0_zero) {
   hipStream_t s = c->stream;
   const long long n = c->n;
   const int m = o.restart;
@@ -129,13 +129,17 @@ int solve_gmres(Ctx* c, const sa_gmres_opts& o, int nsys, const double* sigma, c
   const int* upd = &st->t.have_update;
   // r = b - (J - sigma I) x -> V_s[:,0]; with LGMRES the image of the last
   // correction, A dx = r_prev - r; beta, convergence and budget tests
-  auto start_cycle = [&](hipStream_t q, int naug) -> hipError_t {
-    hipError_t r =
-        launch_jv_batch<R>(c->op, base, bdata, X, T, nsys, n, n, sigma, sig, nullptr, 0, q, c->variant_of<R>());
-    if (r != hipSuccess) return r;
-    bl.residual(n, B, T, V, &st->t.rnorm2, nullptr, q, bb, n, n);
+  // zero_x: x is known to be zero (the first cycle of an x0_zero solve): the
+  // residual is b, no operator product
+  auto start_cycle = [&](hipStream_t q, int naug, bool zero_x = false) -> hipError_t {
+    if (!zero_x) {
+      hipError_t r =
+          launch_jv_batch<R>(c->op, base, bdata, X, T, nsys, n, n, sigma, sig, nullptr, 0, q, c->variant_of<R>());
+      if (r != hipSuccess) return r;
+    }
+    bl.residual(n, B, zero_x ? nullptr : T, V, &st->t.rnorm2, nullptr, q, bb, n, n);
     if (k) bl.lincomb(n, nsys, RPREV, n, 1.0, V, sv, -1.0, AUGA, sa, upd, GS_INTS, q);
-    gstate_cycle_start(st, nsys, q, naug);
+    gstate_cycle_start(st, nsys, q, naug, zero_x ? 0 : 1);
     return hipGetLastError();
   };
   // one Arnoldi step on direction zj (null: the step's w is already in place)
@@ -257,7 +261,7 @@ int solve_gmres(Ctx* c, const sa_gmres_opts& o, int nsys, const double* sigma, c
   gstate_init(st, nsys, o.tol, m, o.max_matvec, s);
   bl.nrm2sq(n, B, &st->t.bnorm2, nullptr, s, bn);
   gstate_set_bnorm(st, nsys, s);
-  e = start_cycle(s, 0);
+  e = start_cycle(s, 0, x0_zero);
   if (e != hipSuccess) return c->hip_fail(e, "gmres residual");
   std::vector<GTail> h;
   int cycles = 0;
@@ -303,9 +307,9 @@ int solve_gmres(Ctx* c, const sa_gmres_opts& o, int nsys, const double* sigma, c
 }
 
 template int solve_gmres<double>(Ctx*, const sa_gmres_opts&, int, const double*, const double*, double*, int,
-                                 sa_gmres_info*, const std::string&, bool);
+                                 sa_gmres_info*, const std::string&, bool, bool);
 template int solve_gmres<float>(Ctx*, const sa_gmres_opts&, int, const double*, const float*, float*, int,
-                                sa_gmres_info*, const std::string&, bool);
+                                sa_gmres_info*, const std::string&, bool, bool);
 
 size_t gmres_workspace_bytes(const Ctx* c, const sa_gmres_opts& o, int nshift) {
   auto r = [](size_t b) -> size_t { return (b + 255) / 256 * 256; };
@@ -334,7 +338,7 @@ size_t gmres_workspace_bytes(const Ctx* c, const sa_gmres_opts& o, int nshift) {
 // residual equation r/||r||, solved to inner_tol relative, or only as far as
 // the outer tolerance still requires (so the last sweep does not overshoot).
 int solve_ir(Ctx* c, const sa_gmres_opts& o, double sigma, const double* b, double* x, int pc_shift,
-             sa_gmres_info* info) {
+             sa_gmres_info* info, bool x0_zero) {
   hipStream_t s = c->stream;
   const long long n = c->n;
   double* r = (double*)c->buffer("ir_r", sizeof(double) * n);
@@ -363,10 +367,13 @@ int solve_ir(Ctx* c, const sa_gmres_opts& o, double sigma, const double* b, doub
   hipError_t e;
   std::vector<GTail> h;
   for (int outer = 0;; ++outer) {
-    e = c->jv<double>(x, y, 1, sigma, nullptr);
-    if (e != hipSuccess) return c->hip_fail(e, "ir residual");
-    bl.residual(n, b, y, r, &st->t.rnorm2, nullptr, s);
-    gstate_cycle_start(st, 1, s);  // beta = ||r||, inv = 1/||r||, converged flag
+    const bool zero_x = x0_zero && outer == 0;   // r = b, no product
+    if (!zero_x) {
+      e = c->jv<double>(x, y, 1, sigma, nullptr);
+      if (e != hipSuccess) return c->hip_fail(e, "ir residual");
+    }
+    bl.residual(n, b, zero_x ? nullptr : y, r, &st->t.rnorm2, nullptr, s);
+    gstate_cycle_start(st, 1, s, 0, zero_x ? 0 : 1);  // beta = ||r||, inv = 1/||r||, converged flag
     e = read_tails(st, 1, h, s);
     if (e != hipSuccess) return c->hip_fail(e, "ir status");
     info->outer = outer;
@@ -395,7 +402,7 @@ int solve_ir(Ctx* c, const sa_gmres_opts& o, double sigma, const double* b, doub
     // the last sweeps need only close the remaining gap: ask the inner solve
     // for max(inner_tol, tol ||b|| / (2 ||r||)), never looser than 1/2
     in.tol = std::min(0.5, std::max(o.inner_tol, 0.5 * o.tol / h[0].relres));
-    int rc = solve_gmres<float>(c, in, 1, &sigma, r32, d32, pc_shift, &ii, "ir32", true);
+    int rc = solve_gmres<float>(c, in, 1, &sigma, r32, d32, pc_shift, &ii, "ir32", true, true);
     if (rc < 0) return rc;
     inner_mv += ii.matvecs;
     inner_it += ii.iters;
