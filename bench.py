@@ -495,8 +495,9 @@ def eigs_c2(torch, dev, log=None, max_restarts=60, restart=(4, 4)):
     factored per Fourier mode): with it a solve needs a few Krylov steps, and
     the steps of a captured cycle past convergence are launches that return
     at once, so a short cycle is the faster one for both forms (FP64 12.31 s
-    and mixed 9.32 s at GMRES(4), 12.43 s and 9.68 s at GMRES(10), before
-    the refinement loop ran its inner cycles on its own buffers).  FP64 form:
+    and mixed 9.32 s at GMRES(4), 12.43 s and 9.68 s at GMRES(10), measured
+    before the refinement loop ran its inner cycles on its own buffers and
+    solves from x0 = 0 skipped their first product).  FP64 form:
     FP64 GMRES, operator and factors, solves to 1e-12.  Mixed form: FP32
     GMRES, operator and factors for solves to 1e-4, inside FP64 refinement to
     1e-12.  The timed region covers the preconditioner setup, the IRAM solve,
